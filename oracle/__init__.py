@@ -1,0 +1,219 @@
+"""FP64 CPU oracle of the Feldman-Cousins grid scan (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg import this package.  The GPU library never does, and the two share no
+code: they meet only through the seeded generator in ``fcgen``.
+
+The arithmetic lives in ``fc_oracle.c`` (plain C, FP64, no FP contraction);
+this module only marshals numpy arrays through ctypes and walks very large
+grids in consecutive q ranges (the running minimum carries over exactly).
+
+Functions follow arXiv:2002.07858:
+  covariance / cholesky  -- the SPD covariance whose inverse is M in Eq. (1)
+  chi2                   -- Eq. (1) / Algorithm 2, as ||L^{-1}(a-b)||^2
+  scan                   -- Algorithm 1 (strict-< running minimum, Delta chi^2)
+  critical_value         -- Section 1 / Figure 1 (quantiles of Delta chi^2)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+STAT_PEARSON = 0
+STAT_FIXED = 1
+
+CFLAGS = ["-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+          "-pthread"]
+
+
+def build(force: bool = True) -> str:
+    """Compile fc_oracle.c into liboracle.so next to it (gcc)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_p = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        L.fco_grid_coords.argtypes = [_i32, _p, _p, _i64, _p]
+        L.fco_covariance.argtypes = [_i32, _p, _p, _i32, _p, _p]
+        L.fco_cholesky.argtypes = [_i32, _p, _p]
+        L.fco_chi2.argtypes = [_i32, _p, _p, _p]
+        L.fco_chi2.restype = _dbl
+        L.fco_factor_range.argtypes = [_i64, _i32, _p, _p, _i32, _p, _i64, _i64, _p, _p, _i32]
+        L.fco_scan.argtypes = [_i64, _i32, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _i32]
+        L.fco_scan_init.argtypes = [_i64, _p, _p, _p, _p, _p]
+        L.fco_scan_range.argtypes = [_i64, _i32, _p, _i64, _i64, _p, _i64, _p, _p, _p, _p,
+                                     _p, _p, _i32]
+        L.fco_scan_finish.argtypes = [_i64, _p, _p, _p]
+        L.fco_chi2_table.argtypes = [_i64, _i32, _p, _p, _i64, _p, _p, _i32]
+        L.fco_critical_value.argtypes = [_i64, _p, _p, _i32, _p, _p, _i32, _dbl, _p]
+        for name in ("fco_grid_coords", "fco_covariance", "fco_cholesky", "fco_factor_range",
+                     "fco_scan", "fco_scan_init", "fco_scan_range", "fco_scan_finish",
+                     "fco_chi2_table", "fco_critical_value"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def default_threads() -> int:
+    env = os.environ.get("OMP_NUM_THREADS")
+    n = int(env) if env and env.isdigit() else (os.cpu_count() or 1)
+    return max(1, min(n, 64))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i64a(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def grid_coords(axes, q: int) -> np.ndarray:
+    """Coordinates of linear grid index q (row-major, last axis fastest)."""
+    lens = _i64a([len(a) for a in axes])
+    vals = _f64(np.concatenate([np.asarray(a, dtype=np.float64) for a in axes]))
+    out = np.zeros(len(axes))
+    if lib().fco_grid_coords(len(axes), _ptr(lens), _ptr(vals), int(q), _ptr(out)) != 0:
+        raise OracleError("bad grid index")
+    return out
+
+
+def covariance(s, F, stat_mode=STAT_PEARSON, stat_diag=None) -> np.ndarray:
+    s = _f64(s)
+    F = _f64(F)
+    N = s.shape[0]
+    sd = None if stat_diag is None else _f64(stat_diag)
+    out = np.zeros((N, N))
+    if lib().fco_covariance(N, _ptr(s), _ptr(F), int(stat_mode), _ptr(sd), _ptr(out)) != 0:
+        raise OracleError("bad covariance arguments")
+    return out
+
+
+def cholesky(A) -> np.ndarray:
+    A = _f64(A)
+    N = A.shape[0]
+    L = np.zeros((N, N))
+    if lib().fco_cholesky(N, _ptr(A), _ptr(L)) != 0:
+        raise OracleError("matrix is not positive definite")
+    return L
+
+
+def chi2(L, a, b) -> float:
+    L = _f64(L)
+    a = _f64(a)
+    b = _f64(b)
+    return float(lib().fco_chi2(L.shape[0], _ptr(L), _ptr(a), _ptr(b)))
+
+
+def factor_range(S, F, stat_mode=STAT_PEARSON, stat_diag=None, q0=0, nq=None, nthreads=None):
+    """Cholesky factors of Sigma_q for q in [q0, q0+nq): [nq][N][N]."""
+    S = _f64(S)
+    F = _f64(F)
+    G, N = S.shape
+    nq = G - q0 if nq is None else nq
+    sd = None if stat_diag is None else _f64(stat_diag)
+    L = np.empty((nq, N, N))
+    bad = np.zeros(1, dtype=np.int64)
+    rc = lib().fco_factor_range(G, N, _ptr(S), _ptr(F), int(stat_mode), _ptr(sd), int(q0),
+                                int(nq), _ptr(L), _ptr(bad), nthreads or default_threads())
+    if rc == -2:
+        raise OracleError("covariance not positive definite at q=%d" % int(bad[0]))
+    if rc != 0:
+        raise OracleError("bad factor arguments")
+    return L
+
+
+def scan(S, F, d, p_idx, stat_mode=STAT_PEARSON, stat_diag=None, nthreads=None,
+         block_bytes=1 << 30):
+    """Algorithm 1 over every universe: returns a dict of per-universe arrays.
+
+    Keys: dchi2, chi2_min, argmin, chi2_p, chi2_2nd.  The grid is walked in
+    consecutive ranges of q so that at most ``block_bytes`` of factors exist at
+    a time; the running minimum carries across ranges unchanged.
+    """
+    S = _f64(S)
+    F = _f64(F)
+    d = _f64(d)
+    p_idx = _i64a(p_idx)
+    G, N = S.shape
+    K = d.shape[0]
+    nt = nthreads or default_threads()
+    out = dict(dchi2=np.empty(K), chi2_min=np.empty(K), argmin=np.empty(K, dtype=np.int64),
+               chi2_p=np.empty(K), chi2_2nd=np.empty(K))
+    L_ = lib()
+    if L_.fco_scan_init(K, _ptr(p_idx), _ptr(out["chi2_min"]), _ptr(out["argmin"]),
+                        _ptr(out["chi2_p"]), _ptr(out["chi2_2nd"])) != 0:
+        raise OracleError("bad scan arguments")
+    if K and (p_idx.min() < 0 or p_idx.max() >= G):
+        raise OracleError("true point out of range")
+    step = max(1, int(block_bytes // (8 * N * N)))
+    for q0 in range(0, G, step):
+        nq = min(step, G - q0)
+        Lb = factor_range(S, F, stat_mode, stat_diag, q0, nq, nt)
+        rc = L_.fco_scan_range(G, N, _ptr(S), q0, nq, _ptr(Lb), K, _ptr(d), _ptr(p_idx),
+                               _ptr(out["chi2_min"]), _ptr(out["argmin"]), _ptr(out["chi2_p"]),
+                               _ptr(out["chi2_2nd"]), nt)
+        if rc != 0:
+            raise OracleError("bad scan arguments")
+    L_.fco_scan_finish(K, _ptr(out["chi2_p"]), _ptr(out["chi2_min"]), _ptr(out["dchi2"]))
+    return out
+
+
+def chi2_table(S, F, d, stat_mode=STAT_PEARSON, stat_diag=None, nthreads=None) -> np.ndarray:
+    """chi^2 of every universe against every grid point: [K][G]."""
+    S = _f64(S)
+    d = _f64(d)
+    G, N = S.shape
+    K = d.shape[0]
+    nt = nthreads or default_threads()
+    Lall = factor_range(S, F, stat_mode, stat_diag, 0, G, nt)
+    out = np.empty((K, G))
+    if lib().fco_chi2_table(G, N, _ptr(S), _ptr(Lall), K, _ptr(d), _ptr(out), nt) != 0:
+        raise OracleError("bad table arguments")
+    return out
+
+
+def critical_value(x, seg_off, alpha, n_bins=200, hist_hi=50.0, with_hist=True):
+    """Per-segment type-1 quantiles crit[n_seg][n_alpha] and histograms [n_seg][n_bins+1]."""
+    x = _f64(x)
+    seg_off = _i64a(seg_off)
+    alpha = _f64(np.atleast_1d(alpha))
+    n_seg = seg_off.shape[0] - 1
+    crit = np.empty((n_seg, alpha.shape[0]))
+    hist = np.empty((n_seg, n_bins + 1), dtype=np.int64) if with_hist else None
+    rc = lib().fco_critical_value(n_seg, _ptr(seg_off), _ptr(x), alpha.shape[0], _ptr(alpha),
+                                  _ptr(crit), int(n_bins), float(hist_hi), _ptr(hist))
+    if rc != 0:
+        raise OracleError("bad critical-value arguments")
+    return crit, hist

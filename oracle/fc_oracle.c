@@ -1,0 +1,347 @@
+/*
+ * fc_oracle.c -- plain FP64 CPU oracle of the Feldman-Cousins grid scan.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the GPU library, with which it
+ * shares no code.  See fc_oracle.h for what each function computes and which
+ * part of arXiv:2002.07858 it follows.
+ *
+ * The code is deliberately plain: textbook Cholesky, forward substitution,
+ * loops in the order the paper states them.  Threads only split the
+ * independent universes (Algorithm 1's outer loop) or grid points (the
+ * covariance factors) into static contiguous ranges.
+ */
+#include "fc_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- Section 2: grid linearisation (last axis fastest) ------------------ */
+int fco_grid_coords(int32_t D, const int64_t *axis_len, const double *axis_vals,
+                    int64_t q, double *coords)
+{
+    if (D <= 0 || !axis_len || !axis_vals || !coords || q < 0) return -1;
+    int64_t G = 1;
+    for (int32_t e = 0; e < D; ++e) {
+        if (axis_len[e] <= 0) return -1;
+        G *= axis_len[e];
+    }
+    if (q >= G) return -1;
+    /* q = sum_d i_d * prod_{e>d} n_e : peel indices from the last axis. */
+    int64_t off[64];
+    if (D > 64) return -1;
+    int64_t o = 0;
+    for (int32_t e = 0; e < D; ++e) { off[e] = o; o += axis_len[e]; }
+    int64_t rest = q;
+    for (int32_t e = D - 1; e >= 0; --e) {
+        int64_t i = rest % axis_len[e];
+        rest /= axis_len[e];
+        coords[e] = axis_vals[off[e] + i];
+    }
+    return 0;
+}
+
+/* ---- covariance: statistical diagonal + fractional systematic ------------ */
+int fco_covariance(int32_t N, const double *s, const double *F, int32_t stat_mode,
+                   const double *stat_diag, double *Sigma)
+{
+    if (N <= 0 || !s || !F || !Sigma) return -1;
+    if (stat_mode == FCO_STAT_FIXED && !stat_diag) return -1;
+    if (stat_mode != FCO_STAT_PEARSON && stat_mode != FCO_STAT_FIXED) return -1;
+    for (int32_t i = 0; i < N; ++i) {
+        for (int32_t j = 0; j < N; ++j) {
+            double v = F[(int64_t)i * N + j] * (s[i] * s[j]);
+            if (i == j) v += (stat_mode == FCO_STAT_PEARSON) ? s[i] : stat_diag[i];
+            Sigma[(int64_t)i * N + j] = v;
+        }
+    }
+    return 0;
+}
+
+/* ---- textbook Cholesky-Banachiewicz, row by row ------------------------- */
+int fco_cholesky(int32_t N, const double *A, double *L)
+{
+    for (int64_t t = 0; t < (int64_t)N * N; ++t) L[t] = 0.0;
+    for (int32_t i = 0; i < N; ++i) {
+        for (int32_t j = 0; j <= i; ++j) {
+            double sum = A[(int64_t)i * N + j];
+            for (int32_t k = 0; k < j; ++k)
+                sum -= L[(int64_t)i * N + k] * L[(int64_t)j * N + k];
+            if (i == j) {
+                if (!(sum > 0.0)) return -1; /* not positive definite (or NaN) */
+                L[(int64_t)i * N + i] = sqrt(sum);
+            } else {
+                L[(int64_t)i * N + j] = sum / L[(int64_t)j * N + j];
+            }
+        }
+    }
+    return 0;
+}
+
+/* ---- Eq. (1): chi^2 = r^T Sigma^{-1} r = ||y||^2 with L y = r ------------- */
+double fco_chi2(int32_t N, const double *L, const double *a, const double *b)
+{
+    double y[256];
+    double chi2 = 0.0;
+    for (int32_t i = 0; i < N; ++i) {
+        double v = a[i] - b[i];
+        for (int32_t k = 0; k < i; ++k) v -= L[(int64_t)i * N + k] * y[k];
+        y[i] = v / L[(int64_t)i * N + i];
+        chi2 += y[i] * y[i];
+    }
+    return chi2;
+}
+
+/* ---- static thread ranges -------------------------------------------------- */
+typedef void (*fco_task_fn)(void *ctx, int64_t lo, int64_t hi);
+
+struct fco_task {
+    fco_task_fn fn;
+    void *ctx;
+    int64_t lo, hi;
+};
+
+static void *fco_task_run(void *arg)
+{
+    struct fco_task *t = (struct fco_task *)arg;
+    t->fn(t->ctx, t->lo, t->hi);
+    return NULL;
+}
+
+static void fco_parallel(int64_t n, int32_t nthreads, fco_task_fn fn, void *ctx)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if ((int64_t)nthreads > n) nthreads = (int32_t)(n > 0 ? n : 1);
+    if (nthreads == 1) { fn(ctx, 0, n); return; }
+    pthread_t th[256];
+    struct fco_task task[256];
+    int started[256];
+    for (int32_t t = 0; t < nthreads; ++t) {
+        task[t].fn = fn;
+        task[t].ctx = ctx;
+        task[t].lo = n * t / nthreads;
+        task[t].hi = n * (t + 1) / nthreads;
+        started[t] = pthread_create(&th[t], NULL, fco_task_run, &task[t]) == 0;
+        if (!started[t]) fn(ctx, task[t].lo, task[t].hi);
+    }
+    for (int32_t t = 0; t < nthreads; ++t)
+        if (started[t]) pthread_join(th[t], NULL);
+}
+
+/* ---- factors of every Sigma_q in a range --------------------------------- */
+struct fco_factor_ctx {
+    int32_t N;
+    const double *S, *F, *stat_diag;
+    int32_t stat_mode;
+    int64_t q0;
+    double *L_blk;
+    int64_t *first_bad; /* per thread-range result, merged afterwards */
+    pthread_mutex_t mu;
+};
+
+static void fco_factor_task(void *vctx, int64_t lo, int64_t hi)
+{
+    struct fco_factor_ctx *c = (struct fco_factor_ctx *)vctx;
+    int32_t N = c->N;
+    double *Sigma = (double *)malloc(sizeof(double) * (size_t)N * (size_t)N);
+    if (!Sigma) return;
+    for (int64_t t = lo; t < hi; ++t) {
+        int64_t q = c->q0 + t;
+        fco_covariance(N, c->S + q * N, c->F, c->stat_mode, c->stat_diag, Sigma);
+        if (fco_cholesky(N, Sigma, c->L_blk + t * (int64_t)N * N) != 0) {
+            pthread_mutex_lock(&c->mu);
+            if (*c->first_bad < 0 || q < *c->first_bad) *c->first_bad = q;
+            pthread_mutex_unlock(&c->mu);
+        }
+    }
+    free(Sigma);
+}
+
+int fco_factor_range(int64_t G, int32_t N, const double *S, const double *F,
+                     int32_t stat_mode, const double *stat_diag, int64_t q0, int64_t nq,
+                     double *L_blk, int64_t *bad_q, int32_t nthreads)
+{
+    if (G <= 0 || N <= 0 || N > 256 || !S || !F || !L_blk || !bad_q) return -1;
+    if (q0 < 0 || nq < 0 || q0 + nq > G) return -1;
+    if (stat_mode == FCO_STAT_FIXED && !stat_diag) return -1;
+    struct fco_factor_ctx c;
+    c.N = N; c.S = S; c.F = F; c.stat_diag = stat_diag; c.stat_mode = stat_mode;
+    c.q0 = q0; c.L_blk = L_blk;
+    int64_t first_bad = -1;
+    c.first_bad = &first_bad;
+    pthread_mutex_init(&c.mu, NULL);
+    fco_parallel(nq, nthreads, fco_factor_task, &c);
+    pthread_mutex_destroy(&c.mu);
+    *bad_q = first_bad;
+    return first_bad >= 0 ? -2 : 0;
+}
+
+/* ---- Algorithm 1 ---------------------------------------------------------- */
+int fco_scan_init(int64_t K, const int64_t *p_idx, double *chi2_min, int64_t *argmin,
+                  double *chi2_p, double *chi2_2nd)
+{
+    if (K < 0 || (K > 0 && (!p_idx || !chi2_min || !argmin || !chi2_p || !chi2_2nd))) return -1;
+    for (int64_t k = 0; k < K; ++k) {
+        chi2_min[k] = INFINITY; /* chi^2_min <- inf */
+        argmin[k] = p_idx[k];   /* p_min = p        */
+        chi2_p[k] = NAN;
+        chi2_2nd[k] = INFINITY;
+    }
+    return 0;
+}
+
+struct fco_scan_ctx {
+    int32_t N;
+    const double *S, *L_blk, *d;
+    const int64_t *p_idx;
+    int64_t q0, nq;
+    double *chi2_min, *chi2_p, *chi2_2nd;
+    int64_t *argmin;
+};
+
+static void fco_scan_task(void *vctx, int64_t lo, int64_t hi)
+{
+    struct fco_scan_ctx *c = (struct fco_scan_ctx *)vctx;
+    int32_t N = c->N;
+    for (int64_t k = lo; k < hi; ++k) {           /* each universe ...        */
+        const double *a = c->d + k * N;
+        double best = c->chi2_min[k];
+        double second = c->chi2_2nd[k];
+        int64_t qbest = c->argmin[k];
+        for (int64_t t = 0; t < c->nq; ++t) {     /* ... against every q, in order */
+            int64_t q = c->q0 + t;
+            double chi2 = fco_chi2(N, c->L_blk + t * (int64_t)N * N, a, c->S + q * N);
+            if (q == c->p_idx[k]) c->chi2_p[k] = chi2;
+            if (chi2 < best) {                    /* strict "<": first q wins ties */
+                second = best;
+                best = chi2;
+                qbest = q;
+            } else if (chi2 < second) {
+                second = chi2;
+            }
+        }
+        c->chi2_min[k] = best;
+        c->chi2_2nd[k] = second;
+        c->argmin[k] = qbest;
+    }
+}
+
+int fco_scan_range(int64_t G, int32_t N, const double *S, int64_t q0, int64_t nq,
+                   const double *L_blk, int64_t K, const double *d, const int64_t *p_idx,
+                   double *chi2_min, int64_t *argmin, double *chi2_p, double *chi2_2nd,
+                   int32_t nthreads)
+{
+    if (G <= 0 || N <= 0 || N > 256 || !S || q0 < 0 || nq < 0 || q0 + nq > G) return -1;
+    if (K < 0 || (K > 0 && (!d || !p_idx || !chi2_min || !argmin || !chi2_p || !chi2_2nd)))
+        return -1;
+    if (nq > 0 && !L_blk) return -1;
+    for (int64_t k = 0; k < K; ++k)
+        if (p_idx[k] < 0 || p_idx[k] >= G) return -1;
+    struct fco_scan_ctx c;
+    c.N = N; c.S = S; c.L_blk = L_blk; c.d = d; c.p_idx = p_idx;
+    c.q0 = q0; c.nq = nq;
+    c.chi2_min = chi2_min; c.chi2_p = chi2_p; c.chi2_2nd = chi2_2nd; c.argmin = argmin;
+    fco_parallel(K, nthreads, fco_scan_task, &c);
+    return 0;
+}
+
+int fco_scan_finish(int64_t K, const double *chi2_p, const double *chi2_min, double *dchi2)
+{
+    if (K < 0 || (K > 0 && (!chi2_p || !chi2_min || !dchi2))) return -1;
+    for (int64_t k = 0; k < K; ++k) dchi2[k] = chi2_p[k] - chi2_min[k];
+    return 0;
+}
+
+int fco_scan(int64_t G, int32_t N, const double *S, const double *L_all, int64_t K,
+             const double *d, const int64_t *p_idx, double *dchi2, double *chi2_min,
+             int64_t *argmin, double *chi2_p, double *chi2_2nd, int32_t nthreads)
+{
+    int rc = fco_scan_init(K, p_idx, chi2_min, argmin, chi2_p, chi2_2nd);
+    if (rc) return rc;
+    rc = fco_scan_range(G, N, S, 0, G, L_all, K, d, p_idx, chi2_min, argmin, chi2_p,
+                        chi2_2nd, nthreads);
+    if (rc) return rc;
+    return fco_scan_finish(K, chi2_p, chi2_min, dchi2);
+}
+
+/* ---- chi^2 of every (universe, grid point) pair ---------------------------- */
+struct fco_table_ctx {
+    int64_t G;
+    int32_t N;
+    const double *S, *L_all, *d;
+    double *out;
+};
+
+static void fco_table_task(void *vctx, int64_t lo, int64_t hi)
+{
+    struct fco_table_ctx *c = (struct fco_table_ctx *)vctx;
+    for (int64_t k = lo; k < hi; ++k)
+        for (int64_t q = 0; q < c->G; ++q)
+            c->out[k * c->G + q] = fco_chi2(c->N, c->L_all + q * (int64_t)c->N * c->N,
+                                            c->d + k * c->N, c->S + q * c->N);
+}
+
+int fco_chi2_table(int64_t G, int32_t N, const double *S, const double *L_all, int64_t K,
+                   const double *d, double *out, int32_t nthreads)
+{
+    if (G <= 0 || N <= 0 || N > 256 || !S || !L_all || K < 0 || (K > 0 && (!d || !out)))
+        return -1;
+    struct fco_table_ctx c = {G, N, S, L_all, d, out};
+    fco_parallel(K, nthreads, fco_table_task, &c);
+    return 0;
+}
+
+/* ---- critical values (type-1 order statistic) and histogram -------------- */
+static int fco_cmp_nan_last(const void *pa, const void *pb)
+{
+    double a = *(const double *)pa, b = *(const double *)pb;
+    int an = isnan(a), bn = isnan(b);
+    if (an || bn) return an - bn;
+    return (a > b) - (a < b);
+}
+
+int fco_critical_value(int64_t n_seg, const int64_t *seg_off, const double *x,
+                       int32_t n_alpha, const double *alpha, double *crit,
+                       int32_t n_bins, double hist_hi, int64_t *hist)
+{
+    if (n_seg < 0 || !seg_off || n_alpha < 0 || (n_alpha > 0 && (!alpha || !crit))) return -1;
+    if (hist && (n_bins <= 0 || !(hist_hi > 0.0))) return -1;
+    for (int32_t a = 0; a < n_alpha; ++a)
+        if (!(alpha[a] > 0.0 && alpha[a] <= 1.0)) return -1;
+    for (int64_t s = 0; s < n_seg; ++s) {
+        int64_t lo = seg_off[s], hi = seg_off[s + 1];
+        if (lo < 0 || hi < lo) return -1;
+        int64_t K = hi - lo;
+        double *v = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+        if (!v) return -3;
+        memcpy(v, x + lo, sizeof(double) * (size_t)K);
+        qsort(v, (size_t)K, sizeof(double), fco_cmp_nan_last);
+        for (int32_t a = 0; a < n_alpha; ++a) {
+            if (K == 0) { crit[s * n_alpha + a] = NAN; continue; }
+            double jr = ceil(alpha[a] * (double)K);
+            int64_t j = (int64_t)jr;
+            if (j < 1) j = 1;
+            if (j > K) j = K;
+            crit[s * n_alpha + a] = v[j - 1];
+        }
+        free(v);
+        if (hist) {
+            int64_t *h = hist + s * (int64_t)(n_bins + 1);
+            for (int32_t b = 0; b <= n_bins; ++b) h[b] = 0;
+            double width = hist_hi / (double)n_bins;
+            for (int64_t k = lo; k < hi; ++k) {
+                double xv = x[k];
+                int64_t b = n_bins;
+                if (xv >= 0.0 && xv < hist_hi) {
+                    b = (int64_t)floor(xv / width);
+                    if (b > n_bins - 1) b = n_bins - 1;
+                }
+                h[b] += 1;
+            }
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,101 @@
+/*
+ * fc_oracle.h -- plain FP64 CPU oracle of the Feldman-Cousins grid scan.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library; the two meet only through the
+ * seeded input generator.
+ *
+ * What it computes (arXiv:2002.07858):
+ *   - Eq. (1) / Algorithm 2: chi^2 = (a-b)^T M (a-b), with M the inverse of an
+ *     SPD covariance.  Evaluated here as ||L^{-1}(a-b)||^2 by forward
+ *     substitution with the Cholesky factor L of the covariance, so no
+ *     inverse is ever formed.
+ *   - Section 2 (grid): the D-dimensional rectangular grid is linearised into
+ *     a list, row-major with the last axis fastest.
+ *   - Algorithm 1: per universe, strict "<" running minimum over the grid in
+ *     list order, initialised to +inf with the minimiser set to the true
+ *     point; Delta chi^2 = chi^2 at the true point minus the minimum.
+ *   - Section 1 / Figure 1: critical values are the values left of which a
+ *     stated fraction of the Delta chi^2 distribution lies (type-1 order
+ *     statistic), plus a fixed-bin histogram.
+ * The covariance at grid point q is Sigma_q = diag(stat) + F o (S_q S_q^T):
+ * Pearson statistical term stat = S_q (or a fixed stat vector) plus a
+ * fractional systematic matrix F scaled by the prediction.
+ *
+ * All arithmetic is IEEE FP64, compiled without FP contraction.
+ */
+#ifndef FC_ORACLE_H
+#define FC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FCO_STAT_PEARSON 0
+#define FCO_STAT_FIXED 1
+
+/* Coordinates of linear grid index q: coords[d] = axis_vals[off_d + i_d]. */
+int fco_grid_coords(int32_t D, const int64_t *axis_len, const double *axis_vals,
+                    int64_t q, double *coords);
+
+/* Sigma = diag(stat) + F o (s s^T), row-major [N][N]. */
+int fco_covariance(int32_t N, const double *s, const double *F, int32_t stat_mode,
+                   const double *stat_diag, double *Sigma);
+
+/* Lower Cholesky factor of A ([N][N] row-major) into L ([N][N], upper part
+ * zeroed).  Returns 0, or -1 if a pivot is not > 0 (not positive definite). */
+int fco_cholesky(int32_t N, const double *A, double *L);
+
+/* chi^2 = ||L^{-1}(a-b)||^2 by forward substitution, L full [N][N]. */
+double fco_chi2(int32_t N, const double *L, const double *a, const double *b);
+
+/* Cholesky factors of Sigma_q for q = q0 .. q0+nq-1, written as full
+ * [nq][N][N] (S is the whole [G][N] table).  On failure returns -2 and sets
+ * *bad_q to the first q that is not PD, else *bad_q = -1. */
+int fco_factor_range(int64_t G, int32_t N, const double *S, const double *F,
+                     int32_t stat_mode, const double *stat_diag, int64_t q0, int64_t nq,
+                     double *L_blk, int64_t *bad_q, int32_t nthreads);
+
+/* Algorithm 1 for K universes d[K][N] with true points p_idx[K].
+ * Outputs per universe: dchi2, chi2_min, argmin, chi2_p (chi^2 at the true
+ * point) and chi2_2nd (smallest chi^2 at a grid point other than argmin,
+ * +inf if G == 1).  Returns -1 on a bad argument. */
+int fco_scan(int64_t G, int32_t N, const double *S, const double *L_all, int64_t K,
+             const double *d, const int64_t *p_idx, double *dchi2, double *chi2_min,
+             int64_t *argmin, double *chi2_p, double *chi2_2nd, int32_t nthreads);
+
+/* The same scan split in three so that very large grids can be walked in
+ * consecutive ranges of q without holding every factor at once:
+ *   init   : chi2_min = +inf, argmin = p, chi2_p = NaN, chi2_2nd = +inf
+ *   range  : continue every universe's running minimum over q0 .. q0+nq-1 in
+ *            order, with L_blk holding the factors of those nq points
+ *   finish : dchi2 = chi2_p - chi2_min
+ * Calling range over 0..G-1 in increasing, contiguous pieces gives exactly the
+ * result of one pass over the whole grid. */
+int fco_scan_init(int64_t K, const int64_t *p_idx, double *chi2_min, int64_t *argmin,
+                  double *chi2_p, double *chi2_2nd);
+int fco_scan_range(int64_t G, int32_t N, const double *S, int64_t q0, int64_t nq,
+                   const double *L_blk, int64_t K, const double *d, const int64_t *p_idx,
+                   double *chi2_min, int64_t *argmin, double *chi2_p, double *chi2_2nd,
+                   int32_t nthreads);
+int fco_scan_finish(int64_t K, const double *chi2_p, const double *chi2_min, double *dchi2);
+
+/* chi^2 of every universe against every grid point: out[K][G]. */
+int fco_chi2_table(int64_t G, int32_t N, const double *S, const double *L_all, int64_t K,
+                   const double *d, double *out, int32_t nthreads);
+
+/* Per segment s (values x[seg_off[s] .. seg_off[s+1])): crit[s][a] is the
+ * j-th smallest value, j = ceil(alpha[a] * K_s) clamped to [1, K_s] (NaN sorts
+ * last; NaN for an empty segment); hist[s][b], b < n_bins, counts values with
+ * 0 <= x < hist_hi in bin floor(x / (hist_hi / n_bins)) (clamped to n_bins-1);
+ * hist[s][n_bins] counts everything else, NaN included.  hist may be NULL. */
+int fco_critical_value(int64_t n_seg, const int64_t *seg_off, const double *x,
+                       int32_t n_alpha, const double *alpha, double *crit,
+                       int32_t n_bins, double hist_hi, int64_t *hist);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
