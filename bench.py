@@ -1,0 +1,175 @@
+"""Benchmark of the FC grid-scan hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--form fp32]
+
+Workload: D = 2 grid 100 x 100 (G = 10^4), N = 57 bins, 256 true points x
+2000 universes (512 000 universes, 5.12e9 universe x grid-point chi^2
+evaluations per step), FP32 scan, 0.6827 / 0.90 / 0.95 critical values and a
+200-bin histogram per true point.  Inputs are seeded synthetic data from the
+toy oscillation model, resident in HBM before the timed region.
+
+One step = covariance factors for every grid point (FP64 Cholesky + inverse,
+stored in the scan form) + the scan of all universes (minimum, argmin,
+Delta chi^2) + critical values.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("universe×gridpoint χ² evals/s at max|Δχ²| err vs FP64; "
+          "FC request p50/p99 latency")
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12}
+ALPHA = (0.6827, 0.9, 0.95)
+N_BINS, HIST_HI = 200, 50.0
+
+
+def flop_per_eval(N: int) -> int:
+    # factor form: N subtractions, triangular W r (N(N+1)/2 multiply-adds),
+    # N squares and N adds
+    return N * N + 4 * N
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pr, per_point: int, dev_out: dict):
+    """Time the FP64 oracle on a bounded sample and measure the device error on it."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import parity
+    idx = []
+    for s in range(len(pr.seg_off) - 1):
+        lo = int(pr.seg_off[s])
+        idx += list(range(lo, lo + per_point))
+    idx = np.array(idx)
+    nt = oracle.default_threads()
+    t0 = time.perf_counter()
+    ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx], nthreads=nt)
+    dt = time.perf_counter() - t0
+    evals = len(idx) * pr.G
+    rep = parity.report({k: v[idx] for k, v in dev_out.items()}, ref, 1e-6)
+    base = {"value": evals / dt, "unit": "evals/s", "cores": nt, "kind": "oracle",
+            "sample": f"first {per_point} universes of each of the {len(pr.seg_off) - 1} true "
+                      f"points x all {pr.G} grid points ({evals:.3g} evals, {dt:.1f} s, "
+                      f"FP64 Cholesky + forward substitution)"}
+    return base, rep
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--form", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--cpu-per-point", type=int, default=100,
+                    help="universes per true point in the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the scan is "
+              "single-GPU by design; see the multi-GPU section of the design notes.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import fcgen
+    import paper_2002_07858_amd as fc
+
+    torch.cuda.set_device(0)
+    fc.lib()
+    form = {"fp32": fc.FC_FORM_FP32, "fp64": fc.FC_FORM_FP64}[args.form]
+
+    log("[bench] generating c2 inputs")
+    pr = fcgen.make_problem("c2")
+    G, N, K = pr.G, pr.N, pr.K
+    dev = torch.device("cuda")
+    d_t = torch.as_tensor(pr.d).to(dev)
+    p_t = torch.as_tensor(pr.p_idx).to(dev)
+    so_t = torch.as_tensor(pr.seg_off).to(dev)
+    n_seg = len(pr.seg_off) - 1
+    outs = {k: torch.empty(K, dtype=torch.float64, device=dev) for k in ("dchi2", "chi2_min",
+                                                                        "chi2_p")}
+    outs["argmin"] = torch.empty(K, dtype=torch.int64, device=dev)
+    crit = torch.empty((n_seg, len(ALPHA)), dtype=torch.float64, device=dev)
+    hist = torch.empty((n_seg, N_BINS + 1), dtype=torch.int64, device=dev)
+    log("[bench] grid residency")
+    grid = fc.fc_build_grid(pr.axes, pr.S)
+    stream = torch.cuda.current_stream()
+
+    ev = {k: torch.cuda.Event(enable_timing=True) for k in ("c0", "c1", "s0", "s1", "k1")}
+
+    def step(times=None):
+        ev["c0"].record(stream)
+        fc.fc_build_covariance(grid, pr.F, pr.stat_mode, pr.stat_diag, forms=form)
+        ev["c1"].record(stream)
+        ev["s0"].record(stream)
+        fc.fc_scan(grid, form, d_t, p_t, outs["dchi2"], outs["chi2_min"], outs["argmin"],
+                   outs["chi2_p"])
+        ev["s1"].record(stream)
+        fc.fc_critical_value(so_t, outs["dchi2"], ALPHA, crit, N_BINS, HIST_HI, hist)
+        ev["k1"].record(stream)
+        if times is not None:
+            ev["k1"].synchronize()
+            times["cov"].append(ev["c0"].elapsed_time(ev["c1"]))
+            times["scan"].append(ev["s0"].elapsed_time(ev["s1"]))
+            times["crit"].append(ev["s1"].elapsed_time(ev["k1"]))
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times = {"cov": [], "scan": [], "crit": []}
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(times)
+        log(f"[bench] step {i}: scan {times['scan'][-1]:.2f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    evals = K * G
+    value = evals * args.steps / wall
+    scan_ms = float(np.mean(times["scan"]))
+    fpe = flop_per_eval(N)
+    achieved = evals * fpe / (scan_ms * 1e-3)
+    peak = PEAK[args.form]
+    roofline = {"bound": "mfma" if args.form == "fp32" else "alu", "achieved": achieved / 1e12,
+                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None}
+
+    dev_out = {k: v.cpu().numpy() for k, v in outs.items()}
+    res = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp32": "f32", "fp64": "f64"}[args.form], "data": "synthetic",
+           "config": {"workload": "c2: D=2 grid 100x100 (G=10000), N=57, 256 true points x "
+                                  "2000 universes, per-point FP64 covariance factor, "
+                                  f"{args.form} scan, crit at 0.6827/0.9/0.95 + 200-bin hist",
+                      "G": G, "N": N, "K_total": K, "evals_per_step": evals,
+                      "form": args.form, "parallelism": "single-gpu"},
+           "phases_ms": {k: float(np.mean(v)) for k, v in times.items()},
+           "scan_evals_per_s": evals / (scan_ms * 1e-3),
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        base, rep = cpu_baseline(pr, args.cpu_per_point, dev_out)
+        res["cpu_baseline"] = base
+        res["err_vs_fp64"] = rep
+    grid.destroy()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

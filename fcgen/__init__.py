@@ -80,6 +80,7 @@ def toy_model(config: int, bins_per_det=(19, 19, 19)) -> ToyModel:
     sigma = rng.uniform(0.05, 0.20, size=N)
     A = rng.standard_normal((N, 2 * N))
     W = A @ A.T
+    W = 0.5 * (W + W.T)          # exactly symmetric
     dw = np.sqrt(np.diag(W))
     C = W / np.outer(dw, dw)
     np.fill_diagonal(C, 1.0)

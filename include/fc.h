@@ -1,0 +1,203 @@
+/*
+ * fc.h -- C ABI of the MI355X (gfx950) Feldman-Cousins grid-scan library.
+ *
+ * The library evaluates, for every pseudo-experiment ("universe") d drawn
+ * around a true grid point p,
+ *
+ *     chi2(d, q) = (d - S(q))^T Sigma_q^{-1} (d - S(q))          (Eq. (1))
+ *
+ * at every point q of a D-dimensional grid, keeps the strict-"<" running
+ * minimum over the grid in list order (Algorithm 1), forms
+ *
+ *     Delta chi2 = chi2(d, p) - min_q chi2(d, q)
+ *
+ * and reduces the Delta chi2 values of each true point to critical values
+ * (Section 1, Figure 1: the value left of which a stated fraction of the
+ * distribution lies) and a histogram.  The per-point covariance is the
+ * statistical plus fractional-systematic form
+ *
+ *     Sigma_q = diag(stat_q) + F o (S(q) S(q)^T),  stat_q = S(q) (Pearson)
+ *                                                  or a fixed vector.
+ *
+ * Conventions for every function:
+ *   - Return value: FC_OK (0) or a negative fc_status.  fc_last_error()
+ *     returns a thread-local, library-owned, NUL-terminated message
+ *     describing the last failure on the calling thread.
+ *   - "host" pointers are read only during the call.  "device" pointers are
+ *     HIP device memory owned by the caller, read or written by work the call
+ *     enqueues on `stream` (NULL = the null stream); that work is
+ *     asynchronous unless stated otherwise.
+ *   - Argument errors that can be seen on the host are reported before any
+ *     device work is enqueued.  A device fault is reported as FC_ERR_DEVICE
+ *     by the call that observes it.
+ *   - A built grid is immutable: concurrent fc_scan calls on one grid from
+ *     different streams are safe; fc_grid_destroy must not race with them.
+ */
+#ifndef FC_H
+#define FC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fc_grid fc_grid; /* opaque, library-owned, device-resident */
+
+enum fc_status_code {
+    FC_OK = 0,
+    FC_ERR_INVALID_ARG = -1, /* bad size, pointer, index or enum value        */
+    FC_ERR_NOT_PD = -2,      /* a covariance is not positive definite         */
+    FC_ERR_NOMEM = -3,       /* device or host allocation failed              */
+    FC_ERR_DEVICE = -4,      /* a HIP call or kernel failed                   */
+    FC_ERR_STATE = -5,       /* e.g. scanning with a form that was not built  */
+    FC_ERR_UNSUPPORTED = -6  /* e.g. N > 64 bins                              */
+};
+
+/* Arithmetic forms of the scan (bit mask for fc_build_covariance). */
+enum fc_form {
+    FC_FORM_FP64 = 1,       /* FP64 factor, FP64 arithmetic                      */
+    FC_FORM_FP32 = 2,       /* FP32 factor, FP32 MFMA contraction               */
+    FC_FORM_SPLIT_BF16 = 4, /* hi+lo BF16 operands, FP32 MFMA accumulation      */
+    FC_FORM_SPLIT_FP16 = 8  /* hi+lo FP16 operands, FP32 MFMA accumulation      */
+};
+
+enum fc_stat_mode {
+    FC_STAT_PEARSON = 0, /* statistical term diag(S(q))                     */
+    FC_STAT_FIXED = 1    /* statistical term diag(stat_diag), same for all q */
+};
+
+#define FC_MAX_BINS 64
+
+/*
+ * fc_build_grid -- make a grid resident on the current HIP device.
+ *
+ * Section 2: the D-dimensional rectangular grid is linearised into a list of
+ * G = prod(axis_len) points, row-major with the LAST axis fastest:
+ *     q = sum_d i_d * prod_{e>d} axis_len[e].
+ * Section 1: every point carries a prediction S(q) of N bins; `central` is the
+ * observed data vector c (optional, kept for the caller).
+ *
+ *   out        host out: receives the new handle (set to NULL on failure)
+ *   D          1..16 axes
+ *   axis_len   host [D], each >= 1; G must be < 2^31
+ *   axis_vals  host [sum(axis_len)], the axes' values concatenated
+ *   N          1..FC_MAX_BINS bins (larger N: FC_ERR_UNSUPPORTED)
+ *   signal     host [G][N] FP64, row q = S(q); must be finite
+ *   central    host [N] FP64 or NULL
+ *   stream     stream for the uploads; the call synchronises it before returning
+ * Ownership: the handle and all device memory behind it belong to the
+ * library until fc_grid_destroy.
+ */
+int fc_build_grid(fc_grid **out, int32_t D, const int64_t *axis_len,
+                  const double *axis_vals, int32_t N, const double *signal,
+                  const double *central, hipStream_t stream);
+
+/*
+ * fc_build_covariance -- per-grid-point covariance, FP64 Cholesky and inverse
+ * factor on the GPU, stored in the requested scan forms.
+ *
+ * For every q: Sigma_q = diag(stat_q) + F o (S(q) S(q)^T) (the inverse of
+ * Sigma_q is the matrix M of Eq. (1)); L_q L_q^T = Sigma_q in FP64;
+ * W_q = L_q^{-1} in FP64, so that Sigma_q^{-1} = W_q^T W_q and
+ * chi2 = ||W_q (d - S(q))||^2.  W_q is stored in every form of `forms`.
+ *
+ *   g          grid from fc_build_grid (replaces any previously built forms)
+ *   frac_cov   host [N][N] FP64 symmetric fractional systematic matrix F
+ *   stat_mode  FC_STAT_PEARSON or FC_STAT_FIXED
+ *   stat_diag  host [N] FP64 (FC_STAT_FIXED only, else ignored / NULL)
+ *   forms      non-empty OR of fc_form values
+ *   bad_q      host out: first q whose Sigma_q is not positive definite, or -1
+ *   stream     the call synchronises this stream before returning
+ * Returns FC_ERR_NOT_PD (with *bad_q set, no forms kept) if some Sigma_q has a
+ * pivot <= 0 (or NaN) during the factorisation.
+ */
+int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
+                        const double *stat_diag, uint32_t forms, int64_t *bad_q,
+                        hipStream_t stream);
+
+/*
+ * fc_scan -- Algorithm 1 for K universes on the GPU (asynchronous).
+ *
+ * For universe k with data d[k] and true point p_idx[k]:
+ *   chi2_p[k]   = chi2(d[k], q = p_idx[k])            (Eq. (1) at the true point)
+ *   chi2_min[k] = min over all q of chi2(d[k], q); the scan runs over q in
+ *                 list order with a strict "<" starting from +inf, so among
+ *                 exact ties the lowest q wins
+ *   argmin[k]   = that q (p_idx[k] if no chi2 value is < +inf, e.g. NaN data)
+ *   dchi2[k]    = chi2_p[k] - chi2_min[k]   (>= 0; the true point is scanned)
+ * chi2 values are computed in the arithmetic of `form` (FP32 forms round each
+ * chi2 to FP32; chi2_p and chi2_min are then exact FP64 copies of FP32
+ * values, and dchi2 is their exact FP64 difference).
+ *
+ *   g        grid with `form` built (else FC_ERR_STATE)
+ *   form     one fc_form value
+ *   K        number of universes, 0 <= K <= 2^30 (K = 0 enqueues nothing)
+ *   d        device [K][N] FP64, row-major
+ *   p_idx    device [K] int64 true-point grid indices.  They are checked on
+ *            the device only: an index outside [0, G) gives that universe
+ *            chi2_p = NaN and dchi2 = NaN and touches no other memory.
+ *   dchi2, chi2_min, chi2_p   device [K] FP64 outputs
+ *   argmin   device [K] int64 output
+ * All four outputs are required; chi2_min's storage doubles as the scan's
+ * packed (chi2, q) minimum keys until the final pass rewrites it.
+ * Universes with NaN/inf data get chi2_min = +inf, argmin = p, dchi2 = NaN;
+ * other universes are unaffected.
+ */
+int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d,
+            const int64_t *p_idx, double *dchi2, double *chi2_min, int64_t *argmin,
+            double *chi2_p, hipStream_t stream);
+
+/*
+ * fc_critical_value -- per-true-point critical values and histogram of
+ * Delta chi2 (asynchronous).  Section 1 / Figure 1: the critical value for a
+ * fraction alpha is the value left of which that fraction of the
+ * distribution lies; it is taken as the type-1 order statistic
+ *     crit = x_(j),  j = ceil(alpha * K_s) (IEEE FP64 product) clamped to [1, K_s],
+ * of the K_s values of segment s sorted ascending with NaN last.
+ *
+ *   n_seg     number of segments (true points), >= 0
+ *   seg_off   device [n_seg+1] int64 offsets into dchi2; segment s is
+ *             dchi2[seg_off[s] .. seg_off[s+1]).  Checked on the device: a
+ *             segment with negative or decreasing offsets yields NaN
+ *             critical values and an all-zero histogram.
+ *   dchi2     device FP64 values
+ *   n_alpha   1..8 fractions, alpha host [n_alpha], each in (0, 1]
+ *   crit      device out [n_seg][n_alpha] FP64 (NaN for an empty segment)
+ *   n_bins    >= 1 (if hist != NULL)
+ *   hist_hi   > 0: bin b < n_bins counts values with 0 <= x < hist_hi and
+ *             floor(x / (hist_hi / n_bins)) = b (IEEE FP64, clamped to
+ *             n_bins - 1); bin n_bins counts every other value, NaN included
+ *   hist      device out [n_seg][n_bins+1] int64, or NULL for no histogram
+ */
+int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2,
+                      int32_t n_alpha, const double *alpha, double *crit, int32_t n_bins,
+                      double hist_hi, int64_t *hist, hipStream_t stream);
+
+/*
+ * fc_grid_inverse_cov -- write Sigma_q^{-1} = W_q^T W_q (FP64, from the FP64
+ * factor) for q = q0 .. q0+nq-1 into device out [nq][N][N] (asynchronous).
+ * Needs FC_FORM_FP64 built (else FC_ERR_STATE).
+ */
+int fc_grid_inverse_cov(const fc_grid *g, int64_t q0, int64_t nq, double *out,
+                        hipStream_t stream);
+
+/* fc_grid_info -- sizes of a grid (any out pointer may be NULL). */
+int fc_grid_info(const fc_grid *g, int32_t *D, int32_t *N, int64_t *G, uint32_t *forms);
+
+/* fc_grid_device_bytes -- device memory held by the grid (0 for NULL). */
+size_t fc_grid_device_bytes(const fc_grid *g);
+
+/* fc_grid_destroy -- free a grid and its device memory (NULL is a no-op).
+ * Synchronises the device before freeing. */
+void fc_grid_destroy(fc_grid *g);
+
+/* fc_last_error -- message of the last failure on this thread ("" if none). */
+const char *fc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FC_H */

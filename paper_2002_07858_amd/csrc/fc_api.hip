@@ -1,0 +1,318 @@
+// fc_api.hip -- host side of the C ABI declared in include/fc.h.
+//
+// Validation happens here, before any device work; every step of the path
+// itself runs in the kernels of k_grid / k_cov / k_scan / k_crit.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "fc_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? FC_ERR_NOMEM : FC_ERR_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define FC_HIP(call, what)                       \
+    do {                                         \
+        hipError_t e_ = (call);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+void free_forms(fc_grid *g)
+{
+    if (g->W64) (void)hipFree(g->W64);
+    if (g->W32) (void)hipFree(g->W32);
+    g->W64 = nullptr;
+    g->W32 = nullptr;
+    g->forms = 0;
+}
+
+size_t grid_bytes(const fc_grid *g)
+{
+    size_t b = 0;
+    b += sizeof(double) * (size_t)g->G * g->N;  // S64
+    b += sizeof(double) * (size_t)g->G * 64;    // S64p
+    if (g->W64) b += sizeof(double) * (size_t)g->G * ((size_t)g->N * (g->N + 1) / 2);
+    if (g->W32) b += sizeof(float) * (size_t)g->G * g->ng * 256;
+    return b;
+}
+
+bool finite_all(const double *v, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fc_last_error(void) { return g_last_error.c_str(); }
+
+int fc_build_grid(fc_grid **out, int32_t D, const int64_t *axis_len, const double *axis_vals,
+                  int32_t N, const double *signal, const double *central, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!out) return fail(FC_ERR_INVALID_ARG, "fc_build_grid: out is NULL");
+    *out = nullptr;
+    if (D < 1 || D > 16) return fail(FC_ERR_INVALID_ARG, "fc_build_grid: D=%d not in 1..16", D);
+    if (!axis_len || !axis_vals || !signal)
+        return fail(FC_ERR_INVALID_ARG, "fc_build_grid: NULL axis_len/axis_vals/signal");
+    if (N < 1) return fail(FC_ERR_INVALID_ARG, "fc_build_grid: N=%d < 1", N);
+    if (N > FC_MAX_BINS)
+        return fail(FC_ERR_UNSUPPORTED, "fc_build_grid: N=%d > %d bins", N, FC_MAX_BINS);
+    int64_t G = 1, nvals = 0;
+    for (int32_t e = 0; e < D; ++e) {
+        if (axis_len[e] < 1)
+            return fail(FC_ERR_INVALID_ARG, "fc_build_grid: axis %d has length %lld", e,
+                        (long long)axis_len[e]);
+        if (G > (int64_t(1) << 31) / axis_len[e])
+            return fail(FC_ERR_INVALID_ARG, "fc_build_grid: grid has >= 2^31 points");
+        G *= axis_len[e];
+        nvals += axis_len[e];
+    }
+    if (G >= (int64_t(1) << 31)) return fail(FC_ERR_INVALID_ARG, "fc_build_grid: grid too large");
+    if (!finite_all(signal, (size_t)G * N))
+        return fail(FC_ERR_INVALID_ARG, "fc_build_grid: signal has a non-finite entry");
+
+    fc_grid *g = new (std::nothrow) fc_grid();
+    if (!g) return fail(FC_ERR_NOMEM, "fc_build_grid: host allocation failed");
+    g->D = D;
+    g->N = N;
+    g->G = G;
+    g->axis_len.assign(axis_len, axis_len + D);
+    g->axis_vals.assign(axis_vals, axis_vals + nvals);
+    if (central) g->central.assign(central, central + N);
+    g->ns = fcx::n_ksteps(N);
+    g->ng = fcx::n_groups_from_ns(g->ns);
+    (void)hipGetDevice(&g->device);
+
+    hipError_t e;
+    if ((e = hipMalloc(&g->S64, sizeof(double) * (size_t)G * N)) != hipSuccess ||
+        (e = hipMalloc(&g->S64p, sizeof(double) * (size_t)G * 64)) != hipSuccess) {
+        fc_grid_destroy(g);
+        return hip_fail(e, "fc_build_grid: hipMalloc");
+    }
+    if ((e = hipMemcpyAsync(g->S64, signal, sizeof(double) * (size_t)G * N, hipMemcpyHostToDevice,
+                            stream)) != hipSuccess ||
+        (e = fcx::launch_stage_signal(g->S64, G, N, g->S64p, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess) {
+        fc_grid_destroy(g);
+        return hip_fail(e, "fc_build_grid: upload/stage");
+    }
+    g->bytes = grid_bytes(g);
+    *out = g;
+    return FC_OK;
+}
+
+int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
+                        const double *stat_diag, uint32_t forms, int64_t *bad_q,
+                        hipStream_t stream)
+{
+    g_last_error.clear();
+    if (bad_q) *bad_q = -1;
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: grid is NULL");
+    if (!frac_cov || !bad_q) return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: NULL argument");
+    if (stat_mode != FC_STAT_PEARSON && stat_mode != FC_STAT_FIXED)
+        return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: bad stat_mode %d", stat_mode);
+    if (stat_mode == FC_STAT_FIXED && !stat_diag)
+        return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: FIXED mode needs stat_diag");
+    const uint32_t known = FC_FORM_FP64 | FC_FORM_FP32 | FC_FORM_SPLIT_BF16 | FC_FORM_SPLIT_FP16;
+    if (forms == 0 || (forms & ~known))
+        return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: bad forms mask 0x%x", forms);
+    if (forms & (FC_FORM_SPLIT_BF16 | FC_FORM_SPLIT_FP16))
+        return fail(FC_ERR_UNSUPPORTED, "fc_build_covariance: split forms are not built yet");
+    const int N = g->N;
+    if (!finite_all(frac_cov, (size_t)N * N))
+        return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: frac_cov has a non-finite entry");
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < i; ++j)
+            if (frac_cov[i * N + j] != frac_cov[j * N + i])
+                return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: frac_cov not symmetric");
+    if (stat_mode == FC_STAT_FIXED && !finite_all(stat_diag, (size_t)N))
+        return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: stat_diag has a non-finite entry");
+
+    free_forms(g);
+    double *dF = nullptr, *dstat = nullptr;
+    unsigned long long *dbad = nullptr;
+    double *W64 = nullptr;
+    float *W32 = nullptr;
+    hipError_t e = hipSuccess;
+    auto cleanup = [&]() {
+        if (dF) (void)hipFree(dF);
+        if (dstat) (void)hipFree(dstat);
+        if (dbad) (void)hipFree(dbad);
+    };
+    const size_t nt = (size_t)N * (N + 1) / 2;
+    if ((e = hipMalloc(&dF, sizeof(double) * N * N)) != hipSuccess ||
+        (e = hipMalloc(&dstat, sizeof(double) * N)) != hipSuccess ||
+        (e = hipMalloc(&dbad, sizeof(unsigned long long))) != hipSuccess ||
+        ((forms & FC_FORM_FP64) &&
+         (e = hipMalloc(&W64, sizeof(double) * (size_t)g->G * nt)) != hipSuccess) ||
+        ((forms & FC_FORM_FP32) &&
+         (e = hipMalloc(&W32, sizeof(float) * (size_t)g->G * g->ng * 256)) != hipSuccess)) {
+        cleanup();
+        if (W64) (void)hipFree(W64);
+        if (W32) (void)hipFree(W32);
+        return hip_fail(e, "fc_build_covariance: hipMalloc");
+    }
+    const unsigned long long none = ~0ull;
+    unsigned long long hbad = none;
+    if ((e = hipMemcpyAsync(dF, frac_cov, sizeof(double) * N * N, hipMemcpyHostToDevice,
+                            stream)) != hipSuccess ||
+        (stat_mode == FC_STAT_FIXED &&
+         (e = hipMemcpyAsync(dstat, stat_diag, sizeof(double) * N, hipMemcpyHostToDevice,
+                             stream)) != hipSuccess) ||
+        (e = hipMemcpyAsync(dbad, &none, sizeof(none), hipMemcpyHostToDevice, stream)) !=
+            hipSuccess ||
+        (e = fcx::launch_cov_build(g, dF, dstat, stat_mode, forms, W64, W32, dbad, stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&hbad, dbad, sizeof(hbad), hipMemcpyDeviceToHost, stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess) {
+        cleanup();
+        if (W64) (void)hipFree(W64);
+        if (W32) (void)hipFree(W32);
+        return hip_fail(e, "fc_build_covariance: build");
+    }
+    cleanup();
+    if (hbad != none) {
+        if (W64) (void)hipFree(W64);
+        if (W32) (void)hipFree(W32);
+        *bad_q = (int64_t)hbad;
+        g->bytes = grid_bytes(g);
+        return fail(FC_ERR_NOT_PD, "fc_build_covariance: covariance not positive definite at q=%lld",
+                    (long long)hbad);
+    }
+    g->W64 = W64;
+    g->W32 = W32;
+    g->forms = forms;
+    g->bytes = grid_bytes(g);
+    return FC_OK;
+}
+
+int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d, const int64_t *p_idx,
+            double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_scan: grid is NULL");
+    if (form != FC_FORM_FP64 && form != FC_FORM_FP32 && form != FC_FORM_SPLIT_BF16 &&
+        form != FC_FORM_SPLIT_FP16)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan: bad form %d", form);
+    if (!(g->forms & (uint32_t)form))
+        return fail(FC_ERR_STATE, "fc_scan: form %d was not built for this grid", form);
+    if (K < 0) return fail(FC_ERR_INVALID_ARG, "fc_scan: K=%lld < 0", (long long)K);
+    if (K == 0) return FC_OK;
+    if (!d || !p_idx || !dchi2 || !chi2_min || !argmin || !chi2_p)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan: NULL device pointer");
+    if (K > (int64_t(1) << 30))
+        return fail(FC_ERR_INVALID_ARG, "fc_scan: K=%lld > 2^30 universes per call", (long long)K);
+    hipError_t e;
+    if (form == FC_FORM_FP64) {
+        if ((e = fcx::launch_scan_fp64(g, K, d, p_idx, dchi2, chi2_min, argmin, chi2_p, stream)) !=
+            hipSuccess)
+            return hip_fail(e, "fc_scan: fp64 launch");
+        return FC_OK;
+    }
+    if (form == FC_FORM_FP32) {
+        unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
+        if ((e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
+            (e = fcx::launch_scan_fp32(g, K, d, p_idx, keys, chi2_p, stream)) != hipSuccess ||
+            (e = fcx::launch_finalize(K, p_idx, keys, argmin, chi2_p, dchi2, stream)) !=
+                hipSuccess)
+            return hip_fail(e, "fc_scan: fp32 launch");
+        return FC_OK;
+    }
+    return fail(FC_ERR_UNSUPPORTED, "fc_scan: form %d not implemented", form);
+}
+
+int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2, int32_t n_alpha,
+                      const double *alpha, double *crit, int32_t n_bins, double hist_hi,
+                      int64_t *hist, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (n_seg < 0) return fail(FC_ERR_INVALID_ARG, "fc_critical_value: n_seg < 0");
+    if (n_seg > 0x7fffffff) return fail(FC_ERR_INVALID_ARG, "fc_critical_value: n_seg too large");
+    if (n_alpha < 1 || n_alpha > 8)
+        return fail(FC_ERR_INVALID_ARG, "fc_critical_value: n_alpha=%d not in 1..8", n_alpha);
+    if (!alpha) return fail(FC_ERR_INVALID_ARG, "fc_critical_value: alpha is NULL");
+    for (int a = 0; a < n_alpha; ++a)
+        if (!(alpha[a] > 0.0 && alpha[a] <= 1.0))
+            return fail(FC_ERR_INVALID_ARG, "fc_critical_value: alpha[%d]=%g not in (0,1]", a,
+                        alpha[a]);
+    if (hist) {
+        if (n_bins < 1 || n_bins > 16383)
+            return fail(FC_ERR_INVALID_ARG, "fc_critical_value: n_bins=%d not in 1..16383", n_bins);
+        if (!(hist_hi > 0.0) || !isfinite(hist_hi))
+            return fail(FC_ERR_INVALID_ARG, "fc_critical_value: hist_hi must be finite and > 0");
+    }
+    if (n_seg == 0) return FC_OK;
+    if (!seg_off || !dchi2 || !crit)
+        return fail(FC_ERR_INVALID_ARG, "fc_critical_value: NULL device pointer");
+    hipError_t e = fcx::launch_crit(n_seg, seg_off, dchi2, n_alpha, alpha, crit, n_bins, hist_hi,
+                                    hist, stream);
+    if (e != hipSuccess) return hip_fail(e, "fc_critical_value: launch");
+    return FC_OK;
+}
+
+int fc_grid_inverse_cov(const fc_grid *g, int64_t q0, int64_t nq, double *out, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_grid_inverse_cov: grid is NULL");
+    if (!(g->forms & FC_FORM_FP64))
+        return fail(FC_ERR_STATE, "fc_grid_inverse_cov: FP64 form not built");
+    if (q0 < 0 || nq < 0 || q0 + nq > g->G)
+        return fail(FC_ERR_INVALID_ARG, "fc_grid_inverse_cov: range out of the grid");
+    if (nq == 0) return FC_OK;
+    if (!out) return fail(FC_ERR_INVALID_ARG, "fc_grid_inverse_cov: out is NULL");
+    if (nq > 0x7fffffff) return fail(FC_ERR_INVALID_ARG, "fc_grid_inverse_cov: nq too large");
+    hipError_t e = fcx::launch_inverse_cov(g, q0, nq, out, stream);
+    if (e != hipSuccess) return hip_fail(e, "fc_grid_inverse_cov: launch");
+    return FC_OK;
+}
+
+int fc_grid_info(const fc_grid *g, int32_t *D, int32_t *N, int64_t *G, uint32_t *forms)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_grid_info: grid is NULL");
+    if (D) *D = g->D;
+    if (N) *N = g->N;
+    if (G) *G = g->G;
+    if (forms) *forms = g->forms;
+    return FC_OK;
+}
+
+size_t fc_grid_device_bytes(const fc_grid *g) { return g ? g->bytes : 0; }
+
+void fc_grid_destroy(fc_grid *g)
+{
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    free_forms(g);
+    if (g->S64) (void)hipFree(g->S64);
+    if (g->S64p) (void)hipFree(g->S64p);
+    delete g;
+}
+
+}  // extern "C"

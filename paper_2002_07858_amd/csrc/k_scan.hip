@@ -1,0 +1,370 @@
+// k_scan.hip -- the chi^2 grid scan (Eq. (1) inside Algorithm 1's loops).
+//
+// FP32 form (the hot kernel).  Eq. (1) is evaluated in factor form,
+//     chi2(d, q) = ||W_q (d - S_q)||^2,   W_q = L_q^{-1} (lower triangular),
+// which equals (d-S_q)^T Sigma_q^{-1} (d-S_q).  For a fixed q and a tile of 64
+// universes this is a dense contraction Z = W_q R (R = bins x universes),
+// done on the matrix cores with v_mfma_f32_16x16x4_f32 over the lower-
+// triangular block pattern of W_q only, followed by a column-wise sum of
+// squares (FP64), a reduce-scatter across the four 16-lane groups and a
+// strict-"<" running minimum per universe.
+//
+// Work decomposition: a block of 4 waves owns 256 universes; each wave owns
+// 64 universes and walks one contiguous chunk of grid points in list order.
+// A wave keeps its universes' residual operands in registers for the whole
+// chunk and streams W_q (lane-major fragments, one 16-byte load per lane per
+// four MFMAs) and S_q from global memory; there is no LDS and no barrier.
+// Chunks of the same universes are merged with a 64-bit atomicMin on keys
+// (FP32 chi2 bits above q), which reproduces Algorithm 1's rule that the
+// lowest q wins exact ties whatever the chunking.
+#include "fc_internal.h"
+
+namespace fcx {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Index of pair (s, b) in the fragment order (s outer, b = s/4 .. nb-1 inner).
+__host__ __device__ constexpr int pair_index(int ns, int s, int b)
+{
+    int nb = n_rowblocks_from_ns(ns), t = 0;
+    for (int s2 = 0; s2 < s; ++s2) t += nb - s2 / 4;
+    return t + (b - s / 4);
+}
+
+__device__ __forceinline__ float pick(const float4 &v, int c)
+{
+    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+
+template <int NS, int NC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32(
+    const float *__restrict__ W32, const double *__restrict__ S64p, const double *__restrict__ d,
+    const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
+    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
+{
+    static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
+    constexpr int NB = n_rowblocks_from_ns(NS);
+    constexpr int NG = n_groups_from_ns(NS);
+    constexpr int UW = 16 * NC;  // universes per wave
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t utile = blockIdx.x % n_utiles;
+    const int64_t qchunk = blockIdx.x / n_utiles;
+    const int64_t u0 = utile * (int64_t)(UW * kWavesPerBlock) + wave * UW;
+    const int64_t qb = qchunk * q_per_chunk;
+    const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
+    if (u0 >= K || qb >= qe) return;  // uniform per wave
+    const int grp = lane >> 4, col = lane & 15;
+
+    // B-operand sources in FP64: universe u0+16c+col, bin 4s+grp (zero past N)
+    double dv[NC][NS];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int64_t u = u0 + 16 * c + col;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = 4 * s + grp;
+            dv[c][s] = (u < K && k < N) ? d[u * N + k] : 0.0;
+        }
+    }
+    // after the reduction, lane l holds column block cl of universe column col
+    const int cl = (NC == 4) ? grp : (grp >> 1);
+    const bool owner = (NC == 4) ? true : ((grp & 1) == 0);
+    const int64_t u_own = u0 + 16 * cl + col;
+    const int64_t p_own = (u_own < K) ? p_idx[u_own] : -1;
+    float best = __builtin_inff();
+    uint32_t qbest = 0xffffffffu;
+    float cp = 0.0f;
+    bool have_cp = false;
+
+    for (int64_t q = qb; q < qe; ++q) {
+        const float4 *wq = reinterpret_cast<const float4 *>(W32 + q * (int64_t)(NG * 256));
+        float4 wv[NG];
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) wv[gi] = wq[gi * 64 + lane];
+        const double2 *sq = reinterpret_cast<const double2 *>(S64p + q * 64 + grp * 16);
+        double2 sv2[(NS + 1) / 2];
+#pragma unroll
+        for (int i = 0; i < (NS + 1) / 2; ++i) sv2[i] = sq[i];
+
+        v4f acc[NC][NB];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[c][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const double sval = (s & 1) ? sv2[s >> 1].y : sv2[s >> 1].x;
+            float r[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) r[c] = (float)(dv[c][s] - sval);  // one rounding
+#pragma unroll
+            for (int b = s / 4; b < NB; ++b) {
+                const int t = pair_index(NS, s, b);
+                const float w = pick(wv[t >> 2], t & 3);
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, r[c], acc[c][b], 0, 0, 0);
+            }
+        }
+
+        // sum of squares per universe column, in FP64
+        double part[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double a = 0.0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double z = (double)acc[c][b][j];
+                    a = fma(z, z, a);
+                }
+            part[c] = a;
+        }
+        // reduce over the four lane groups (each holds 4 of every 16 z rows)
+        const bool hi = lane >= 32;
+        double kk;
+        if constexpr (NC == 4) {
+            // reduce-scatter: lane l ends with column block l/16
+            double k0 = hi ? part[2] : part[0];
+            double k1 = hi ? part[3] : part[1];
+            const double s0 = hi ? part[0] : part[2];
+            const double s1 = hi ? part[1] : part[3];
+            k0 += __shfl_xor(s0, 32);
+            k1 += __shfl_xor(s1, 32);
+            const bool odd = grp & 1;
+            kk = odd ? k1 : k0;
+            const double ss = odd ? k0 : k1;
+            kk += __shfl_xor(ss, 16);
+        } else {
+            // lanes < 32 keep block 0, lanes >= 32 block 1; then pair groups
+            kk = hi ? part[1] : part[0];
+            const double s0 = hi ? part[0] : part[1];
+            kk += __shfl_xor(s0, 32);
+            kk += __shfl_xor(kk, 16);
+        }
+        const float chi2 = (float)kk;
+
+        if (q == p_own) {
+            cp = chi2;
+            have_cp = true;
+        }
+        if (chi2 < best) {
+            best = chi2;
+            qbest = (uint32_t)q;
+        }
+    }
+
+    if (owner && u_own < K) {
+        if (have_cp) chi2_p[u_own] = (double)cp;
+        if (best < __builtin_inff()) {
+            const unsigned long long key =
+                ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)qbest;
+            atomicMin(&keys[u_own], key);
+        }
+    }
+}
+
+// FP64 form: one thread per universe over the whole grid (the parity anchor).
+// W_q is uniform across the wave, so its entries arrive through scalar loads.
+template <int NP>
+__global__ __launch_bounds__(64) void k_scan_fp64(
+    const double *__restrict__ W64, const double *__restrict__ S64, const double *__restrict__ d,
+    const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, double *__restrict__ dchi2,
+    double *__restrict__ chi2_min, int64_t *__restrict__ argmin, double *__restrict__ chi2_p)
+{
+    const int64_t u = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (u >= K) return;
+    const int64_t NT = (int64_t)N * (N + 1) / 2;
+    double dv[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) dv[j] = (j < N) ? d[u * N + j] : 0.0;
+    const int64_t p = p_idx[u];
+    double best = __builtin_inf();
+    int64_t qbest = p;
+    double cp = __builtin_nan("");
+    for (int64_t q = 0; q < G; ++q) {
+        const double *Wq = W64 + q * NT;
+        const double *Sq = S64 + q * N;
+        double r[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) r[j] = (j < N) ? dv[j] - Sq[j] : 0.0;
+        double chi2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            if (i < N) {
+                double z = 0.0;
+#pragma unroll
+                for (int j = 0; j <= i; ++j) z = fma(Wq[tri_index(i, j)], r[j], z);
+                chi2 = fma(z, z, chi2);
+            }
+        }
+        if (q == p) cp = chi2;
+        if (chi2 < best) {
+            best = chi2;
+            qbest = q;
+        }
+    }
+    chi2_min[u] = best;
+    argmin[u] = qbest;
+    chi2_p[u] = cp;
+    dchi2[u] = cp - best;
+}
+
+__global__ __launch_bounds__(256) void k_init_keys(int64_t K, unsigned long long *__restrict__ keys,
+                                                  double *__restrict__ chi2_p)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= K) return;
+    keys[u] = kKeyNone;
+    chi2_p[u] = __builtin_nan("");
+}
+
+// Decode the keys in place (the key buffer is the caller's chi2_min array).
+__global__ __launch_bounds__(256) void k_finalize(int64_t K, const int64_t *__restrict__ p_idx,
+                                                 unsigned long long *__restrict__ keys,
+                                                 int64_t *__restrict__ argmin,
+                                                 const double *__restrict__ chi2_p,
+                                                 double *__restrict__ dchi2)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= K) return;
+    const unsigned long long key = keys[u];
+    const uint32_t hi = (uint32_t)(key >> 32);
+    double cmin;
+    int64_t am;
+    if (hi >= 0x7f800000u) {  // no chi2 < +inf was seen: Algorithm 1's initial state
+        cmin = __builtin_inf();
+        am = p_idx[u];
+    } else {
+        cmin = (double)__uint_as_float(hi);
+        am = (int64_t)(uint32_t)(key & 0xffffffffu);
+    }
+    reinterpret_cast<double *>(keys)[u] = cmin;
+    argmin[u] = am;
+    dchi2[u] = chi2_p[u] - cmin;
+}
+
+// ---------------------------------------------------------------------------
+// Resident block slots of a kernel on the current device: CUs x blocks per CU
+// from the occupancy calculator.
+static int resident_slots(const void *kernel, int block_threads)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 512;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block_threads, 0) !=
+            hipSuccess ||
+        per_cu <= 0)
+        per_cu = 2;
+    return cus * per_cu;
+}
+
+// Pick the number of grid chunks so that tiles x chunks fills the resident
+// block slots with the smallest tail: minimise ceil(tiles*c/slots)/c.
+ScanGeometry scan_geometry(int64_t K, int64_t G, int slots, int univ_per_block)
+{
+    ScanGeometry sg;
+    sg.n_utiles = (K + univ_per_block - 1) / univ_per_block;
+    const int64_t min_chunk = 64;
+    int64_t cmax = G / min_chunk;
+    if (cmax < 1) cmax = 1;
+    if (cmax > 256) cmax = 256;
+    // keep blocks * 256 work-items well inside the 32-bit dispatch size
+    const int64_t max_blocks = int64_t(1) << 23;
+    const int64_t cfit = max_blocks / (sg.n_utiles > 0 ? sg.n_utiles : 1);
+    if (cmax > cfit) cmax = cfit > 0 ? cfit : 1;
+    double best = 1e300;
+    int64_t bestc = 1;
+    for (int64_t c = 1; c <= cmax; ++c) {
+        const int64_t units = sg.n_utiles * c;
+        const double rounds = (double)((units + slots - 1) / slots);
+        const double cost = rounds / (double)c * (1.0 + 0.002 * (double)c);  // chunk overhead
+        if (cost < best * (1.0 - 1e-9)) {
+            best = cost;
+            bestc = c;
+        }
+    }
+    sg.q_per_chunk = (G + bestc - 1) / bestc;
+    sg.n_qchunks = (G + sg.q_per_chunk - 1) / sg.q_per_chunk;
+    return sg;
+}
+
+template <int NS>
+static hipError_t launch_fp32_ns(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
+                                 unsigned long long *keys, double *chi2_p, hipStream_t st)
+{
+    constexpr int NC = kScanColBlocks;
+    static int slots = 0;  // per instantiation; same device model for the process
+    if (slots == 0)
+        slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32<NS, NC>),
+                               64 * kWavesPerBlock);
+    const ScanGeometry sg = scan_geometry(K, g->G, slots, 16 * NC * kWavesPerBlock);
+    const int64_t blocks = sg.n_utiles * sg.n_qchunks;
+    hipLaunchKernelGGL((k_scan_fp32<NS, NC>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
+                       st, g->W32, g->S64p, d, p_idx, K, g->N, g->G, sg.n_utiles, sg.q_per_chunk,
+                       keys, chi2_p);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
+                            unsigned long long *keys, double *chi2_p, hipStream_t st)
+{
+    switch (g->ns) {
+#define FC_CASE(n) \
+    case n: return launch_fp32_ns<n>(g, K, d, p_idx, keys, chi2_p, st);
+        FC_CASE(1) FC_CASE(2) FC_CASE(3) FC_CASE(4) FC_CASE(5) FC_CASE(6) FC_CASE(7) FC_CASE(8)
+        FC_CASE(9) FC_CASE(10) FC_CASE(11) FC_CASE(12) FC_CASE(13) FC_CASE(14) FC_CASE(15)
+        FC_CASE(16)
+#undef FC_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NP>
+static hipError_t launch_fp64_np(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
+                                 double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p,
+                                 hipStream_t st)
+{
+    const int64_t blocks = (K + 63) / 64;
+    hipLaunchKernelGGL(k_scan_fp64<NP>, dim3((unsigned)blocks), dim3(64), 0, st, g->W64, g->S64, d,
+                       p_idx, K, g->N, g->G, dchi2, chi2_min, argmin, chi2_p);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
+                            double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p,
+                            hipStream_t st)
+{
+    const int np = ((g->N + 7) / 8) * 8;
+    switch (np) {
+#define FC_CASE(n) \
+    case n: return launch_fp64_np<n>(g, K, d, p_idx, dchi2, chi2_min, argmin, chi2_p, st);
+        FC_CASE(8) FC_CASE(16) FC_CASE(24) FC_CASE(32) FC_CASE(40) FC_CASE(48) FC_CASE(56)
+        FC_CASE(64)
+#undef FC_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p, hipStream_t st)
+{
+    const int64_t blocks = (K + 255) / 256;
+    hipLaunchKernelGGL(k_init_keys, dim3((unsigned)blocks), dim3(256), 0, st, K, keys, chi2_p);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(int64_t K, const int64_t *p_idx, unsigned long long *keys_as_chi2_min,
+                           int64_t *argmin, const double *chi2_p, double *dchi2, hipStream_t st)
+{
+    const int64_t blocks = (K + 255) / 256;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, st, K, p_idx,
+                       keys_as_chi2_min, argmin, chi2_p, dchi2);
+    return hipGetLastError();
+}
+
+}  // namespace fcx

@@ -1,0 +1,222 @@
+"""Thin ctypes binding of libfc.so (include/fc.h), same names as the C ABI.
+
+Argument marshalling only: host arrays are numpy, device arrays are torch CUDA
+tensors (PyTorch-ROCm supplies device memory and streams), and every step of
+the computation runs in the library's HIP kernels.  There is no CPU fallback:
+if libfc.so is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfc.so")
+
+FC_OK = 0
+FC_ERR_INVALID_ARG = -1
+FC_ERR_NOT_PD = -2
+FC_ERR_NOMEM = -3
+FC_ERR_DEVICE = -4
+FC_ERR_STATE = -5
+FC_ERR_UNSUPPORTED = -6
+
+FC_FORM_FP64 = 1
+FC_FORM_FP32 = 2
+FC_FORM_SPLIT_BF16 = 4
+FC_FORM_SPLIT_FP16 = 8
+
+FC_STAT_PEARSON = 0
+FC_STAT_FIXED = 1
+
+FC_MAX_BINS = 64
+
+EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
+            "fc_grid_inverse_cov", "fc_grid_info", "fc_grid_device_bytes", "fc_grid_destroy",
+            "fc_last_error")
+
+
+class FCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_dbl = ctypes.c_double
+
+
+def lib():
+    """Load libfc.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2002_07858_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.fc_build_grid.argtypes = [ctypes.POINTER(_p), _i32, _p, _p, _i32, _p, _p, _p]
+        L.fc_build_covariance.argtypes = [_p, _p, _i32, _p, _u32, _p, _p]
+        L.fc_scan.argtypes = [_p, _i32, _i64, _p, _p, _p, _p, _p, _p, _p]
+        L.fc_critical_value.argtypes = [_i64, _p, _p, _i32, _p, _p, _i32, _dbl, _p, _p]
+        L.fc_grid_inverse_cov.argtypes = [_p, _i64, _i64, _p, _p]
+        L.fc_grid_info.argtypes = [_p, _p, _p, _p, _p]
+        L.fc_grid_device_bytes.argtypes = [_p]
+        L.fc_grid_device_bytes.restype = ctypes.c_size_t
+        L.fc_grid_destroy.argtypes = [_p]
+        L.fc_grid_destroy.restype = None
+        L.fc_last_error.argtypes = []
+        L.fc_last_error.restype = ctypes.c_char_p
+        for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
+                     "fc_grid_inverse_cov", "fc_grid_info"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def fc_last_error() -> str:
+    return lib().fc_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != FC_OK:
+        raise FCError(rc, fc_last_error())
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hp(a):
+    return None if a is None else a.ctypes.data_as(_p)
+
+
+def _dev(t, dtype_name: str, name: str):
+    """Device pointer of a contiguous torch CUDA tensor of the given dtype (or None)."""
+    if t is None:
+        return None
+    import torch
+    want = {"f64": torch.float64, "i64": torch.int64}[dtype_name]
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch CUDA tensor")
+    if t.dtype != want:
+        raise TypeError(f"{name} must have dtype {want}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return _p(t.data_ptr()) if t.numel() else None
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return _p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _p(stream)
+    return _p(stream.cuda_stream)
+
+
+class Grid:
+    """Owning wrapper of an fc_grid handle."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    @property
+    def _h(self):
+        if not self.handle:
+            raise FCError(FC_ERR_STATE, "grid was destroyed")
+        return _p(self.handle)
+
+    def info(self):
+        return fc_grid_info(self)
+
+    def device_bytes(self) -> int:
+        return fc_grid_device_bytes(self)
+
+    def destroy(self):
+        if self.handle:
+            lib().fc_grid_destroy(_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def fc_build_grid(axes, signal, central=None, stream=None) -> Grid:
+    """Make a grid resident: ``axes`` is a list of D 1-D arrays, ``signal`` [G][N]."""
+    lens = _host([len(a) for a in axes], np.int64)
+    vals = _host(np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in axes]),
+                 np.float64)
+    S = _host(signal, np.float64)
+    if S.ndim != 2:
+        raise ValueError("signal must be [G][N]")
+    c = None if central is None else _host(central, np.float64)
+    out = _p()
+    _check(lib().fc_build_grid(ctypes.byref(out), len(axes), _hp(lens), _hp(vals),
+                               int(S.shape[1]), _hp(S), _hp(c), _stream(stream)))
+    return Grid(out.value)
+
+
+def fc_build_covariance(grid: Grid, frac_cov, stat_mode=FC_STAT_PEARSON, stat_diag=None,
+                        forms=FC_FORM_FP32 | FC_FORM_FP64, stream=None) -> int:
+    """Build every requested form; returns -1, raises FCError (with .bad_q) if not PD."""
+    F = _host(frac_cov, np.float64)
+    sd = None if stat_diag is None else _host(stat_diag, np.float64)
+    bad = np.full(1, -1, dtype=np.int64)
+    rc = lib().fc_build_covariance(grid._h, _hp(F), int(stat_mode), _hp(sd), int(forms),
+                                   _hp(bad), _stream(stream))
+    if rc != FC_OK:
+        err = FCError(rc, fc_last_error())
+        err.bad_q = int(bad[0])
+        raise err
+    return int(bad[0])
+
+
+def fc_scan(grid: Grid, form: int, d, p_idx, dchi2, chi2_min, argmin, chi2_p, stream=None):
+    """Enqueue the scan of K = d.shape[0] universes (all arrays torch CUDA tensors)."""
+    K = int(d.shape[0]) if d is not None else 0
+    _check(lib().fc_scan(grid._h, int(form), K, _dev(d, "f64", "d"), _dev(p_idx, "i64", "p_idx"),
+                         _dev(dchi2, "f64", "dchi2"), _dev(chi2_min, "f64", "chi2_min"),
+                         _dev(argmin, "i64", "argmin"), _dev(chi2_p, "f64", "chi2_p"),
+                         _stream(stream)))
+
+
+def fc_critical_value(seg_off, dchi2, alpha, crit, n_bins=200, hist_hi=50.0, hist=None,
+                      stream=None):
+    """Enqueue critical values (and histograms) for n_seg = seg_off.numel()-1 segments."""
+    a = _host(np.atleast_1d(alpha), np.float64)
+    n_seg = int(seg_off.numel()) - 1
+    _check(lib().fc_critical_value(n_seg, _dev(seg_off, "i64", "seg_off"),
+                                   _dev(dchi2, "f64", "dchi2"), int(a.shape[0]), _hp(a),
+                                   _dev(crit, "f64", "crit"), int(n_bins), float(hist_hi),
+                                   _dev(hist, "i64", "hist"), _stream(stream)))
+
+
+def fc_grid_inverse_cov(grid: Grid, q0: int, nq: int, out, stream=None):
+    _check(lib().fc_grid_inverse_cov(grid._h, int(q0), int(nq), _dev(out, "f64", "out"),
+                                     _stream(stream)))
+
+
+def fc_grid_info(grid: Grid):
+    D = ctypes.c_int32()
+    N = ctypes.c_int32()
+    G = ctypes.c_int64()
+    forms = ctypes.c_uint32()
+    _check(lib().fc_grid_info(grid._h, ctypes.byref(D), ctypes.byref(N), ctypes.byref(G),
+                              ctypes.byref(forms)))
+    return dict(D=D.value, N=N.value, G=G.value, forms=forms.value)
+
+
+def fc_grid_device_bytes(grid: Grid) -> int:
+    return int(lib().fc_grid_device_bytes(grid._h))
+
+
+def fc_grid_destroy(grid: Grid):
+    grid.destroy()

@@ -1,0 +1,119 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments before touching the device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fc.h")
+
+
+@pytest.fixture(scope="module")
+def fcmod():
+    import paper_2002_07858_amd.fc as fc
+    if not os.path.exists(fc.LIB_PATH):
+        from paper_2002_07858_amd import build
+        build.build()
+    return fc
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
+              "fc_grid_destroy", "fc_grid_device_bytes", "fc_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(fcmod):
+    lib = ctypes.CDLL(fcmod.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(declared_functions()) == set(fcmod.EXPORTED)
+
+
+def test_status_codes_match_header(fcmod):
+    text = open(HEADER).read()
+    for name in ("FC_OK", "FC_ERR_INVALID_ARG", "FC_ERR_NOT_PD", "FC_ERR_NOMEM",
+                 "FC_ERR_DEVICE", "FC_ERR_STATE", "FC_ERR_UNSUPPORTED", "FC_FORM_FP64",
+                 "FC_FORM_FP32", "FC_FORM_SPLIT_BF16", "FC_FORM_SPLIT_FP16", "FC_STAT_PEARSON",
+                 "FC_STAT_FIXED", "FC_MAX_BINS"):
+        m = re.search(rf"\b{name}\s*=?\s*(-?\d+)", text)
+        assert m, name
+        assert int(m.group(1)) == getattr(fcmod, name), name
+
+
+def _call_build_grid(fcmod, D, lens, vals, N, S):
+    out = ctypes.c_void_p()
+    lens = np.ascontiguousarray(lens, dtype=np.int64)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    rc = fcmod.lib().fc_build_grid(ctypes.byref(out), D, lens.ctypes.data_as(ctypes.c_void_p),
+                                   vals.ctypes.data_as(ctypes.c_void_p), N,
+                                   S.ctypes.data_as(ctypes.c_void_p), None, None)
+    return rc, out.value
+
+
+def test_build_grid_rejects_bad_arguments_on_host(fcmod):
+    S = np.ones((4, 3))
+    assert _call_build_grid(fcmod, 0, [4], [0, 1, 2, 3], 3, S)[0] == fcmod.FC_ERR_INVALID_ARG
+    assert _call_build_grid(fcmod, 1, [0], [0.0], 3, S)[0] == fcmod.FC_ERR_INVALID_ARG
+    assert _call_build_grid(fcmod, 1, [4], [0, 1, 2, 3], 0, S)[0] == fcmod.FC_ERR_INVALID_ARG
+    S65 = np.ones((4, 65))
+    rc, h = _call_build_grid(fcmod, 1, [4], [0, 1, 2, 3], 65, S65)
+    assert rc == fcmod.FC_ERR_UNSUPPORTED and h is None
+    Sbad = np.ones((4, 3))
+    Sbad[2, 1] = np.nan
+    rc, _ = _call_build_grid(fcmod, 1, [4], [0, 1, 2, 3], 3, Sbad)
+    assert rc == fcmod.FC_ERR_INVALID_ARG
+    assert "non-finite" in fcmod.fc_last_error()
+    rc, _ = _call_build_grid(fcmod, 2, [1 << 16, 1 << 16], np.zeros(1 << 17), 3, S)
+    assert rc == fcmod.FC_ERR_INVALID_ARG
+
+
+def test_calls_on_null_grid_fail_cleanly(fcmod):
+    L = fcmod.lib()
+    F = np.eye(3)
+    bad = np.zeros(1, dtype=np.int64)
+    assert L.fc_build_covariance(None, F.ctypes.data_as(ctypes.c_void_p), 0, None, 2,
+                                 bad.ctypes.data_as(ctypes.c_void_p), None) == \
+        fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_scan(None, 2, 10, None, None, None, None, None, None, None) == \
+        fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_grid_inverse_cov(None, 0, 1, None, None) == fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_grid_info(None, None, None, None, None) == fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_grid_device_bytes(None) == 0
+    L.fc_grid_destroy(None)
+
+
+def test_critical_value_validation(fcmod):
+    L = fcmod.lib()
+    a = np.array([0.9])
+    ap = a.ctypes.data_as(ctypes.c_void_p)
+    assert L.fc_critical_value(-1, None, None, 1, ap, None, 10, 5.0, None, None) == \
+        fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_critical_value(1, None, None, 0, ap, None, 10, 5.0, None, None) == \
+        fcmod.FC_ERR_INVALID_ARG
+    a0 = np.array([0.0])
+    assert L.fc_critical_value(1, None, None, 1, a0.ctypes.data_as(ctypes.c_void_p), None, 10,
+                               5.0, None, None) == fcmod.FC_ERR_INVALID_ARG
+    # zero segments: nothing to do, no device work
+    assert L.fc_critical_value(0, None, None, 1, ap, None, 10, 5.0, None, None) == fcmod.FC_OK
+    # a segment but NULL device pointers
+    assert L.fc_critical_value(1, None, None, 1, ap, None, 10, 5.0, None, None) == \
+        fcmod.FC_ERR_INVALID_ARG
+
+
+def test_binding_refuses_host_arrays(fcmod):
+    with pytest.raises(TypeError):
+        fcmod._dev(np.zeros(3), "f64", "d")

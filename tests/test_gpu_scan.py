@@ -1,0 +1,298 @@
+"""GPU parity of the hot path against the FP64 oracle (through the C ABI)."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import fcgen
+import oracle
+import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2002_07858_amd as fc
+    fc.lib()  # raises if libfc.so is missing: no fallback
+    return fc
+
+
+def to_dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def run_scan(fc, grid, form, d, p):
+    K = d.shape[0]
+    d_t = to_dev(d, torch.float64)
+    p_t = to_dev(p, torch.int64)
+    out = {k: torch.full((K,), -7.0, dtype=torch.float64, device="cuda")
+           for k in ("dchi2", "chi2_min", "chi2_p")}
+    out["argmin"] = torch.full((K,), -7, dtype=torch.int64, device="cuda")
+    fc.fc_scan(grid, form, d_t, p_t, out["dchi2"], out["chi2_min"], out["argmin"],
+               out["chi2_p"])
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def make_grid(fc, pr, forms):
+    g = fc.fc_build_grid(pr.axes, pr.S)
+    fc.fc_build_covariance(g, pr.F, pr.stat_mode, pr.stat_diag, forms=forms)
+    return g
+
+
+FORM = {"fp64": 1, "fp32": 2}
+
+
+# ---------------------------------------------------------------------------
+# covariance factors: W^T W against LAPACK's inverse
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_inverse_covariance_matches_lapack(fc, name):
+    pr = fcgen.make_problem(name, K=1, true_subset=[0])
+    g = make_grid(fc, pr, 1 | 2)
+    qs = np.unique(np.linspace(0, pr.G - 1, 25).astype(int))
+    for q in qs:
+        out = torch.empty((1, pr.N, pr.N), dtype=torch.float64, device="cuda")
+        fc.fc_grid_inverse_cov(g, int(q), 1, out)
+        torch.cuda.synchronize()
+        M = out.cpu().numpy()[0]
+        Sig = oracle.covariance(pr.S[q], pr.F)
+        ref = np.linalg.inv(Sig)
+        kappa = np.linalg.cond(Sig)
+        err = np.linalg.norm(M - ref) / np.linalg.norm(ref)
+        assert err <= 1e-12 * kappa, (q, err, kappa)
+
+
+def test_not_positive_definite_reports_first_bad_point(fc):
+    N = 4
+    S = np.full((6, N), 100.0)
+    S[3] = [100.0, 200.0, 50.0, 10.0]
+    F = np.diag([0.01, 0.01, 0.01, 0.01])
+    F[0, 1] = F[1, 0] = 0.5
+    g = fc.fc_build_grid([np.arange(6.0)], S)
+    with pytest.raises(fc.FCError) as ei:
+        fc.fc_build_covariance(g, F, fc.FC_STAT_FIXED, np.zeros(N), forms=2)
+    assert ei.value.code == fc.FC_ERR_NOT_PD and ei.value.bad_q == 0
+    # a form that was not built is a state error
+    d = to_dev(np.zeros((3, N)), torch.float64)
+    p = to_dev(np.zeros(3), torch.int64)
+    o = torch.empty(3, dtype=torch.float64, device="cuda")
+    a = torch.empty(3, dtype=torch.int64, device="cuda")
+    with pytest.raises(fc.FCError) as ei:
+        fc.fc_scan(g, fc.FC_FORM_FP32, d, p, o, o.clone(), a, o.clone())
+    assert ei.value.code == fc.FC_ERR_STATE
+
+
+# ---------------------------------------------------------------------------
+# scan parity on the small FP64 case and a ragged FP32 case
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_scan_parity_c1(fc, form):
+    pr = fcgen.make_problem("c1")
+    ref = oracle.scan(pr.S, pr.F, pr.d, pr.p_idx)
+    g = make_grid(fc, pr, 1 | 2)
+    dev = run_scan(fc, g, FORM[form], pr.d, pr.p_idx)
+    parity.check_invariants(dev, pr.G)
+    rep = parity.report(dev, ref, parity.TOL[form])
+    print(form, rep)
+    assert rep["e_rel"] <= parity.TOL[form]
+    assert rep["argmin_agree"] == 1.0
+
+
+def test_scan_parity_fp32_ragged_multi_tile(fc):
+    # 4 true points x 301 universes: 1204 universes = 4 full 256-blocks + a ragged tail
+    pr = fcgen.make_problem("c2", K=301, true_subset=[0, 77, 200, 255])
+    ref = oracle.scan(pr.S, pr.F, pr.d, pr.p_idx)
+    g = make_grid(fc, pr, 2)
+    dev = run_scan(fc, g, 2, pr.d, pr.p_idx)
+    parity.check_invariants(dev, pr.G)
+    rep = parity.report(dev, ref, parity.TOL["fp32"])
+    print(rep)
+    assert rep["e_rel"] <= 1e-6
+    assert rep["argmin_agree"] >= 0.999
+
+
+@pytest.mark.parametrize("N", [1, 3, 4, 5, 16, 17, 33, 64])
+def test_scan_parity_bin_counts(fc, N):
+    # every k-step count 1..16 class and N at the 64-bin maximum
+    rng = np.random.default_rng(100 + N)
+    G, K = 37, 150
+    S = rng.uniform(50, 300, size=(G, N))
+    A = rng.normal(size=(N, 2 * N))
+    W = A @ A.T
+    W = 0.5 * (W + W.T)
+    dw = np.sqrt(np.diag(W))
+    F = (W / np.outer(dw, dw)) * 0.01
+    F = 0.5 * (F + F.T)
+    p = rng.integers(0, G, size=K)
+    d = S[p] + rng.normal(0, 1, size=(K, N)) * np.sqrt(S[p])
+    ref = oracle.scan(S, F, d, p)
+    g = fc.fc_build_grid([np.arange(float(G))], S)
+    fc.fc_build_covariance(g, F, forms=3)
+    for form in ("fp64", "fp32"):
+        dev = run_scan(fc, g, FORM[form], d, p)
+        parity.check_invariants(dev, G)
+        rep = parity.report(dev, ref, parity.TOL[form])
+        assert rep["e_rel"] <= parity.TOL[form], (form, rep)
+        assert rep["argmin_agree"] == 1.0, (form, rep)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_edge_cases(fc):
+    pr = fcgen.make_problem("c1", K=70)
+    g = make_grid(fc, pr, 1 | 2)
+    # K = 0 enqueues nothing
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    ei = torch.empty(0, dtype=torch.int64, device="cuda")
+    fc.fc_scan(g, 2, torch.empty((0, pr.N), dtype=torch.float64, device="cuda"), ei, e, e, ei, e)
+    # unfluctuated universes at on-grid points: chi2_min = dchi2 = 0 exactly
+    ps = np.array([0, 17, 382, 399, 200])
+    for form in (1, 2):
+        dev = run_scan(fc, g, form, pr.S[ps], ps)
+        assert np.all(dev["dchi2"] == 0.0) and np.all(dev["chi2_min"] == 0.0)
+        np.testing.assert_array_equal(dev["argmin"], ps)
+    # NaN data: that universe only gets (inf, p, NaN); an out-of-range p gives NaN
+    d = pr.d.copy()
+    p = pr.p_idx.copy()
+    d[3, 7] = np.nan
+    p[5] = pr.G + 3
+    p[6] = -2
+    ref = oracle.scan(pr.S, pr.F, np.delete(d, [3, 5, 6], 0), np.delete(p, [3, 5, 6]))
+    for form in ("fp64", "fp32"):
+        dev = run_scan(fc, g, FORM[form], d, p)
+        assert np.isinf(dev["chi2_min"][3]) and dev["argmin"][3] == p[3]
+        assert np.isnan(dev["dchi2"][3])
+        assert np.isnan(dev["dchi2"][5]) and np.isnan(dev["chi2_p"][5])
+        assert np.isnan(dev["dchi2"][6])
+        keep = {k: np.delete(v, [3, 5, 6]) for k, v in dev.items()}
+        rep = parity.report(keep, ref, parity.TOL[form])
+        assert rep["e_rel"] <= parity.TOL[form]
+
+
+def test_single_point_grid_and_single_universe(fc):
+    pr = fcgen.make_problem("c1", K=1)
+    S1 = pr.S[[382]]
+    g = fc.fc_build_grid([np.array([0.0])], S1)
+    fc.fc_build_covariance(g, pr.F, forms=3)
+    for form in (1, 2):
+        dev = run_scan(fc, g, form, pr.d[:1], np.zeros(1, dtype=np.int64))
+        assert dev["dchi2"][0] == 0.0 and dev["argmin"][0] == 0
+
+
+def test_exact_ties_pick_lowest_grid_index(fc):
+    pr = fcgen.make_problem("c1", K=200)
+    S = pr.S.copy()
+    S[390] = S[5]           # duplicate rows: identical chi^2 at q=5 and q=390
+    S[391] = S[5]
+    d = np.repeat(S[[5]], 3, axis=0)
+    d[1] += 0.25            # not on the grid: compared with the oracle instead
+    p = np.array([390, 391, 5])
+    ref = oracle.scan(S, pr.F, d, p)
+    g = fc.fc_build_grid(pr.axes, S)
+    fc.fc_build_covariance(g, pr.F, forms=3)
+    for form in (1, 2):
+        dev = run_scan(fc, g, form, d, p)
+        # chi^2 = 0 exactly at q = 5, 390 and 391: the lowest index wins
+        assert dev["argmin"][0] == 5 and dev["argmin"][2] == 5
+        assert dev["dchi2"][0] == 0.0 and dev["dchi2"][2] == 0.0
+        assert dev["argmin"][1] == ref["argmin"][1]
+
+
+# ---------------------------------------------------------------------------
+# determinism: rerun and batch composition do not change a single bit
+# ---------------------------------------------------------------------------
+def test_bitwise_determinism_and_batch_invariance(fc):
+    pr = fcgen.make_problem("c2", K=600, true_subset=[3, 100, 250])
+    g = make_grid(fc, pr, 2)
+    a = run_scan(fc, g, 2, pr.d, pr.p_idx)
+    b = run_scan(fc, g, 2, pr.d, pr.p_idx)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+    # the same universes alone (different tiles and grid chunking) and in a mix
+    sub = slice(650, 777)
+    c = run_scan(fc, g, 2, pr.d[sub], pr.p_idx[sub])
+    for k in a:
+        np.testing.assert_array_equal(a[k][sub], c[k])
+
+
+# ---------------------------------------------------------------------------
+# critical values and histograms
+# ---------------------------------------------------------------------------
+def test_critical_values_match_oracle(fc):
+    pr = fcgen.make_problem("c2", K=700, true_subset=[0, 1, 2, 9])
+    g = make_grid(fc, pr, 2)
+    dev = run_scan(fc, g, 2, pr.d, pr.p_idx)
+    alphas = [0.6827, 0.9, 0.95]
+    x = dev["dchi2"].copy()
+    x[5] = np.nan
+    off = np.array([0, 700, 700, 1400, 2100, 2800])   # includes an empty segment
+    seg = to_dev(off, torch.int64)
+    xt = to_dev(x, torch.float64)
+    crit = torch.empty((5, 3), dtype=torch.float64, device="cuda")
+    hist = torch.empty((5, 201), dtype=torch.int64, device="cuda")
+    fc.fc_critical_value(seg, xt, alphas, crit, 200, 50.0, hist)
+    torch.cuda.synchronize()
+    c_ref, h_ref = oracle.critical_value(x, off, alphas, n_bins=200, hist_hi=50.0)
+    c_dev = crit.cpu().numpy()
+    assert np.isnan(c_dev[1]).all()
+    np.testing.assert_array_equal(c_dev[[0, 2, 3, 4]], c_ref[[0, 2, 3, 4]])
+    np.testing.assert_array_equal(hist.cpu().numpy(), h_ref)
+    assert hist.cpu().numpy()[1].sum() == 0
+
+
+def test_critical_values_edge_distributions(fc):
+    rng = np.random.default_rng(5)
+    parts = [np.arange(1, 2001, dtype=np.float64)[rng.permutation(2000)],
+             np.full(300, 3.5), np.array([7.0]), np.array([np.nan, 1.0, np.nan]),
+             np.array([-0.0, 0.0, 2.0, 60.0, 49.999999]), rng.chisquare(3, size=20000)]
+    x = np.concatenate(parts)
+    off = np.concatenate([[0], np.cumsum([len(p) for p in parts])])
+    alphas = [1e-9, 0.5, 0.6827, 0.9, 0.95, 0.99, 1.0]
+    crit = torch.empty((len(parts), len(alphas)), dtype=torch.float64, device="cuda")
+    hist = torch.empty((len(parts), 51), dtype=torch.int64, device="cuda")
+    fc.fc_critical_value(to_dev(off, torch.int64), to_dev(x, torch.float64), alphas, crit, 50,
+                         50.0, hist)
+    torch.cuda.synchronize()
+    c_ref, h_ref = oracle.critical_value(x, off, alphas, n_bins=50, hist_hi=50.0)
+    c_dev = crit.cpu().numpy()
+    assert np.array_equal(np.isnan(c_dev), np.isnan(c_ref))
+    ok = ~np.isnan(c_ref)
+    np.testing.assert_array_equal(c_dev[ok], c_ref[ok])
+    np.testing.assert_array_equal(hist.cpu().numpy(), h_ref)
+    assert c_dev[0, 3] == math.ceil(0.9 * 2000)
+
+
+# ---------------------------------------------------------------------------
+# full-size configurations: sampled universes against the oracle
+# ---------------------------------------------------------------------------
+def _sample_idx(pr, per_point):
+    idx = []
+    for s in range(len(pr.seg_off) - 1):
+        lo, hi = pr.seg_off[s], pr.seg_off[s + 1]
+        idx += list(range(lo, min(hi, lo + per_point)))
+        if hi - lo > per_point:
+            idx.append(hi - 1)
+    return np.array(idx)
+
+
+def test_full_size_c2_sampled_parity(fc):
+    """The bench workload (G = 10^4, 512000 universes) in one launch."""
+    pr = fcgen.make_problem("c2")
+    g = make_grid(fc, pr, 2)
+    dev = run_scan(fc, g, 2, pr.d, pr.p_idx)
+    parity.check_invariants(dev, pr.G)
+    idx = _sample_idx(pr, 1)
+    ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx])
+    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, 1e-6)
+    print(rep)
+    assert rep["e_rel"] <= 1e-6
+    assert rep["argmin_agree"] >= 0.99
