@@ -41,9 +41,9 @@ int hip_fail(hipError_t e, const char *what)
 void free_forms(fc_grid *g)
 {
     if (g->W64) (void)hipFree(g->W64);
-    if (g->W32) (void)hipFree(g->W32);
+    if (g->R32) (void)hipFree(g->R32);
     g->W64 = nullptr;
-    g->W32 = nullptr;
+    g->R32 = nullptr;
     g->forms = 0;
 }
 
@@ -51,9 +51,8 @@ size_t grid_bytes(const fc_grid *g)
 {
     size_t b = 0;
     b += sizeof(double) * (size_t)g->G * g->N;  // S64
-    b += sizeof(double) * (size_t)g->G * 64;    // S64p
     if (g->W64) b += sizeof(double) * (size_t)g->G * ((size_t)g->N * (g->N + 1) / 2);
-    if (g->W32) b += sizeof(float) * (size_t)g->G * g->ng * 256;
+    if (g->R32) b += sizeof(uint4) * (size_t)g->G * fcx::rec_units(g->ns);
     return b;
 }
 
@@ -109,14 +108,12 @@ int fc_build_grid(fc_grid **out, int32_t D, const int64_t *axis_len, const doubl
     (void)hipGetDevice(&g->device);
 
     hipError_t e;
-    if ((e = hipMalloc(&g->S64, sizeof(double) * (size_t)G * N)) != hipSuccess ||
-        (e = hipMalloc(&g->S64p, sizeof(double) * (size_t)G * 64)) != hipSuccess) {
+    if ((e = hipMalloc(&g->S64, sizeof(double) * (size_t)G * N)) != hipSuccess) {
         fc_grid_destroy(g);
         return hip_fail(e, "fc_build_grid: hipMalloc");
     }
     if ((e = hipMemcpyAsync(g->S64, signal, sizeof(double) * (size_t)G * N, hipMemcpyHostToDevice,
                             stream)) != hipSuccess ||
-        (e = fcx::launch_stage_signal(g->S64, G, N, g->S64p, stream)) != hipSuccess ||
         (e = hipStreamSynchronize(stream)) != hipSuccess) {
         fc_grid_destroy(g);
         return hip_fail(e, "fc_build_grid: upload/stage");
@@ -157,7 +154,7 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
     double *dF = nullptr, *dstat = nullptr;
     unsigned long long *dbad = nullptr;
     double *W64 = nullptr;
-    float *W32 = nullptr;
+    uint4 *R32 = nullptr;
     hipError_t e = hipSuccess;
     auto cleanup = [&]() {
         if (dF) (void)hipFree(dF);
@@ -171,10 +168,11 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
         ((forms & FC_FORM_FP64) &&
          (e = hipMalloc(&W64, sizeof(double) * (size_t)g->G * nt)) != hipSuccess) ||
         ((forms & FC_FORM_FP32) &&
-         (e = hipMalloc(&W32, sizeof(float) * (size_t)g->G * g->ng * 256)) != hipSuccess)) {
+         (e = hipMalloc(&R32, sizeof(uint4) * (size_t)g->G * fcx::rec_units(g->ns))) !=
+             hipSuccess)) {
         cleanup();
         if (W64) (void)hipFree(W64);
-        if (W32) (void)hipFree(W32);
+        if (R32) (void)hipFree(R32);
         return hip_fail(e, "fc_build_covariance: hipMalloc");
     }
     const unsigned long long none = ~0ull;
@@ -186,27 +184,27 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
                              stream)) != hipSuccess) ||
         (e = hipMemcpyAsync(dbad, &none, sizeof(none), hipMemcpyHostToDevice, stream)) !=
             hipSuccess ||
-        (e = fcx::launch_cov_build(g, dF, dstat, stat_mode, forms, W64, W32, dbad, stream)) !=
+        (e = fcx::launch_cov_build(g, dF, dstat, stat_mode, forms, W64, R32, dbad, stream)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(&hbad, dbad, sizeof(hbad), hipMemcpyDeviceToHost, stream)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(stream)) != hipSuccess) {
         cleanup();
         if (W64) (void)hipFree(W64);
-        if (W32) (void)hipFree(W32);
+        if (R32) (void)hipFree(R32);
         return hip_fail(e, "fc_build_covariance: build");
     }
     cleanup();
     if (hbad != none) {
         if (W64) (void)hipFree(W64);
-        if (W32) (void)hipFree(W32);
+        if (R32) (void)hipFree(R32);
         *bad_q = (int64_t)hbad;
         g->bytes = grid_bytes(g);
         return fail(FC_ERR_NOT_PD, "fc_build_covariance: covariance not positive definite at q=%lld",
                     (long long)hbad);
     }
     g->W64 = W64;
-    g->W32 = W32;
+    g->R32 = R32;
     g->forms = forms;
     g->bytes = grid_bytes(g);
     return FC_OK;
@@ -311,7 +309,6 @@ void fc_grid_destroy(fc_grid *g)
     (void)hipDeviceSynchronize();
     free_forms(g);
     if (g->S64) (void)hipFree(g->S64);
-    if (g->S64p) (void)hipFree(g->S64p);
     delete g;
 }
 

@@ -17,19 +17,25 @@
 // v_mfma_f32_16x16x4_f32: A = a 16x4 block of W_q (rows = z index, cols =
 // bins), B = a 4x16 block of R (bins x universes).  Bins are taken four at a
 // time ("k-steps", ns = ceil(N/4)); z rows sixteen at a time ("row blocks",
-// nb = ceil(N/16)).  W_q is lower triangular, so row block b only needs the
-// k-steps s <= 4b+3.  The (s, b) pairs actually needed are enumerated with s
-// outer and b = s/4 .. nb-1 inner; pair t holds, for lane l, the value
-// W_q[16b + l%16][4s + l/16] (the A-operand layout).  Per grid point the pairs
-// are stored lane-major in groups of four:
-//     W32[q][t/4][lane][t%4]           (ng = ceil(npair/4) groups)
-// so that every lane fetches its next four A values with one 16-byte load and
-// a wave reads 1 KB contiguously.
-//
-// The signal is kept in FP64 and also stored per grid point in the lane order
-// of the B operand,
-//     S64p[q][g][s] = S_q[4s+g]   (g = 0..3, s = 0..15, zero past N)
-// so that the residual d - S_q is formed in FP64 and rounded to FP32 once.
+// nb = ceil(ns/4)).  The 16*nb padded rows hold the N real rows shifted down
+// by r0 = 16*nb - 4*ns (a multiple of 4 below 16), so that the padding sits
+// above the first real row and the last row block ends on the last real row.
+// W_q is lower triangular, so row block b only needs the first
+//     cnt(b) = ns - 4*(nb-1-b)
+// k-steps (N = 57: 3+7+11+15 = 36 blocks instead of the full 4*15 = 60).
+// The (s, b) pairs actually needed are enumerated with s outer and b inner;
+// pair t holds, for lane l, the A-operand value
+//     W_q[16b + l%16 - r0][4s + l/16]        (zero outside the triangle)
+// Per grid point the pairs are stored lane-major in groups of four,
+//     W[t/4][lane][t%4]                (ng = ceil(npair/4) groups of 1 KB)
+// so that every lane fetches its next four A values with one 16-byte access
+// and a wave reads 1 KB contiguously.  They are followed by the signal in
+// FP64 in the lane order of the B operand,
+//     Sp[g][s] = S_q[4s+g]             (g = 0..3, s = 0..15, zero past N; 512 B)
+// so that the residual d - S_q is formed in FP64 and rounded to FP32 once,
+// and by zero padding up to a whole number of 4 KB (256 x 16 B) pieces: one
+// grid point's record is rec_units(ns) 16-byte units, which the scan's 256
+// threads copy with the same number of unpredicated loads each.
 // ---------------------------------------------------------------------------
 namespace fcx {
 
@@ -40,12 +46,34 @@ constexpr int kScanColBlocks = 2;  // 16-universe column blocks per wave (32 uni
 __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int n_ksteps(int N) { return ceil_div(N, 4); }
 __host__ __device__ constexpr int n_rowblocks_from_ns(int ns) { return ceil_div(ns, 4); }
-__host__ __device__ constexpr int n_pairs_from_ns(int ns) {
-    int nb = n_rowblocks_from_ns(ns), t = 0;
-    for (int s = 0; s < ns; ++s) t += nb - s / 4;
+__host__ __device__ constexpr int row_shift(int ns) { return 16 * n_rowblocks_from_ns(ns) - 4 * ns; }
+__host__ __device__ constexpr int ksteps_of_block(int ns, int b)
+{
+    return ns - 4 * (n_rowblocks_from_ns(ns) - 1 - b);
+}
+__host__ __device__ constexpr int first_block_of_kstep(int ns, int s)
+{
+    int b = 0;
+    while (ksteps_of_block(ns, b) <= s) ++b;
+    return b;
+}
+__host__ __device__ constexpr int n_pairs_from_ns(int ns)
+{
+    int t = 0;
+    for (int b = 0; b < n_rowblocks_from_ns(ns); ++b) t += ksteps_of_block(ns, b);
     return t;
 }
 __host__ __device__ constexpr int n_groups_from_ns(int ns) { return ceil_div(n_pairs_from_ns(ns), 4); }
+__host__ __device__ constexpr int rec_w_units(int ns) { return n_groups_from_ns(ns) * 64; }
+__host__ __device__ constexpr int rec_units(int ns) { return 256 * ceil_div(rec_w_units(ns) + 32, 256); }
+// Index of pair (s, b) in the fragment order (s outer, b inner).
+__host__ __device__ constexpr int pair_index(int ns, int s, int b)
+{
+    const int nb = n_rowblocks_from_ns(ns);
+    int t = 0;
+    for (int s2 = 0; s2 < s; ++s2) t += nb - first_block_of_kstep(ns, s2);
+    return t + (b - first_block_of_kstep(ns, s));
+}
 
 // Packed lower-triangle index for the FP64 factor.
 __host__ __device__ inline int64_t tri_index(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
@@ -64,11 +92,10 @@ struct fc_grid {
     std::vector<int64_t> axis_len;
     std::vector<double> axis_vals;
     std::vector<double> central;
-    double *S64 = nullptr;   // device [G][N]
-    double *S64p = nullptr;  // device [G][64], see layout above
+    double *S64 = nullptr;  // device [G][N]
     uint32_t forms = 0;
     double *W64 = nullptr;  // device [G][N(N+1)/2], packed lower W_q = L_q^{-1}
-    float *W32 = nullptr;   // device [G][ng][64][4]
+    uint4 *R32 = nullptr;   // device [G][rec_units(ns)] FP32-form records (see above)
     size_t bytes = 0;
     int ns = 0, ng = 0;     // FP32 fragment geometry
 };
@@ -76,9 +103,8 @@ struct fc_grid {
 // ---- launchers (defined in the .hip files) ------------------------------
 namespace fcx {
 
-hipError_t launch_stage_signal(const double *S64, int64_t G, int N, double *S64p, hipStream_t st);
 hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *stat, int stat_mode,
-                            uint32_t forms, double *W64, float *W32, unsigned long long *bad_q,
+                            uint32_t forms, double *W64, uint4 *R32, unsigned long long *bad_q,
                             hipStream_t st);
 hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
                             unsigned long long *keys, double *chi2_p, hipStream_t st);

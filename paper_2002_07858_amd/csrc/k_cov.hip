@@ -19,8 +19,8 @@ constexpr int kLdsStride = kMaxBins + 1;
 
 __global__ __launch_bounds__(64) void k_cov_build(
     const double *__restrict__ S64, const double *__restrict__ F, const double *__restrict__ stat,
-    int N, int64_t G, int stat_mode, uint32_t forms, int ns, int ng, double *__restrict__ W64,
-    float *__restrict__ W32, unsigned long long *__restrict__ bad_q)
+    int N, int64_t G, int stat_mode, uint32_t forms, int ns, double *__restrict__ W64,
+    uint4 *__restrict__ R32, unsigned long long *__restrict__ bad_q)
 {
     __shared__ double A[kMaxBins * kLdsStride];
     __shared__ double Wc[kMaxBins * kLdsStride];
@@ -83,17 +83,19 @@ __global__ __launch_bounds__(64) void k_cov_build(
                 for (int r = c; r < N; ++r) Wq[tri_index(r, c)] = Wc[r * kLdsStride + c];
         }
         if (forms & FC_FORM_FP32) {
-            // pair t = (s, b) in the scan's order; lane i holds W[16b + i%16][4s + i/16]
-            float4 *Wq = reinterpret_cast<float4 *>(W32 + q * (int64_t)ng * 256);
+            // pair t = (s, b) in the scan's order; lane i holds W[16b + i%16 - r0][4s + i/16]
+            const int ru = rec_units(ns), wu = rec_w_units(ns);
+            uint4 *rq = R32 + q * (int64_t)ru;
+            float4 *Wq = reinterpret_cast<float4 *>(rq);
             const int row_in = i & 15, col_in = i >> 4;
+            const int r0 = row_shift(ns);
             float vals[4];
-            int t = 0, slot = 0, gi = 0;
+            int slot = 0, gi = 0;
             for (int s = 0; s < ns; ++s) {
-                for (int b = s / 4; b < nb; ++b) {
-                    const int rr = 16 * b + row_in, cc = 4 * s + col_in;
-                    vals[slot] = (rr < N && cc < N && cc <= rr) ? (float)Wc[rr * kLdsStride + cc]
-                                                                 : 0.0f;
-                    ++t;
+                for (int b = first_block_of_kstep(ns, s); b < nb; ++b) {
+                    const int rr = 16 * b + row_in - r0, cc = 4 * s + col_in;
+                    vals[slot] = (rr >= 0 && rr < N && cc <= rr) ? (float)Wc[rr * kLdsStride + cc]
+                                                                  : 0.0f;
                     if (++slot == 4) {
                         Wq[gi * 64 + i] = make_float4(vals[0], vals[1], vals[2], vals[3]);
                         slot = 0;
@@ -105,19 +107,25 @@ __global__ __launch_bounds__(64) void k_cov_build(
                 for (int z = slot; z < 4; ++z) vals[z] = 0.0f;
                 Wq[gi * 64 + i] = make_float4(vals[0], vals[1], vals[2], vals[3]);
             }
-            (void)t;
+            // signal in B-operand lane order: element g*16 + s = S_q[4s + g]
+            double *Sp = reinterpret_cast<double *>(rq + wu);
+            {
+                const int g4 = i >> 4, s16 = i & 15, k = 4 * s16 + g4;
+                Sp[i] = (k < N) ? Sq[k] : 0.0;
+            }
+            for (int u = wu + 32 + i; u < ru; u += 64) rq[u] = make_uint4(0u, 0u, 0u, 0u);
         }
         __syncthreads();
     }
 }
 
 hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *stat, int stat_mode,
-                            uint32_t forms, double *W64, float *W32, unsigned long long *bad_q,
+                            uint32_t forms, double *W64, uint4 *R32, unsigned long long *bad_q,
                             hipStream_t st)
 {
     const int64_t blocks = g->G < 65536 ? g->G : 65536;
     hipLaunchKernelGGL(k_cov_build, dim3((unsigned)blocks), dim3(64), 0, st, g->S64, F, stat, g->N,
-                       g->G, stat_mode, forms, g->ns, g->ng, W64, W32, bad_q);
+                       g->G, stat_mode, forms, g->ns, W64, R32, bad_q);
     return hipGetLastError();
 }
 

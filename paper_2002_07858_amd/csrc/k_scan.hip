@@ -23,40 +23,51 @@ namespace fcx {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Index of pair (s, b) in the fragment order (s outer, b = s/4 .. nb-1 inner).
-__host__ __device__ constexpr int pair_index(int ns, int s, int b)
-{
-    int nb = n_rowblocks_from_ns(ns), t = 0;
-    for (int s2 = 0; s2 < s; ++s2) t += nb - s2 / 4;
-    return t + (b - s / 4);
-}
-
 __device__ __forceinline__ float pick(const float4 &v, int c)
 {
     return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
 }
 
+// Per grid point the block stages one record in LDS: the W_q fragments (NG
+// groups of 1 KB) followed by S_q in FP64 lane order (512 B).  Records are
+// double-buffered: while the waves contract grid point q from one buffer, the
+// block's 256 threads copy record q+1 into the other with coalesced 16-byte
+// loads, and one barrier per grid point hands the buffers over.
 template <int NS, int NC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32(
-    const float *__restrict__ W32, const double *__restrict__ S64p, const double *__restrict__ d,
+    const uint4 *__restrict__ R32, const double *__restrict__ d,
     const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
     int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
 {
     static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
     constexpr int NB = n_rowblocks_from_ns(NS);
     constexpr int NG = n_groups_from_ns(NS);
-    constexpr int UW = 16 * NC;  // universes per wave
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    constexpr int UW = 16 * NC;            // universes per wave
+    constexpr int NWU = rec_w_units(NS);   // 16-byte units of W per record
+    constexpr int REC = rec_units(NS);     // W + 512 B of S + padding
+    constexpr int THREADS = 64 * kWavesPerBlock;
+    static_assert(REC % THREADS == 0, "records are whole 4 KB pieces");
+    constexpr int CPT = REC / THREADS;     // units copied per thread
+    static_assert(NG * 64 == NWU, "W groups");
+    __shared__ uint4 buf[2][REC];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int64_t utile = blockIdx.x % n_utiles;
     const int64_t qchunk = blockIdx.x / n_utiles;
     const int64_t u0 = utile * (int64_t)(UW * kWavesPerBlock) + wave * UW;
     const int64_t qb = qchunk * q_per_chunk;
     const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
-    if (u0 >= K || qb >= qe) return;  // uniform per wave
+    if (qb >= qe) return;  // uniform per block
     const int grp = lane >> 4, col = lane & 15;
 
-    // B-operand sources in FP64: universe u0+16c+col, bin 4s+grp (zero past N)
+    static_assert(CPT >= 1 && CPT <= 3, "records of at most three 4 KB pieces");
+    // the thread's share of a record, units tid, tid+256, tid+512, held in
+    // named registers (an array here ends up in scratch memory)
+    uint4 st0 = make_uint4(0u, 0u, 0u, 0u), st1 = st0, st2 = st0;
+    // B-operand sources in FP64: universe u0+16c+col, bin 4s+grp (zero past N
+    // and past K; waves past K still take part in the copies and barriers)
     double dv[NC][NS];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -77,32 +88,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     float cp = 0.0f;
     bool have_cp = false;
 
+    {
+        const uint4 *rq = R32 + qb * REC + tid;
+        st0 = rq[0];
+        if constexpr (CPT > 1) st1 = rq[THREADS];
+        if constexpr (CPT > 2) st2 = rq[2 * THREADS];
+        uint4 *bq = &buf[0][tid];
+        bq[0] = st0;
+        if constexpr (CPT > 1) bq[THREADS] = st1;
+        if constexpr (CPT > 2) bq[2 * THREADS] = st2;
+    }
+    __syncthreads();
+    int slot = 0;
     for (int64_t q = qb; q < qe; ++q) {
-        const float4 *wq = reinterpret_cast<const float4 *>(W32 + q * (int64_t)(NG * 256));
-        float4 wv[NG];
-#pragma unroll
-        for (int gi = 0; gi < NG; ++gi) wv[gi] = wq[gi * 64 + lane];
-        const double2 *sq = reinterpret_cast<const double2 *>(S64p + q * 64 + grp * 16);
-        double2 sv2[(NS + 1) / 2];
-#pragma unroll
-        for (int i = 0; i < (NS + 1) / 2; ++i) sv2[i] = sq[i];
+        const bool more = q + 1 < qe;
+        if (more) {
+            const uint4 *rq = R32 + (q + 1) * REC + tid;
+            st0 = rq[0];
+            if constexpr (CPT > 1) st1 = rq[THREADS];
+            if constexpr (CPT > 2) st2 = rq[2 * THREADS];
+        }
 
+        const float4 *wl = reinterpret_cast<const float4 *>(&buf[slot][0]);
+        const double2 *sl = reinterpret_cast<const double2 *>(&buf[slot][NWU]) + grp * 8;
         v4f acc[NC][NB];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
             for (int b = 0; b < NB; ++b) acc[c][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
+        float4 wv = wl[lane];
+        int wg_loaded = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const double sval = (s & 1) ? sv2[s >> 1].y : sv2[s >> 1].x;
+            const double2 s2 = sl[s >> 1];
+            const double sval = (s & 1) ? s2.y : s2.x;
             float r[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) r[c] = (float)(dv[c][s] - sval);  // one rounding
 #pragma unroll
-            for (int b = s / 4; b < NB; ++b) {
+            for (int b = first_block_of_kstep(NS, s); b < NB; ++b) {
                 const int t = pair_index(NS, s, b);
-                const float w = pick(wv[t >> 2], t & 3);
+                if ((t >> 2) != wg_loaded) {
+                    wg_loaded = t >> 2;
+                    wv = wl[wg_loaded * 64 + lane];
+                }
+                const float w = pick(wv, t & 3);
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
                     acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, r[c], acc[c][b], 0, 0, 0);
@@ -155,6 +186,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             best = chi2;
             qbest = (uint32_t)q;
         }
+
+        if (more) {
+            uint4 *bq = &buf[slot ^ 1][tid];
+            bq[0] = st0;
+            if constexpr (CPT > 1) bq[THREADS] = st1;
+            if constexpr (CPT > 2) bq[2 * THREADS] = st2;
+        }
+        __syncthreads();
+        slot ^= 1;
     }
 
     if (owner && u_own < K) {
@@ -306,8 +346,8 @@ static hipError_t launch_fp32_ns(const fc_grid *g, int64_t K, const double *d, c
     const ScanGeometry sg = scan_geometry(K, g->G, slots, 16 * NC * kWavesPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     hipLaunchKernelGGL((k_scan_fp32<NS, NC>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
-                       st, g->W32, g->S64p, d, p_idx, K, g->N, g->G, sg.n_utiles, sg.q_per_chunk,
-                       keys, chi2_p);
+                       st, g->R32, d, p_idx, K, g->N, g->G, sg.n_utiles, sg.q_per_chunk, keys,
+                       chi2_p);
     return hipGetLastError();
 }
 
