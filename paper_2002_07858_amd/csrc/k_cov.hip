@@ -107,11 +107,15 @@ __global__ __launch_bounds__(64) void k_cov_build(
                 for (int z = slot; z < 4; ++z) vals[z] = 0.0f;
                 Wq[gi * 64 + i] = make_float4(vals[0], vals[1], vals[2], vals[3]);
             }
-            // signal in B-operand lane order: element g*16 + s = S_q[4s + g]
-            double *Sp = reinterpret_cast<double *>(rq + wu);
+            // signal as an FP32 pair in B-operand lane order: element g*16 + s
+            // holds S_q[4s + g]
+            float *Sp = reinterpret_cast<float *>(rq + wu);
             {
                 const int g4 = i >> 4, s16 = i & 15, k = 4 * s16 + g4;
-                Sp[i] = (k < N) ? Sq[k] : 0.0;
+                const double sv = (k < N) ? Sq[k] : 0.0;
+                const float hi = (float)sv;
+                Sp[i] = hi;
+                Sp[64 + i] = (float)(sv - (double)hi);
             }
             for (int u = wu + 32 + i; u < ru; u += 64) rq[u] = make_uint4(0u, 0u, 0u, 0u);
         }

@@ -6,8 +6,10 @@
 // universes this is a dense contraction Z = W_q R (R = bins x universes),
 // done on the matrix cores with v_mfma_f32_16x16x4_f32 over the lower-
 // triangular block pattern of W_q only, followed by a column-wise sum of
-// squares (FP64), a reduce-scatter across the four 16-lane groups and a
-// strict-"<" running minimum per universe.
+// squares, a reduction across the four 16-lane groups and a strict-"<"
+// running minimum per universe.  The FP32 MFMA shares issue with the vector
+// ALU on this chip, so the vector work around it (residuals, squares) is
+// kept to FP32 instructions: FP64 ones cost twice as much.
 //
 // Work decomposition: a block of 4 waves owns 256 universes; each wave owns
 // 64 universes and walks one contiguous chunk of grid points in list order.
@@ -66,16 +68,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     // the thread's share of a record, units tid, tid+256, tid+512, held in
     // named registers (an array here ends up in scratch memory)
     uint4 st0 = make_uint4(0u, 0u, 0u, 0u), st1 = st0, st2 = st0;
-    // B-operand sources in FP64: universe u0+16c+col, bin 4s+grp (zero past N
-    // and past K; waves past K still take part in the copies and barriers)
-    double dv[NC][NS];
+    // B-operand sources as FP32 pairs d = dh + dl: universe u0+16c+col, bin
+    // 4s+grp (zero past N and past K; waves past K still take part in the
+    // copies and barriers)
+    float dh[NC][NS], dl[NC][NS];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const int64_t u = u0 + 16 * c + col;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int k = 4 * s + grp;
-            dv[c][s] = (u < K && k < N) ? d[u * N + k] : 0.0;
+            const double v = (u < K && k < N) ? d[u * N + k] : 0.0;
+            dh[c][s] = (float)v;
+            dl[c][s] = (float)(v - (double)dh[c][s]);
         }
     }
     // after the reduction, lane l holds column block cl of universe column col
@@ -110,7 +115,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
 
         const float4 *wl = reinterpret_cast<const float4 *>(&buf[slot][0]);
-        const double2 *sl = reinterpret_cast<const double2 *>(&buf[slot][NWU]) + grp * 8;
+        const float *shl = reinterpret_cast<const float *>(&buf[slot][NWU]) + grp * 16;
         v4f acc[NC][NB];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
@@ -121,11 +126,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         int wg_loaded = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const double2 s2 = sl[s >> 1];
-            const double sval = (s & 1) ? s2.y : s2.x;
+            const float sh = shl[s], sl = shl[64 + s];
             float r[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) r[c] = (float)(dv[c][s] - sval);  // one rounding
+            for (int c = 0; c < NC; ++c) r[c] = (dh[c][s] - sh) + (dl[c][s] - sl);
 #pragma unroll
             for (int b = first_block_of_kstep(NS, s); b < NB; ++b) {
                 const int t = pair_index(NS, s, b);
@@ -140,43 +144,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
         }
 
-        // sum of squares per universe column, in FP64
-        double part[NC];
+        // sum of squares per universe column: FP32 chains of the 4 rows a lane
+        // holds per row block, a pairwise tree over the blocks, then the four
+        // lane groups (FP32 instructions only)
+        float part[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            double a = 0.0;
+            float blk[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
+            for (int b = 0; b < NB; ++b) {
+                float a = acc[c][b][0] * acc[c][b][0];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const double z = (double)acc[c][b][j];
-                    a = fma(z, z, a);
-                }
-            part[c] = a;
+                for (int j = 1; j < 4; ++j) a = fmaf(acc[c][b][j], acc[c][b][j], a);
+                blk[b] = a;
+            }
+            if constexpr (NB == 4)
+                part[c] = (blk[0] + blk[1]) + (blk[2] + blk[3]);
+            else if constexpr (NB == 3)
+                part[c] = (blk[0] + blk[1]) + blk[2];
+            else if constexpr (NB == 2)
+                part[c] = blk[0] + blk[1];
+            else
+                part[c] = blk[0];
         }
-        // reduce over the four lane groups (each holds 4 of every 16 z rows)
         const bool hi = lane >= 32;
-        double kk;
+        float kk;
         if constexpr (NC == 4) {
             // reduce-scatter: lane l ends with column block l/16
-            double k0 = hi ? part[2] : part[0];
-            double k1 = hi ? part[3] : part[1];
-            const double s0 = hi ? part[0] : part[2];
-            const double s1 = hi ? part[1] : part[3];
+            float k0 = hi ? part[2] : part[0];
+            float k1 = hi ? part[3] : part[1];
+            const float s0 = hi ? part[0] : part[2];
+            const float s1 = hi ? part[1] : part[3];
             k0 += __shfl_xor(s0, 32);
             k1 += __shfl_xor(s1, 32);
             const bool odd = grp & 1;
             kk = odd ? k1 : k0;
-            const double ss = odd ? k0 : k1;
+            const float ss = odd ? k0 : k1;
             kk += __shfl_xor(ss, 16);
         } else {
             // lanes < 32 keep block 0, lanes >= 32 block 1; then pair groups
             kk = hi ? part[1] : part[0];
-            const double s0 = hi ? part[0] : part[1];
+            const float s0 = hi ? part[0] : part[1];
             kk += __shfl_xor(s0, 32);
             kk += __shfl_xor(kk, 16);
         }
-        const float chi2 = (float)kk;
+        const float chi2 = kk;
 
         if (q == p_own) {
             cp = chi2;
