@@ -28,7 +28,9 @@ if ROOT not in sys.path:
 
 METRIC = ("universe×gridpoint χ² evals/s at max|Δχ²| err vs FP64; "
           "FC request p50/p99 latency")
-PEAK = {"fp32": 157.3e12, "fp64": 78.6e12}
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "split_bf16": 2500e12, "split_fp16": 2500e12}
+DTYPE = {"fp32": "f32", "fp64": "f64", "split_bf16": "bf16x2+f32acc", "split_fp16": "f16x2+f32acc"}
+TOL = {"fp32": 1e-6, "fp64": 1e-11, "split_bf16": 1e-4, "split_fp16": 1e-4}
 ALPHA = (0.6827, 0.9, 0.95)
 N_BINS, HIST_HI = 200, 50.0
 
@@ -39,11 +41,17 @@ def flop_per_eval(N: int) -> int:
     return N * N + 4 * N
 
 
+def split_flop_per_eval(N: int) -> int:
+    # split forms: three 16-bit products (hi*hi, hi*lo, lo*hi) per multiply-add
+    # of the triangular W r, on the 16-bit matrix cores
+    return 3 * N * (N + 1)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pr, per_point: int, dev_out: dict):
+def cpu_baseline(pr, per_point: int, dev_out: dict, tol: float):
     """Time the FP64 oracle on a bounded sample and measure the device error on it."""
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -58,7 +66,7 @@ def cpu_baseline(pr, per_point: int, dev_out: dict):
     ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx], nthreads=nt)
     dt = time.perf_counter() - t0
     evals = len(idx) * pr.G
-    rep = parity.report({k: v[idx] for k, v in dev_out.items()}, ref, 1e-6)
+    rep = parity.report({k: v[idx] for k, v in dev_out.items()}, ref, tol)
     base = {"value": evals / dt, "unit": "evals/s", "cores": nt, "kind": "oracle",
             "sample": f"first {per_point} universes of each of the {len(pr.seg_off) - 1} true "
                       f"points x all {pr.G} grid points ({evals:.3g} evals, {dt:.1f} s, "
@@ -71,7 +79,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--form", default="fp32", choices=["fp32", "fp64", "split_bf16", "split_fp16"])
     ap.add_argument("--cpu-per-point", type=int, default=100,
                     help="universes per true point in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -88,7 +96,8 @@ def main():
 
     torch.cuda.set_device(0)
     fc.lib()
-    form = {"fp32": fc.FC_FORM_FP32, "fp64": fc.FC_FORM_FP64}[args.form]
+    form = {"fp32": fc.FC_FORM_FP32, "fp64": fc.FC_FORM_FP64, "split_bf16": fc.FC_FORM_SPLIT_BF16,
+            "split_fp16": fc.FC_FORM_SPLIT_FP16}[args.form]
 
     log("[bench] generating c2 inputs")
     pr = fcgen.make_problem("c2")
@@ -143,17 +152,22 @@ def main():
     value = evals * args.steps / wall
     scan_ms = float(np.mean(times["scan"]))
     fpe = flop_per_eval(N)
-    achieved = evals * fpe / (scan_ms * 1e-3)
+    split = args.form.startswith("split")
+    achieved = evals * (split_flop_per_eval(N) if split else fpe) / (scan_ms * 1e-3)
     peak = PEAK[args.form]
-    roofline = {"bound": "mfma" if args.form == "fp32" else "alu", "achieved": achieved / 1e12,
+    roofline = {"bound": "alu" if args.form == "fp64" else "mfma", "achieved": achieved / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None}
+    if split:
+        fp32_equiv = evals * fpe / (scan_ms * 1e-3)
+        roofline["fp32_equivalent"] = {"achieved": fp32_equiv / 1e12, "peak": PEAK["fp32"] / 1e12,
+                                       "frac": fp32_equiv / PEAK["fp32"]}
 
     dev_out = {k: v.cpu().numpy() for k, v in outs.items()}
     res = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"fp32": "f32", "fp64": "f64"}[args.form], "data": "synthetic",
+           "dtype": DTYPE[args.form], "data": "synthetic",
            "config": {"workload": "c2: D=2 grid 100x100 (G=10000), N=57, 256 true points x "
                                   "2000 universes, per-point FP64 covariance factor, "
                                   f"{args.form} scan, crit at 0.6827/0.9/0.95 + 200-bin hist",
@@ -164,7 +178,7 @@ def main():
            "roofline": roofline}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
-        base, rep = cpu_baseline(pr, args.cpu_per_point, dev_out)
+        base, rep = cpu_baseline(pr, args.cpu_per_point, dev_out, TOL[args.form])
         res["cpu_baseline"] = base
         res["err_vs_fp64"] = rep
     grid.destroy()

@@ -42,9 +42,18 @@ void free_forms(fc_grid *g)
 {
     if (g->W64) (void)hipFree(g->W64);
     if (g->R32) (void)hipFree(g->R32);
+    if (g->RB16) (void)hipFree(g->RB16);
+    if (g->RH16) (void)hipFree(g->RH16);
     g->W64 = nullptr;
     g->R32 = nullptr;
+    g->RB16 = nullptr;
+    g->RH16 = nullptr;
     g->forms = 0;
+}
+
+size_t split_record_bytes(const fc_grid *g)
+{
+    return sizeof(uint4) * (size_t)fcx::split_rec_units(fcx::split_nk(g->N), fcx::split_nb(g->N));
 }
 
 size_t grid_bytes(const fc_grid *g)
@@ -52,7 +61,10 @@ size_t grid_bytes(const fc_grid *g)
     size_t b = 0;
     b += sizeof(double) * (size_t)g->G * g->N;  // S64
     if (g->W64) b += sizeof(double) * (size_t)g->G * ((size_t)g->N * (g->N + 1) / 2);
+    b += sizeof(double) * 128;                  // off, dev
     if (g->R32) b += sizeof(uint4) * (size_t)g->G * fcx::rec_units(g->ns);
+    if (g->RB16) b += (size_t)g->G * split_record_bytes(g);
+    if (g->RH16) b += (size_t)g->G * split_record_bytes(g);
     return b;
 }
 
@@ -108,16 +120,26 @@ int fc_build_grid(fc_grid **out, int32_t D, const int64_t *axis_len, const doubl
     (void)hipGetDevice(&g->device);
 
     hipError_t e;
-    if ((e = hipMalloc(&g->S64, sizeof(double) * (size_t)G * N)) != hipSuccess) {
+    if ((e = hipMalloc(&g->S64, sizeof(double) * (size_t)G * N)) != hipSuccess ||
+        (e = hipMalloc(&g->off, sizeof(double) * 64)) != hipSuccess ||
+        (e = hipMalloc(&g->dev, sizeof(double) * 64)) != hipSuccess) {
         fc_grid_destroy(g);
         return hip_fail(e, "fc_build_grid: hipMalloc");
     }
+    double hdev[64];
     if ((e = hipMemcpyAsync(g->S64, signal, sizeof(double) * (size_t)G * N, hipMemcpyHostToDevice,
                             stream)) != hipSuccess ||
+        (e = fcx::launch_offset(g->S64, G, N, g->off, g->dev, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(hdev, g->dev, sizeof(hdev), hipMemcpyDeviceToHost, stream)) !=
+            hipSuccess ||
         (e = hipStreamSynchronize(stream)) != hipSuccess) {
         fc_grid_destroy(g);
         return hip_fail(e, "fc_build_grid: upload/stage");
     }
+    // split-FP16 range: 2^ed16 max|S - o| < 2^13
+    double dmax = 0.0;
+    for (int j = 0; j < N; ++j) dmax = fmax(dmax, hdev[j]);
+    g->ed16 = (dmax > 0.0) ? 12 - ilogb(dmax) : 0;
     g->bytes = grid_bytes(g);
     *out = g;
     return FC_OK;
@@ -138,8 +160,6 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
     const uint32_t known = FC_FORM_FP64 | FC_FORM_FP32 | FC_FORM_SPLIT_BF16 | FC_FORM_SPLIT_FP16;
     if (forms == 0 || (forms & ~known))
         return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: bad forms mask 0x%x", forms);
-    if (forms & (FC_FORM_SPLIT_BF16 | FC_FORM_SPLIT_FP16))
-        return fail(FC_ERR_UNSUPPORTED, "fc_build_covariance: split forms are not built yet");
     const int N = g->N;
     if (!finite_all(frac_cov, (size_t)N * N))
         return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: frac_cov has a non-finite entry");
@@ -154,7 +174,7 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
     double *dF = nullptr, *dstat = nullptr;
     unsigned long long *dbad = nullptr;
     double *W64 = nullptr;
-    uint4 *R32 = nullptr;
+    uint4 *R32 = nullptr, *RB16 = nullptr, *RH16 = nullptr;
     hipError_t e = hipSuccess;
     auto cleanup = [&]() {
         if (dF) (void)hipFree(dF);
@@ -169,10 +189,16 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
          (e = hipMalloc(&W64, sizeof(double) * (size_t)g->G * nt)) != hipSuccess) ||
         ((forms & FC_FORM_FP32) &&
          (e = hipMalloc(&R32, sizeof(uint4) * (size_t)g->G * fcx::rec_units(g->ns))) !=
-             hipSuccess)) {
+             hipSuccess) ||
+        ((forms & FC_FORM_SPLIT_BF16) &&
+         (e = hipMalloc(&RB16, (size_t)g->G * split_record_bytes(g))) != hipSuccess) ||
+        ((forms & FC_FORM_SPLIT_FP16) &&
+         (e = hipMalloc(&RH16, (size_t)g->G * split_record_bytes(g))) != hipSuccess)) {
         cleanup();
         if (W64) (void)hipFree(W64);
         if (R32) (void)hipFree(R32);
+        if (RB16) (void)hipFree(RB16);
+        if (RH16) (void)hipFree(RH16);
         return hip_fail(e, "fc_build_covariance: hipMalloc");
     }
     const unsigned long long none = ~0ull;
@@ -184,7 +210,8 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
                              stream)) != hipSuccess) ||
         (e = hipMemcpyAsync(dbad, &none, sizeof(none), hipMemcpyHostToDevice, stream)) !=
             hipSuccess ||
-        (e = fcx::launch_cov_build(g, dF, dstat, stat_mode, forms, W64, R32, dbad, stream)) !=
+        (e = fcx::launch_cov_build(g, dF, dstat, stat_mode, forms, W64, R32, RB16, RH16, dbad,
+                                   stream)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(&hbad, dbad, sizeof(hbad), hipMemcpyDeviceToHost, stream)) !=
             hipSuccess ||
@@ -192,12 +219,16 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
         cleanup();
         if (W64) (void)hipFree(W64);
         if (R32) (void)hipFree(R32);
+        if (RB16) (void)hipFree(RB16);
+        if (RH16) (void)hipFree(RH16);
         return hip_fail(e, "fc_build_covariance: build");
     }
     cleanup();
     if (hbad != none) {
         if (W64) (void)hipFree(W64);
         if (R32) (void)hipFree(R32);
+        if (RB16) (void)hipFree(RB16);
+        if (RH16) (void)hipFree(RH16);
         *bad_q = (int64_t)hbad;
         g->bytes = grid_bytes(g);
         return fail(FC_ERR_NOT_PD, "fc_build_covariance: covariance not positive definite at q=%lld",
@@ -205,6 +236,8 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
     }
     g->W64 = W64;
     g->R32 = R32;
+    g->RB16 = RB16;
+    g->RH16 = RH16;
     g->forms = forms;
     g->bytes = grid_bytes(g);
     return FC_OK;
@@ -240,6 +273,16 @@ int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d, const in
             (e = fcx::launch_finalize(K, p_idx, keys, argmin, chi2_p, dchi2, stream)) !=
                 hipSuccess)
             return hip_fail(e, "fc_scan: fp32 launch");
+        return FC_OK;
+    }
+    if (form == FC_FORM_SPLIT_BF16 || form == FC_FORM_SPLIT_FP16) {
+        unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
+        if ((e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
+            (e = fcx::launch_scan_split(g, form == FC_FORM_SPLIT_FP16, K, d, p_idx, keys, chi2_p,
+                                        stream)) != hipSuccess ||
+            (e = fcx::launch_finalize(K, p_idx, keys, argmin, chi2_p, dchi2, stream)) !=
+                hipSuccess)
+            return hip_fail(e, "fc_scan: split launch");
         return FC_OK;
     }
     return fail(FC_ERR_UNSUPPORTED, "fc_scan: form %d not implemented", form);
@@ -309,6 +352,8 @@ void fc_grid_destroy(fc_grid *g)
     (void)hipDeviceSynchronize();
     free_forms(g);
     if (g->S64) (void)hipFree(g->S64);
+    if (g->off) (void)hipFree(g->off);
+    if (g->dev) (void)hipFree(g->dev);
     delete g;
 }
 

@@ -78,6 +78,51 @@ __host__ __device__ constexpr int pair_index(int ns, int s, int b)
     return t + (b - first_block_of_kstep(ns, s));
 }
 
+// ---------------------------------------------------------------------------
+// Split-form layout (hi+lo BF16 or FP16 operands, FP32 accumulation) for
+// v_mfma_f32_16x16x32_{bf16,f16}: A = 16x32 tiles of the factor, B = 32x16
+// tiles of the universes.  The split forms use linearity,
+//     z = W_q (d - S_q) = W_q (d - o) - W_q (S_q - o),
+// so that the universes are split once (registers, for the whole scan) and
+// u_q = W_q (S_q - o) is computed per grid point in FP64 when the form is
+// built; o is a per-bin offset (the grid mean of S).  Bins are taken 32 at a
+// time (nk = ceil(N/32) k-steps), rows 16 at a time (nb = ceil(N/16)); row
+// block b needs the first cnt(b) = min(nk, b/2 + 1) k-steps.  Pairs (s, b)
+// run s outer, b = 2s .. nb-1 inner.  Lane l of pair (s, b) holds the eight
+// A-operand values W_q[16b + l%16][32s + 8(l/16) + e], e = 0..7, scaled by
+// 2^eq (FP16 form) and split hi + lo.  Record of one grid point (16 B units):
+//     [pair][hi | lo][lane]           npair * 128 units
+//     c[g][b][j] FP32, -2^(eq+ed) * u_q[16b + 4g + j]           16 units
+//     {2^-2(eq+ed), 0, 0, 0}                                       1 unit
+//     zero padding to a whole number of 256 units
+// c is the initial accumulator of every row block, so that the MFMA chain
+// ends at 2^(eq+ed) z and chi^2 = 2^-2(eq+ed) sum z'^2.  eq is chosen per grid
+// point so that max |W_q| 2^eq lies in [2^13, 2^14); ed per grid so that
+// max |S - o| 2^ed is below 2^13 (both 0 for BF16, whose range is FP32's).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int split_nk(int N) { return ceil_div(N, 32); }
+__host__ __device__ constexpr int split_nb(int N) { return ceil_div(N, 16); }
+__host__ __device__ constexpr int split_cnt(int nk, int b) { return (b / 2 + 1 < nk) ? b / 2 + 1 : nk; }
+__host__ __device__ constexpr int split_npairs(int nk, int nb)
+{
+    int t = 0;
+    for (int b = 0; b < nb; ++b) t += split_cnt(nk, b);
+    return t;
+}
+__host__ __device__ constexpr int split_pair_index(int nk, int nb, int s, int b)
+{
+    int t = 0;
+    for (int s2 = 0; s2 < s; ++s2) t += nb - 2 * s2;
+    (void)nk;
+    return t + (b - 2 * s);
+}
+__host__ __device__ constexpr int split_u_unit(int nk, int nb) { return split_npairs(nk, nb) * 128; }
+__host__ __device__ constexpr int split_scale_unit(int nk, int nb) { return split_u_unit(nk, nb) + 16; }
+__host__ __device__ constexpr int split_rec_units(int nk, int nb)
+{
+    return 256 * ceil_div(split_scale_unit(nk, nb) + 1, 256);
+}
+
 // Packed lower-triangle index for the FP64 factor.
 __host__ __device__ inline int64_t tri_index(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
 
@@ -99,6 +144,11 @@ struct fc_grid {
     uint32_t forms = 0;
     double *W64 = nullptr;  // device [G][N(N+1)/2], packed lower W_q = L_q^{-1}
     uint4 *R32 = nullptr;   // device [G][rec_units(ns)] FP32-form records (see above)
+    uint4 *RB16 = nullptr;  // device [G][split_rec_units] split-BF16 records
+    uint4 *RH16 = nullptr;  // device [G][split_rec_units] split-FP16 records
+    double *off = nullptr;  // device [64] per-bin offset o (grid mean of S), zero past N
+    double *dev = nullptr;  // device [64] per-bin max |S - o|
+    int ed16 = 0;           // power-of-two scale of (d - o) in the split-FP16 form
     size_t bytes = 0;
     int ns = 0, ng = 0;     // FP32 fragment geometry
 };
@@ -106,9 +156,14 @@ struct fc_grid {
 // ---- launchers (defined in the .hip files) ------------------------------
 namespace fcx {
 
+hipError_t launch_offset(const double *S64, int64_t G, int N, double *off, double *dev,
+                         hipStream_t st);
 hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *stat, int stat_mode,
-                            uint32_t forms, double *W64, uint4 *R32, unsigned long long *bad_q,
-                            hipStream_t st);
+                            uint32_t forms, double *W64, uint4 *R32, uint4 *RB16, uint4 *RH16,
+                            unsigned long long *bad_q, hipStream_t st);
+hipError_t launch_scan_split(const fc_grid *g, bool fp16, int64_t K, const double *d,
+                             const int64_t *p_idx, unsigned long long *keys, double *chi2_p,
+                             hipStream_t st);
 hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
                             unsigned long long *keys, double *chi2_p, hipStream_t st);
 hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,

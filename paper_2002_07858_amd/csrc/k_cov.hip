@@ -17,10 +17,84 @@ namespace fcx {
 
 constexpr int kLdsStride = kMaxBins + 1;
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// hi + lo split of eight FP32 values into two 16-byte fragments (round to
+// nearest even for both halves).
+template <bool FP16>
+__device__ inline void split8(const float (&x)[8], uint4 &hi, uint4 &lo)
+{
+    if constexpr (FP16) {
+        f16x8 h, l;
+        for (int e = 0; e < 8; ++e) {
+            h[e] = (_Float16)x[e];
+            l[e] = (_Float16)(x[e] - (float)h[e]);
+        }
+        hi = __builtin_bit_cast(uint4, h);
+        lo = __builtin_bit_cast(uint4, l);
+    } else {
+        bf16x8 h, l;
+        for (int e = 0; e < 8; ++e) {
+            h[e] = (__bf16)x[e];
+            l[e] = (__bf16)(x[e] - (float)h[e]);
+        }
+        hi = __builtin_bit_cast(uint4, h);
+        lo = __builtin_bit_cast(uint4, l);
+    }
+}
+
+// One split-form record (see fc_internal.h) from the FP64 factor in LDS.
+template <bool FP16>
+__device__ void write_split_record(const double *Wc, const double *Sq, const double *off, int N,
+                                   int ed, uint4 *rq)
+{
+    const int i = threadIdx.x;
+    const int nk = split_nk(N), nb = split_nb(N);
+    // per-point power-of-two scale of the factor (FP16 range)
+    int eq = 0;
+    if constexpr (FP16) {
+        double wm = 0.0;
+        if (i < N)
+            for (int r = i; r < N; ++r) wm = fmax(wm, fabs(Wc[r * kLdsStride + i]));
+        for (int m = 32; m > 0; m >>= 1) wm = fmax(wm, __shfl_xor(wm, m));
+        eq = (wm > 0.0) ? 13 - ilogb(wm) : 0;
+    }
+    // fragments of every (k-step, row block) pair
+    for (int s = 0; s < nk; ++s) {
+        for (int b = 2 * s; b < nb; ++b) {
+            const int t = split_pair_index(nk, nb, s, b);
+            const int rr = 16 * b + (i & 15), c0 = 32 * s + 8 * (i >> 4);
+            float x[8];
+            for (int e = 0; e < 8; ++e) {
+                const int cc = c0 + e;
+                x[e] = (rr < N && cc <= rr) ? (float)ldexp(Wc[rr * kLdsStride + cc], eq) : 0.0f;
+            }
+            uint4 hi, lo;
+            split8<FP16>(x, hi, lo);
+            rq[t * 128 + i] = hi;
+            rq[t * 128 + 64 + i] = lo;
+        }
+    }
+    // u_q = W_q (S_q - o) in FP64, in the accumulator's row order [g][b][j]
+    {
+        const int g = i >> 4, b = (i >> 2) & 3, j = i & 3;
+        const int row = 16 * b + 4 * g + j;
+        double u = 0.0;
+        if (row < N)
+            for (int k = 0; k <= row; ++k) u += Wc[row * kLdsStride + k] * (Sq[k] - off[k]);
+        reinterpret_cast<float *>(rq + split_u_unit(nk, nb))[i] = (float)ldexp(-u, eq + ed);
+    }
+    const int su = split_scale_unit(nk, nb), ru = split_rec_units(nk, nb);
+    if (i == 0) rq[su] = make_uint4(__float_as_uint(ldexpf(1.0f, -2 * (eq + ed))), 0u, 0u, 0u);
+    for (int u = su + 1 + i; u < ru; u += 64) rq[u] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 __global__ __launch_bounds__(64) void k_cov_build(
     const double *__restrict__ S64, const double *__restrict__ F, const double *__restrict__ stat,
-    int N, int64_t G, int stat_mode, uint32_t forms, int ns, double *__restrict__ W64,
-    uint4 *__restrict__ R32, unsigned long long *__restrict__ bad_q)
+    const double *__restrict__ off, int N, int64_t G, int stat_mode, uint32_t forms, int ns,
+    int ed16, double *__restrict__ W64, uint4 *__restrict__ R32, uint4 *__restrict__ RB16,
+    uint4 *__restrict__ RH16, unsigned long long *__restrict__ bad_q)
 {
     __shared__ double A[kMaxBins * kLdsStride];
     __shared__ double Wc[kMaxBins * kLdsStride];
@@ -119,17 +193,25 @@ __global__ __launch_bounds__(64) void k_cov_build(
             }
             for (int u = wu + 32 + i; u < ru; u += 64) rq[u] = make_uint4(0u, 0u, 0u, 0u);
         }
+        if (forms & (FC_FORM_SPLIT_BF16 | FC_FORM_SPLIT_FP16)) {
+            const int64_t sru = split_rec_units(split_nk(N), split_nb(N));
+            if (forms & FC_FORM_SPLIT_BF16)
+                write_split_record<false>(Wc, Sq, off, N, 0, RB16 + q * sru);
+            if (forms & FC_FORM_SPLIT_FP16)
+                write_split_record<true>(Wc, Sq, off, N, ed16, RH16 + q * sru);
+        }
         __syncthreads();
     }
 }
 
 hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *stat, int stat_mode,
-                            uint32_t forms, double *W64, uint4 *R32, unsigned long long *bad_q,
-                            hipStream_t st)
+                            uint32_t forms, double *W64, uint4 *R32, uint4 *RB16, uint4 *RH16,
+                            unsigned long long *bad_q, hipStream_t st)
 {
     const int64_t blocks = g->G < 65536 ? g->G : 65536;
-    hipLaunchKernelGGL(k_cov_build, dim3((unsigned)blocks), dim3(64), 0, st, g->S64, F, stat, g->N,
-                       g->G, stat_mode, forms, g->ns, W64, R32, bad_q);
+    hipLaunchKernelGGL(k_cov_build, dim3((unsigned)blocks), dim3(64), 0, st, g->S64, F, stat,
+                       g->off, g->N, g->G, stat_mode, forms, g->ns, g->ed16, W64, R32, RB16, RH16,
+                       bad_q);
     return hipGetLastError();
 }
 

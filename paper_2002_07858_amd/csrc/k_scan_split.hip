@@ -1,0 +1,292 @@
+// k_scan_split.hip -- the chi^2 scan in the split-precision forms.
+//
+// Same statistic as the FP32 form (Eq. (1) in factor form inside Algorithm
+// 1's loops), evaluated on the 16-bit matrix cores: every FP32 operand is
+// written as hi + lo (BF16 or FP16) and a product as hi*hi + hi*lo + lo*hi,
+// accumulated in FP32 by v_mfma_f32_16x16x32_{bf16,f16}.  By linearity
+//     2^(eq+ed) z = [2^eq W_q] [2^ed (d - o)] - 2^(eq+ed) W_q (S_q - o),
+// the universes 2^ed (d - o) are split once into registers and the per-point
+// vector -2^(eq+ed) u_q, u_q = W_q (S_q - o), comes precomputed (FP64) with
+// the record as the accumulators' initial value, so the loop over grid points
+// does no per-universe residual work: MFMAs, then one square per z value and
+// one power-of-two rescale per universe.
+//
+// Work decomposition as in the FP32 form: a 256-thread block owns 4 waves x
+// 16*NC universes and walks a chunk of grid points, double-buffering one
+// record per point in LDS; chunks merge through the packed-key atomicMin.
+#include "fc_internal.h"
+
+namespace fcx {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <bool FP16>
+__device__ __forceinline__ v4f mfma16x16x32(const uint4 &a, const uint4 &b, const v4f &c)
+{
+    if constexpr (FP16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+template <bool FP16>
+__device__ __forceinline__ void split8(const float (&x)[8], uint4 &hi, uint4 &lo)
+{
+    if constexpr (FP16) {
+        f16x8 h, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            h[e] = (_Float16)x[e];
+            l[e] = (_Float16)(x[e] - (float)h[e]);
+        }
+        hi = __builtin_bit_cast(uint4, h);
+        lo = __builtin_bit_cast(uint4, l);
+    } else {
+        bf16x8 h, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            h[e] = (__bf16)x[e];
+            l[e] = (__bf16)(x[e] - (float)h[e]);
+        }
+        hi = __builtin_bit_cast(uint4, h);
+        lo = __builtin_bit_cast(uint4, l);
+    }
+}
+
+template <int NK, int NB, int NC, bool FP16>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_split(
+    const uint4 *__restrict__ R16, const double *__restrict__ d, const double *__restrict__ off,
+    int ed, const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
+    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
+{
+    static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
+    constexpr int UW = 16 * NC;
+    constexpr int REC = split_rec_units(NK, NB);
+    constexpr int UU = split_u_unit(NK, NB);
+    constexpr int SU = split_scale_unit(NK, NB);
+    constexpr int THREADS = 64 * kWavesPerBlock;
+    static_assert(REC % THREADS == 0, "records are whole 4 KB pieces");
+    constexpr int CPT = REC / THREADS;
+    static_assert(CPT >= 1 && CPT <= 4, "records of at most four 4 KB pieces");
+    __shared__ uint4 buf[2][REC];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t utile = blockIdx.x % n_utiles;
+    const int64_t qchunk = blockIdx.x / n_utiles;
+    const int64_t u0 = utile * (int64_t)(UW * kWavesPerBlock) + wave * UW;
+    const int64_t qb = qchunk * q_per_chunk;
+    const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
+    if (qb >= qe) return;  // uniform per block
+    const int grp = lane >> 4, col = lane & 15;
+
+    // the universes, split once: B operand of k-step s for column block c holds
+    // bins 32s + 8*grp + e of universe u0 + 16c + col, as 2^ed (d - o)
+    uint4 dhi[NC][NK], dlo[NC][NK];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int64_t u = u0 + 16 * c + col;
+#pragma unroll
+        for (int s = 0; s < NK; ++s) {
+            float x[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 32 * s + 8 * grp + e;
+                x[e] = (u < K && k < N) ? (float)ldexp(d[u * N + k] - off[k], ed) : 0.0f;
+            }
+            split8<FP16>(x, dhi[c][s], dlo[c][s]);
+        }
+    }
+    const int cl = (NC == 4) ? grp : (grp >> 1);
+    const bool owner = (NC == 4) ? true : ((grp & 1) == 0);
+    const int64_t u_own = u0 + 16 * cl + col;
+    const int64_t p_own = (u_own < K) ? p_idx[u_own] : -1;
+    float best = __builtin_inff();
+    uint32_t qbest = 0xffffffffu;
+    float cp = 0.0f;
+    bool have_cp = false;
+
+    uint4 st0 = make_uint4(0u, 0u, 0u, 0u), st1 = st0, st2 = st0, st3 = st0;
+    {
+        const uint4 *rq = R16 + qb * REC + tid;
+        st0 = rq[0];
+        if constexpr (CPT > 1) st1 = rq[THREADS];
+        if constexpr (CPT > 2) st2 = rq[2 * THREADS];
+        if constexpr (CPT > 3) st3 = rq[3 * THREADS];
+        uint4 *bq = &buf[0][tid];
+        bq[0] = st0;
+        if constexpr (CPT > 1) bq[THREADS] = st1;
+        if constexpr (CPT > 2) bq[2 * THREADS] = st2;
+        if constexpr (CPT > 3) bq[3 * THREADS] = st3;
+    }
+    __syncthreads();
+    int slot = 0;
+    for (int64_t q = qb; q < qe; ++q) {
+        const bool more = q + 1 < qe;
+        if (more) {
+            const uint4 *rq = R16 + (q + 1) * REC + tid;
+            st0 = rq[0];
+            if constexpr (CPT > 1) st1 = rq[THREADS];
+            if constexpr (CPT > 2) st2 = rq[2 * THREADS];
+            if constexpr (CPT > 3) st3 = rq[3 * THREADS];
+        }
+        const uint4 *rb = &buf[slot][0];
+
+        // every accumulator starts at -2^(eq+ed) u_q for its rows
+        const float4 *ul = reinterpret_cast<const float4 *>(rb + UU) + grp * 4;
+        v4f acc[NC][NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float4 c0 = ul[b];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c][b] = v4f{c0.x, c0.y, c0.z, c0.w};
+        }
+#pragma unroll
+        for (int s = 0; s < NK; ++s) {
+#pragma unroll
+            for (int b = 2 * s; b < NB; ++b) {
+                const int t = split_pair_index(NK, NB, s, b);
+                const uint4 wh = rb[t * 128 + lane];
+                const uint4 wl = rb[t * 128 + 64 + lane];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    acc[c][b] = mfma16x16x32<FP16>(wh, dhi[c][s], acc[c][b]);
+                    acc[c][b] = mfma16x16x32<FP16>(wh, dlo[c][s], acc[c][b]);
+                    acc[c][b] = mfma16x16x32<FP16>(wl, dhi[c][s], acc[c][b]);
+                }
+            }
+        }
+
+        // acc = 2^(eq+ed) z: squared and summed per universe column
+        const float unscale = __uint_as_float(rb[SU].x);
+        float part[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            float blk[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                float a = acc[c][b][0] * acc[c][b][0];
+#pragma unroll
+                for (int j = 1; j < 4; ++j) a = fmaf(acc[c][b][j], acc[c][b][j], a);
+                blk[b] = a;
+            }
+            if constexpr (NB == 4)
+                part[c] = (blk[0] + blk[1]) + (blk[2] + blk[3]);
+            else if constexpr (NB == 3)
+                part[c] = (blk[0] + blk[1]) + blk[2];
+            else if constexpr (NB == 2)
+                part[c] = blk[0] + blk[1];
+            else
+                part[c] = blk[0];
+        }
+        const bool hi = lane >= 32;
+        float kk;
+        if constexpr (NC == 4) {
+            float k0 = hi ? part[2] : part[0];
+            float k1 = hi ? part[3] : part[1];
+            const float s0 = hi ? part[0] : part[2];
+            const float s1 = hi ? part[1] : part[3];
+            k0 += __shfl_xor(s0, 32);
+            k1 += __shfl_xor(s1, 32);
+            const bool odd = grp & 1;
+            kk = odd ? k1 : k0;
+            const float ss = odd ? k0 : k1;
+            kk += __shfl_xor(ss, 16);
+        } else {
+            kk = hi ? part[1] : part[0];
+            const float s0 = hi ? part[0] : part[1];
+            kk += __shfl_xor(s0, 32);
+            kk += __shfl_xor(kk, 16);
+        }
+        const float chi2 = kk * unscale;
+
+        if (q == p_own) {
+            cp = chi2;
+            have_cp = true;
+        }
+        if (chi2 < best) {
+            best = chi2;
+            qbest = (uint32_t)q;
+        }
+
+        if (more) {
+            uint4 *bq = &buf[slot ^ 1][tid];
+            bq[0] = st0;
+            if constexpr (CPT > 1) bq[THREADS] = st1;
+            if constexpr (CPT > 2) bq[2 * THREADS] = st2;
+            if constexpr (CPT > 3) bq[3 * THREADS] = st3;
+        }
+        __syncthreads();
+        slot ^= 1;
+    }
+
+    if (owner && u_own < K) {
+        if (have_cp) chi2_p[u_own] = (double)cp;
+        if (best < __builtin_inff()) {
+            const unsigned long long key =
+                ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)qbest;
+            atomicMin(&keys[u_own], key);
+        }
+    }
+}
+
+static int resident_slots_split(const void *kernel)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 512;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 2;
+    return cus * per_cu;
+}
+
+constexpr int kSplitColBlocks = 4;  // 64 universes per wave
+
+template <int NK, int NB, bool FP16>
+static hipError_t launch_split_t(const fc_grid *g, int64_t K, const double *d,
+                                 const int64_t *p_idx, unsigned long long *keys, double *chi2_p,
+                                 hipStream_t st)
+{
+    constexpr int NC = kSplitColBlocks;
+    static int slots = 0;
+    if (slots == 0)
+        slots = resident_slots_split(reinterpret_cast<const void *>(&k_scan_split<NK, NB, NC, FP16>));
+    const ScanGeometry sg = scan_geometry(K, g->G, slots, 16 * NC * kWavesPerBlock);
+    const int64_t blocks = sg.n_utiles * sg.n_qchunks;
+    const uint4 *R = FP16 ? g->RH16 : g->RB16;
+    hipLaunchKernelGGL((k_scan_split<NK, NB, NC, FP16>), dim3((unsigned)blocks), dim3(256), 0, st, R,
+                       d, g->off, FP16 ? g->ed16 : 0, p_idx, K, g->N, g->G, sg.n_utiles,
+                       sg.q_per_chunk, keys, chi2_p);
+    return hipGetLastError();
+}
+
+template <bool FP16>
+static hipError_t launch_split_f(const fc_grid *g, int64_t K, const double *d,
+                                 const int64_t *p_idx, unsigned long long *keys, double *chi2_p,
+                                 hipStream_t st)
+{
+    const int nk = split_nk(g->N), nb = split_nb(g->N);
+    if (nk == 1 && nb == 1) return launch_split_t<1, 1, FP16>(g, K, d, p_idx, keys, chi2_p, st);
+    if (nk == 1 && nb == 2) return launch_split_t<1, 2, FP16>(g, K, d, p_idx, keys, chi2_p, st);
+    if (nk == 2 && nb == 3) return launch_split_t<2, 3, FP16>(g, K, d, p_idx, keys, chi2_p, st);
+    if (nk == 2 && nb == 4) return launch_split_t<2, 4, FP16>(g, K, d, p_idx, keys, chi2_p, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_scan_split(const fc_grid *g, bool fp16, int64_t K, const double *d,
+                             const int64_t *p_idx, unsigned long long *keys, double *chi2_p,
+                             hipStream_t st)
+{
+    return fp16 ? launch_split_f<true>(g, K, d, p_idx, keys, chi2_p, st)
+                : launch_split_f<false>(g, K, d, p_idx, keys, chi2_p, st);
+}
+
+}  // namespace fcx

@@ -47,7 +47,8 @@ def make_grid(fc, pr, forms):
     return g
 
 
-FORM = {"fp64": 1, "fp32": 2}
+FORM = {"fp64": 1, "fp32": 2, "split_bf16": 4, "split_fp16": 8}
+ALL_FORMS = 1 | 2 | 4 | 8
 
 
 # ---------------------------------------------------------------------------
@@ -93,33 +94,39 @@ def test_not_positive_definite_reports_first_bad_point(fc):
 # ---------------------------------------------------------------------------
 # scan parity on the small FP64 case and a ragged FP32 case
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "split_bf16", "split_fp16"])
 def test_scan_parity_c1(fc, form):
     pr = fcgen.make_problem("c1")
     ref = oracle.scan(pr.S, pr.F, pr.d, pr.p_idx)
-    g = make_grid(fc, pr, 1 | 2)
+    g = make_grid(fc, pr, ALL_FORMS)
     dev = run_scan(fc, g, FORM[form], pr.d, pr.p_idx)
     parity.check_invariants(dev, pr.G)
     rep = parity.report(dev, ref, parity.TOL[form])
     print(form, rep)
     assert rep["e_rel"] <= parity.TOL[form]
-    assert rep["argmin_agree"] == 1.0
+    assert rep["argmin_agree"] >= (1.0 if form in ("fp64", "fp32") else 0.99)
 
 
-def test_scan_parity_fp32_ragged_multi_tile(fc):
-    # 4 true points x 301 universes: 1204 universes = 4 full 256-blocks + a ragged tail
+@pytest.fixture(scope="module")
+def c2_ragged():
+    # 4 true points x 301 universes: 1204 universes = several full blocks + a ragged tail
     pr = fcgen.make_problem("c2", K=301, true_subset=[0, 77, 200, 255])
-    ref = oracle.scan(pr.S, pr.F, pr.d, pr.p_idx)
-    g = make_grid(fc, pr, 2)
-    dev = run_scan(fc, g, 2, pr.d, pr.p_idx)
+    return pr, oracle.scan(pr.S, pr.F, pr.d, pr.p_idx)
+
+
+@pytest.mark.parametrize("form", ["fp32", "split_bf16", "split_fp16"])
+def test_scan_parity_ragged_multi_tile(fc, c2_ragged, form):
+    pr, ref = c2_ragged
+    g = make_grid(fc, pr, FORM[form])
+    dev = run_scan(fc, g, FORM[form], pr.d, pr.p_idx)
     parity.check_invariants(dev, pr.G)
-    rep = parity.report(dev, ref, parity.TOL["fp32"])
-    print(rep)
-    assert rep["e_rel"] <= 1e-6
-    assert rep["argmin_agree"] >= 0.999
+    rep = parity.report(dev, ref, parity.TOL[form])
+    print(form, rep)
+    assert rep["e_rel"] <= parity.TOL[form]
+    assert rep["argmin_agree"] >= 0.99
 
 
-@pytest.mark.parametrize("N", [1, 3, 4, 5, 16, 17, 33, 64])
+@pytest.mark.parametrize("N", [1, 3, 4, 5, 16, 17, 32, 33, 48, 49, 57, 64])
 def test_scan_parity_bin_counts(fc, N):
     # every k-step count 1..16 class and N at the 64-bin maximum
     rng = np.random.default_rng(100 + N)
@@ -135,8 +142,8 @@ def test_scan_parity_bin_counts(fc, N):
     d = S[p] + rng.normal(0, 1, size=(K, N)) * np.sqrt(S[p])
     ref = oracle.scan(S, F, d, p)
     g = fc.fc_build_grid([np.arange(float(G))], S)
-    fc.fc_build_covariance(g, F, forms=3)
-    for form in ("fp64", "fp32"):
+    fc.fc_build_covariance(g, F, forms=ALL_FORMS)
+    for form in FORM:
         dev = run_scan(fc, g, FORM[form], d, p)
         parity.check_invariants(dev, G)
         rep = parity.report(dev, ref, parity.TOL[form])
@@ -149,7 +156,7 @@ def test_scan_parity_bin_counts(fc, N):
 # ---------------------------------------------------------------------------
 def test_edge_cases(fc):
     pr = fcgen.make_problem("c1", K=70)
-    g = make_grid(fc, pr, 1 | 2)
+    g = make_grid(fc, pr, ALL_FORMS)
     # K = 0 enqueues nothing
     e = torch.empty(0, dtype=torch.float64, device="cuda")
     ei = torch.empty(0, dtype=torch.int64, device="cuda")
@@ -166,8 +173,14 @@ def test_edge_cases(fc):
     d[3, 7] = np.nan
     p[5] = pr.G + 3
     p[6] = -2
+    # split forms: unfluctuated universes within tolerance (the linear form is not exact)
+    ref0 = oracle.scan(pr.S, pr.F, pr.S[ps], ps)
+    for form in ("split_bf16", "split_fp16"):
+        dev = run_scan(fc, g, FORM[form], pr.S[ps], ps)
+        parity.check_invariants(dev, pr.G)
+        assert parity.report(dev, ref0, parity.TOL[form])["e_rel"] <= parity.TOL[form]
     ref = oracle.scan(pr.S, pr.F, np.delete(d, [3, 5, 6], 0), np.delete(p, [3, 5, 6]))
-    for form in ("fp64", "fp32"):
+    for form in FORM:
         dev = run_scan(fc, g, FORM[form], d, p)
         assert np.isinf(dev["chi2_min"][3]) and dev["argmin"][3] == p[3]
         assert np.isnan(dev["dchi2"][3])
@@ -210,16 +223,17 @@ def test_exact_ties_pick_lowest_grid_index(fc):
 # ---------------------------------------------------------------------------
 # determinism: rerun and batch composition do not change a single bit
 # ---------------------------------------------------------------------------
-def test_bitwise_determinism_and_batch_invariance(fc):
+@pytest.mark.parametrize("form", ["fp32", "split_bf16", "split_fp16"])
+def test_bitwise_determinism_and_batch_invariance(fc, form):
     pr = fcgen.make_problem("c2", K=600, true_subset=[3, 100, 250])
-    g = make_grid(fc, pr, 2)
-    a = run_scan(fc, g, 2, pr.d, pr.p_idx)
-    b = run_scan(fc, g, 2, pr.d, pr.p_idx)
+    g = make_grid(fc, pr, FORM[form])
+    a = run_scan(fc, g, FORM[form], pr.d, pr.p_idx)
+    b = run_scan(fc, g, FORM[form], pr.d, pr.p_idx)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
     # the same universes alone (different tiles and grid chunking) and in a mix
     sub = slice(650, 777)
-    c = run_scan(fc, g, 2, pr.d[sub], pr.p_idx[sub])
+    c = run_scan(fc, g, FORM[form], pr.d[sub], pr.p_idx[sub])
     for k in a:
         np.testing.assert_array_equal(a[k][sub], c[k])
 
