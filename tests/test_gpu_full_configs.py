@@ -1,0 +1,118 @@
+"""Full-size configurations on the GPU, checked on sampled universes against
+the FP64 oracle (which computes them one by one) and on properties that hold
+at any size.
+
+c3: D=3 grid 60^3 (216 000 points), N=57, 64 true points x 4000 universes,
+    FP32 and split BF16 / FP16 forms on the same inputs.
+c5: D=5 grid 16^5 (1 048 576 points), N=57, 16 true points x 10 000
+    universes, FP32 and split FP16.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import fcgen
+import oracle
+import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FORM = {"fp32": 2, "split_bf16": 4, "split_fp16": 8}
+
+
+@pytest.fixture(scope="module")
+def fc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2002_07858_amd as fc
+    fc.lib()
+    return fc
+
+
+def scan(fc, grid, form, d_t, p_t):
+    K = d_t.shape[0]
+    out = {k: torch.empty(K, dtype=torch.float64, device="cuda")
+           for k in ("dchi2", "chi2_min", "chi2_p")}
+    out["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
+    fc.fc_scan(grid, form, d_t, p_t, out["dchi2"], out["chi2_min"], out["argmin"],
+               out["chi2_p"])
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def sample_idx(pr, per_point):
+    idx = []
+    for s in range(len(pr.seg_off) - 1):
+        lo, hi = int(pr.seg_off[s]), int(pr.seg_off[s + 1])
+        idx += list(range(lo, lo + per_point)) + [hi - 1]
+    return np.array(idx)
+
+
+@pytest.fixture(scope="module")
+def c3(fc):
+    pr = fcgen.make_problem("c3")
+    grid = fc.fc_build_grid(pr.axes, pr.S)
+    fc.fc_build_covariance(grid, pr.F, forms=2 | 4 | 8)
+    d_t = torch.as_tensor(pr.d).cuda()
+    p_t = torch.as_tensor(pr.p_idx).cuda()
+    outs = {f: scan(fc, grid, FORM[f], d_t, p_t) for f in FORM}
+    idx = sample_idx(pr, 1)
+    ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx])
+    yield pr, outs, idx, ref
+    grid.destroy()
+
+
+@pytest.mark.parametrize("form", list(FORM))
+def test_c3_sampled_parity(c3, form):
+    pr, outs, idx, ref = c3
+    dev = outs[form]
+    parity.check_invariants(dev, pr.G)
+    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, parity.TOL[form])
+    print(form, rep)
+    assert rep["e_rel"] <= parity.TOL[form]
+    assert rep["argmin_agree"] >= 0.98
+
+
+def test_c3_forms_agree_on_every_universe(c3):
+    """All 256 000 universes: split forms against the FP32 form on the same inputs."""
+    pr, outs, _, _ = c3
+    base = outs["fp32"]
+    scale = np.maximum(1.0, base["chi2_p"])
+    for form in ("split_bf16", "split_fp16"):
+        e = np.abs(outs[form]["dchi2"] - base["dchi2"]) / scale
+        assert e.max() <= parity.TOL[form] + parity.TOL["fp32"], (form, e.max())
+    # per-point 90 % critical values agree within the same Lipschitz bound
+    for form in ("split_bf16", "split_fp16"):
+        c_a, _ = oracle.critical_value(base["dchi2"], pr.seg_off, [0.9], with_hist=False)
+        c_b, _ = oracle.critical_value(outs[form]["dchi2"], pr.seg_off, [0.9], with_hist=False)
+        bound = (parity.TOL[form] + parity.TOL["fp32"]) * scale.max()
+        assert np.max(np.abs(c_a - c_b)) <= bound
+
+
+@pytest.fixture(scope="module")
+def c5(fc):
+    pr = fcgen.make_problem("c5")
+    grid = fc.fc_build_grid(pr.axes, pr.S)
+    fc.fc_build_covariance(grid, pr.F, forms=2 | 8)
+    d_t = torch.as_tensor(pr.d).cuda()
+    p_t = torch.as_tensor(pr.p_idx).cuda()
+    outs = {f: scan(fc, grid, FORM[f], d_t, p_t) for f in ("fp32", "split_fp16")}
+    idx = sample_idx(pr, 1)
+    ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx])
+    yield pr, outs, idx, ref
+    grid.destroy()
+
+
+@pytest.mark.parametrize("form", ["fp32", "split_fp16"])
+def test_c5_sampled_parity(c5, form):
+    pr, outs, idx, ref = c5
+    assert pr.G == 16 ** 5
+    dev = outs[form]
+    parity.check_invariants(dev, pr.G)
+    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, parity.TOL[form])
+    print(form, rep)
+    assert rep["e_rel"] <= parity.TOL[form]
+    assert rep["argmin_agree"] >= 0.95
