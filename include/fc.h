@@ -197,6 +197,85 @@ void fc_grid_destroy(fc_grid *g);
 /* fc_last_error -- message of the last failure on this thread ("" if none). */
 const char *fc_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Serving: FC requests against resident grids, with continuous batching.
+ *
+ * A request is one true point p of one resident grid and K universes
+ * (Section 2: the Delta chi2 distribution of a single point from N_univ
+ * fluctuated universes; Algorithm 1 for that point).  Its result is what
+ * fc_scan + fc_critical_value give for the same inputs, bit for bit: the
+ * server only changes which launch and which block evaluate each
+ * (universe, grid point) pair, and the running minimum is merged in an
+ * order-independent way.
+ *
+ * A scheduler thread owned by the server admits queued requests in arrival
+ * order while their device memory fits a fixed budget (allocated once at
+ * creation), uploads their universes, and keeps a short queue of batched
+ * launches per bin-count class: every launch takes work items (a tile of
+ * universes x a range of grid points) from all admitted requests in turn, so
+ * requests that arrive while others run join the next launch and their work
+ * overlaps on the device.  A request's Delta chi2 values, critical values
+ * and histogram are copied back when its last item has run.
+ * ------------------------------------------------------------------------ */
+typedef struct fc_server fc_server; /* opaque, library-owned */
+
+enum fc_request_state {
+    FC_REQ_QUEUED = 0,   /* waiting for device memory                  */
+    FC_REQ_RUNNING = 1,  /* admitted; items queued or running          */
+    FC_REQ_DONE = 2,     /* results are on the host                    */
+    FC_REQ_FAILED = -1   /* a device error ended it (see fc_last_error) */
+};
+
+/*
+ * fc_server_create -- start a server over resident grids.
+ *
+ *   out          host out: the new server
+ *   grids        host [n_grids] grid handles, each with `form` built; the
+ *                caller keeps them alive until fc_server_destroy returns
+ *   form         one fc_form value other than FC_FORM_FP64
+ *   hbm_budget   bytes of device memory for request data (universes,
+ *                outputs), allocated once; requests are admitted while they fit
+ *   host_budget  bytes of page-locked host memory for staging and results
+ *   n_alpha, alpha, n_bins, hist_hi   critical-value settings applied to every
+ *                request (as in fc_critical_value; n_bins >= 1)
+ *   launch_evals target (universe x grid point) evaluations per batched
+ *                launch; 0 selects a default of 1.5e8
+ */
+int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_grids, int32_t form,
+                     size_t hbm_budget, size_t host_budget, int32_t n_alpha, const double *alpha,
+                     int32_t n_bins, double hist_hi, double launch_evals);
+
+/*
+ * fc_server_submit -- queue one request (returns at once).
+ *   grid   index into the server's grids;  p   true point, 0 <= p < G
+ *   K      1..2^24 universes;  d   host [K][N] FP64, copied during the call
+ *   req    host out: request id
+ * FC_ERR_NOMEM if the request alone exceeds hbm_budget or the host staging
+ * memory is exhausted.
+ */
+int fc_server_submit(fc_server *s, int32_t grid, int64_t p, int64_t K, const double *d,
+                     int64_t *req);
+
+/*
+ * fc_server_poll -- state of a request; when FC_REQ_DONE, copies its results
+ * into the non-NULL host buffers: dchi2, chi2_min, chi2_p [K] FP64, argmin [K]
+ * int64, crit [n_alpha] FP64, hist [n_bins+1] int64, and latency (seconds from
+ * submit to results on the host).  release != 0 with a done request frees its
+ * host storage (the id is then unknown).
+ */
+int fc_server_poll(fc_server *s, int64_t req, int32_t *state, double *dchi2, double *chi2_min,
+                   int64_t *argmin, double *chi2_p, double *crit, int64_t *hist, double *latency,
+                   int32_t release);
+
+/* fc_server_stats -- totals so far (any out pointer may be NULL): requests
+ * done, launches, evaluations, device bytes in use. */
+int fc_server_stats(fc_server *s, int64_t *done, int64_t *launches, double *evals,
+                    size_t *hbm_in_use);
+
+/* fc_server_destroy -- stop admitting, wait for the launches already on the
+ * device, drop requests not yet done, free everything (NULL is a no-op). */
+void fc_server_destroy(fc_server *s);
+
 #ifdef __cplusplus
 }
 #endif

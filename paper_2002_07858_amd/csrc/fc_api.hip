@@ -77,6 +77,15 @@ bool finite_all(const double *v, size_t n)
 
 }  // namespace
 
+namespace fcx {
+// Record a failure for fc_last_error on the calling thread; returns code.
+int set_last_error(int code, const char *msg)
+{
+    g_last_error = msg;
+    return code;
+}
+}  // namespace fcx
+
 extern "C" {
 
 const char *fc_last_error(void) { return g_last_error.c_str(); }

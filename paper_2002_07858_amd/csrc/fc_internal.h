@@ -170,13 +170,42 @@ hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const 
                             double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p,
                             hipStream_t st);
 hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p, hipStream_t st);
+// p_idx may be nullptr: then every universe's true point is p_uniform.
 hipError_t launch_finalize(int64_t K, const int64_t *p_idx, unsigned long long *keys_as_chi2_min,
-                           int64_t *argmin, const double *chi2_p, double *dchi2, hipStream_t st);
+                           int64_t *argmin, const double *chi2_p, double *dchi2, hipStream_t st,
+                           int64_t p_uniform = -1);
 hipError_t launch_inverse_cov(const fc_grid *g, int64_t q0, int64_t nq, double *out,
                               hipStream_t st);
 hipError_t launch_crit(int64_t n_seg, const int64_t *seg_off, const double *x, int n_alpha,
                        const double *alpha, double *crit, int n_bins, double hist_hi,
                        int64_t *hist, hipStream_t st);
+
+// One block's unit of scan work: a tile of universes of one request against
+// a contiguous range of grid points of one grid.  fc_scan derives its items
+// from the block index; the serving kernels read them from a table.
+struct ScanItem {
+    const uint4 *R;               // the grid's records (form layout)
+    const double *d;              // universes [K][N] FP64
+    const int64_t *p_idx;         // per-universe true points, or nullptr
+    int64_t p;                    // the true point when p_idx is nullptr
+    unsigned long long *keys;     // [K] packed (chi2 bits, q) minimum keys
+    double *chi2_p;               // [K] chi2 at the true point
+    const double *off;            // split forms: per-bin offset o
+    int64_t K;                    // universes of the request
+    int64_t u0;                   // first universe of the block's tile
+    int64_t qb, qe;               // grid points [qb, qe)
+    int32_t N;                    // bins
+    int32_t ed;                   // split FP16: scale exponent of (d - o)
+};
+
+hipError_t launch_serve_fp32(int ns, const ScanItem *items, int n_items, int *counter, int blocks,
+                             hipStream_t st);
+hipError_t launch_serve_split(int nk, int nb, bool fp16, const ScanItem *items, int n_items,
+                              int *counter, int blocks, hipStream_t st);
+int serve_fp32_univ_per_item();
+int serve_split_univ_per_item();
+int serve_slots_fp32(int ns);
+int serve_slots_split(int nk, int nb, bool fp16);
 
 // Scan launch geometry chosen by the host: universe tiles x grid chunks.
 struct ScanGeometry {

@@ -12,7 +12,6 @@
 namespace fcx {
 
 constexpr int kMaxAlpha = 8;
-constexpr int kMaxHistBins = 16384;  // LDS u32 counters incl. the overflow bin
 
 struct AlphaArgs {
     double a[kMaxAlpha];

@@ -2,7 +2,7 @@
 //
 // FP32 form (the hot kernel).  Eq. (1) is evaluated in factor form,
 //     chi2(d, q) = ||W_q (d - S_q)||^2,   W_q = L_q^{-1} (lower triangular),
-// which equals (d-S_q)^T Sigma_q^{-1} (d-S_q).  For a fixed q and a tile of 64
+// which equals (d-S_q)^T Sigma_q^{-1} (d-S_q).  For a fixed q and a tile of
 // universes this is a dense contraction Z = W_q R (R = bins x universes),
 // done on the matrix cores with v_mfma_f32_16x16x4_f32 over the lower-
 // triangular block pattern of W_q only, followed by a column-wise sum of
@@ -11,14 +11,14 @@
 // ALU on this chip, so the vector work around it (residuals, squares) is
 // kept to FP32 instructions: FP64 ones cost twice as much.
 //
-// Work decomposition: a block of 4 waves owns 256 universes; each wave owns
-// 64 universes and walks one contiguous chunk of grid points in list order.
-// A wave keeps its universes' residual operands in registers for the whole
-// chunk and streams W_q (lane-major fragments, one 16-byte load per lane per
-// four MFMAs) and S_q from global memory; there is no LDS and no barrier.
-// Chunks of the same universes are merged with a 64-bit atomicMin on keys
-// (FP32 chi2 bits above q), which reproduces Algorithm 1's rule that the
-// lowest q wins exact ties whatever the chunking.
+// Work decomposition: a 256-thread block owns a tile of 4 waves x 32
+// universes and walks a contiguous range of grid points in list order.  Each
+// wave keeps its universes' residual operands in registers; the block
+// double-buffers one record per grid point in LDS (W_q fragments and S_q),
+// copying the next record while the waves contract the current one, with one
+// barrier per grid point.  Ranges of the same universes are merged with a
+// 64-bit atomicMin on keys (FP32 chi2 bits above q), which reproduces
+// Algorithm 1's rule that the lowest q wins exact ties whatever the split.
 #include "fc_internal.h"
 
 namespace fcx {
@@ -35,15 +35,20 @@ __device__ __forceinline__ float pick(const float4 &v, int c)
 // double-buffered: while the waves contract grid point q from one buffer, the
 // block's 256 threads copy record q+1 into the other with coalesced 16-byte
 // loads, and one barrier per grid point hands the buffers over.
+template <int NS>
+struct Fp32Geo {
+    static constexpr int NB = n_rowblocks_from_ns(NS);
+    static constexpr int NG = n_groups_from_ns(NS);
+    static constexpr int NWU = rec_w_units(NS);  // 16-byte units of W per record
+    static constexpr int REC = rec_units(NS);    // W + 512 B of S + padding
+};
+
 template <int NS, int NC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32(
-    const uint4 *__restrict__ R32, const double *__restrict__ d,
-    const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
-    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
+__device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 (*buf)[Fp32Geo<NS>::REC])
 {
     static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
-    constexpr int NB = n_rowblocks_from_ns(NS);
-    constexpr int NG = n_groups_from_ns(NS);
+    constexpr int NB = Fp32Geo<NS>::NB;
+    constexpr int NG = Fp32Geo<NS>::NG;
     constexpr int UW = 16 * NC;            // universes per wave
     constexpr int NWU = rec_w_units(NS);   // 16-byte units of W per record
     constexpr int REC = rec_units(NS);     // W + 512 B of S + padding
@@ -51,16 +56,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     static_assert(REC % THREADS == 0, "records are whole 4 KB pieces");
     constexpr int CPT = REC / THREADS;     // units copied per thread
     static_assert(NG * 64 == NWU, "W groups");
-    __shared__ uint4 buf[2][REC];
 
+    const uint4 *__restrict__ R32 = it.R;
+    const double *__restrict__ d = it.d;
+    const int64_t K = it.K;
+    const int N = it.N;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t utile = blockIdx.x % n_utiles;
-    const int64_t qchunk = blockIdx.x / n_utiles;
-    const int64_t u0 = utile * (int64_t)(UW * kWavesPerBlock) + wave * UW;
-    const int64_t qb = qchunk * q_per_chunk;
-    const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
+    const int64_t u0 = it.u0 + wave * UW;
+    const int64_t qb = it.qb, qe = it.qe;
     if (qb >= qe) return;  // uniform per block
     const int grp = lane >> 4, col = lane & 15;
 
@@ -87,7 +92,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int cl = (NC == 4) ? grp : (grp >> 1);
     const bool owner = (NC == 4) ? true : ((grp & 1) == 0);
     const int64_t u_own = u0 + 16 * cl + col;
-    const int64_t p_own = (u_own < K) ? p_idx[u_own] : -1;
+    const int64_t p_own = (u_own < K) ? (it.p_idx ? it.p_idx[u_own] : it.p) : -1;
     float best = __builtin_inff();
     uint32_t qbest = 0xffffffffu;
     float cp = 0.0f;
@@ -210,12 +215,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 
     if (owner && u_own < K) {
-        if (have_cp) chi2_p[u_own] = (double)cp;
+        if (have_cp) it.chi2_p[u_own] = (double)cp;
         if (best < __builtin_inff()) {
             const unsigned long long key =
                 ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)qbest;
-            atomicMin(&keys[u_own], key);
+            atomicMin(&it.keys[u_own], key);
         }
+    }
+}
+
+template <int NS, int NC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32(
+    const uint4 *__restrict__ R32, const double *__restrict__ d,
+    const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
+    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
+{
+    __shared__ uint4 buf[2][Fp32Geo<NS>::REC];
+    ScanItem it;
+    it.R = R32;
+    it.d = d;
+    it.p_idx = p_idx;
+    it.p = -1;
+    it.keys = keys;
+    it.chi2_p = chi2_p;
+    it.off = nullptr;
+    it.K = K;
+    it.N = N;
+    it.ed = 0;
+    const int64_t utile = blockIdx.x % n_utiles;
+    const int64_t qchunk = blockIdx.x / n_utiles;
+    it.u0 = utile * (int64_t)(16 * NC * kWavesPerBlock);
+    it.qb = qchunk * q_per_chunk;
+    it.qe = (it.qb + q_per_chunk < G) ? it.qb + q_per_chunk : G;
+    fp32_item<NS, NC>(it, buf);
+}
+
+// Serving: a persistent-style launch over a table of items (any mix of
+// requests and grids with this bin count).  Resident blocks take items in
+// turn from an atomic counter until the table is exhausted; the table is
+// finite and fixed at launch, so every block reaches the exit.
+template <int NS, int NC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_serve_fp32(
+    const ScanItem *__restrict__ items, int n_items, int *__restrict__ counter)
+{
+    __shared__ uint4 buf[2][Fp32Geo<NS>::REC];
+    __shared__ int cur;
+    for (;;) {
+        if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+        __syncthreads();
+        const int i = cur;
+        __syncthreads();
+        if (i >= n_items) break;
+        fp32_item<NS, NC>(items[i], buf);
+        __syncthreads();
     }
 }
 
@@ -276,6 +328,7 @@ __global__ __launch_bounds__(256) void k_init_keys(int64_t K, unsigned long long
 
 // Decode the keys in place (the key buffer is the caller's chi2_min array).
 __global__ __launch_bounds__(256) void k_finalize(int64_t K, const int64_t *__restrict__ p_idx,
+                                                 int64_t p_uniform,
                                                  unsigned long long *__restrict__ keys,
                                                  int64_t *__restrict__ argmin,
                                                  const double *__restrict__ chi2_p,
@@ -289,7 +342,7 @@ __global__ __launch_bounds__(256) void k_finalize(int64_t K, const int64_t *__re
     int64_t am;
     if (hi >= 0x7f800000u) {  // no chi2 < +inf was seen: Algorithm 1's initial state
         cmin = __builtin_inf();
-        am = p_idx[u];
+        am = p_idx ? p_idx[u] : p_uniform;
     } else {
         cmin = (double)__uint_as_float(hi);
         am = (int64_t)(uint32_t)(key & 0xffffffffu);
@@ -363,6 +416,53 @@ static hipError_t launch_fp32_ns(const fc_grid *g, int64_t K, const double *d, c
     return hipGetLastError();
 }
 
+template <int NS>
+static hipError_t launch_serve_fp32_ns(const ScanItem *items, int n_items, int *counter, int blocks,
+                                       hipStream_t st)
+{
+    hipLaunchKernelGGL((k_serve_fp32<NS, kScanColBlocks>), dim3((unsigned)blocks), dim3(256), 0, st,
+                       items, n_items, counter);
+    return hipGetLastError();
+}
+
+template <int NS>
+static int serve_slots_fp32_ns()
+{
+    static int slots = 0;
+    if (slots == 0)
+        slots = resident_slots(reinterpret_cast<const void *>(&k_serve_fp32<NS, kScanColBlocks>), 256);
+    return slots;
+}
+
+int serve_fp32_univ_per_item() { return 16 * kScanColBlocks * kWavesPerBlock; }
+
+hipError_t launch_serve_fp32(int ns, const ScanItem *items, int n_items, int *counter, int blocks,
+                             hipStream_t st)
+{
+    switch (ns) {
+#define FC_CASE(n) \
+    case n: return launch_serve_fp32_ns<n>(items, n_items, counter, blocks, st);
+        FC_CASE(1) FC_CASE(2) FC_CASE(3) FC_CASE(4) FC_CASE(5) FC_CASE(6) FC_CASE(7) FC_CASE(8)
+        FC_CASE(9) FC_CASE(10) FC_CASE(11) FC_CASE(12) FC_CASE(13) FC_CASE(14) FC_CASE(15)
+        FC_CASE(16)
+#undef FC_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int serve_slots_fp32(int ns)
+{
+    switch (ns) {
+#define FC_CASE(n) \
+    case n: return serve_slots_fp32_ns<n>();
+        FC_CASE(1) FC_CASE(2) FC_CASE(3) FC_CASE(4) FC_CASE(5) FC_CASE(6) FC_CASE(7) FC_CASE(8)
+        FC_CASE(9) FC_CASE(10) FC_CASE(11) FC_CASE(12) FC_CASE(13) FC_CASE(14) FC_CASE(15)
+        FC_CASE(16)
+#undef FC_CASE
+    default: return 512;
+    }
+}
+
 hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
                             unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
@@ -411,10 +511,11 @@ hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p,
 }
 
 hipError_t launch_finalize(int64_t K, const int64_t *p_idx, unsigned long long *keys_as_chi2_min,
-                           int64_t *argmin, const double *chi2_p, double *dchi2, hipStream_t st)
+                           int64_t *argmin, const double *chi2_p, double *dchi2, hipStream_t st,
+                           int64_t p_uniform)
 {
     const int64_t blocks = (K + 255) / 256;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, st, K, p_idx,
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, st, K, p_idx, p_uniform,
                        keys_as_chi2_min, argmin, chi2_p, dchi2);
     return hipGetLastError();
 }

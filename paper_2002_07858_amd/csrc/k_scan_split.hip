@@ -58,10 +58,8 @@ __device__ __forceinline__ void split8(const float (&x)[8], uint4 &hi, uint4 &lo
 }
 
 template <int NK, int NB, int NC, bool FP16>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_split(
-    const uint4 *__restrict__ R16, const double *__restrict__ d, const double *__restrict__ off,
-    int ed, const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
-    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
+__device__ __forceinline__ void split_item(const ScanItem &it,
+                                           uint4 (*buf)[split_rec_units(NK, NB)])
 {
     static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
     constexpr int UW = 16 * NC;
@@ -72,16 +70,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     static_assert(REC % THREADS == 0, "records are whole 4 KB pieces");
     constexpr int CPT = REC / THREADS;
     static_assert(CPT >= 1 && CPT <= 4, "records of at most four 4 KB pieces");
-    __shared__ uint4 buf[2][REC];
 
+    const uint4 *__restrict__ R16 = it.R;
+    const double *__restrict__ d = it.d;
+    const double *__restrict__ off = it.off;
+    const int64_t K = it.K;
+    const int N = it.N;
+    const int ed = it.ed;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t utile = blockIdx.x % n_utiles;
-    const int64_t qchunk = blockIdx.x / n_utiles;
-    const int64_t u0 = utile * (int64_t)(UW * kWavesPerBlock) + wave * UW;
-    const int64_t qb = qchunk * q_per_chunk;
-    const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
+    const int64_t u0 = it.u0 + wave * UW;
+    const int64_t qb = it.qb, qe = it.qe;
     if (qb >= qe) return;  // uniform per block
     const int grp = lane >> 4, col = lane & 15;
 
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int cl = (NC == 4) ? grp : (grp >> 1);
     const bool owner = (NC == 4) ? true : ((grp & 1) == 0);
     const int64_t u_own = u0 + 16 * cl + col;
-    const int64_t p_own = (u_own < K) ? p_idx[u_own] : -1;
+    const int64_t p_own = (u_own < K) ? (it.p_idx ? it.p_idx[u_own] : it.p) : -1;
     float best = __builtin_inff();
     uint32_t qbest = 0xffffffffu;
     float cp = 0.0f;
@@ -226,12 +226,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 
     if (owner && u_own < K) {
-        if (have_cp) chi2_p[u_own] = (double)cp;
+        if (have_cp) it.chi2_p[u_own] = (double)cp;
         if (best < __builtin_inff()) {
             const unsigned long long key =
                 ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)qbest;
-            atomicMin(&keys[u_own], key);
+            atomicMin(&it.keys[u_own], key);
         }
+    }
+}
+
+template <int NK, int NB, int NC, bool FP16>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_split(
+    const uint4 *__restrict__ R16, const double *__restrict__ d, const double *__restrict__ off,
+    int ed, const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
+    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
+{
+    __shared__ uint4 buf[2][split_rec_units(NK, NB)];
+    ScanItem it;
+    it.R = R16;
+    it.d = d;
+    it.p_idx = p_idx;
+    it.p = -1;
+    it.keys = keys;
+    it.chi2_p = chi2_p;
+    it.off = off;
+    it.K = K;
+    it.N = N;
+    it.ed = ed;
+    const int64_t utile = blockIdx.x % n_utiles;
+    const int64_t qchunk = blockIdx.x / n_utiles;
+    it.u0 = utile * (int64_t)(16 * NC * kWavesPerBlock);
+    it.qb = qchunk * q_per_chunk;
+    it.qe = (it.qb + q_per_chunk < G) ? it.qb + q_per_chunk : G;
+    split_item<NK, NB, NC, FP16>(it, buf);
+}
+
+// Serving: persistent-style launch over a finite table of items (see the
+// FP32 form).
+template <int NK, int NB, int NC, bool FP16>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_serve_split(
+    const ScanItem *__restrict__ items, int n_items, int *__restrict__ counter)
+{
+    __shared__ uint4 buf[2][split_rec_units(NK, NB)];
+    __shared__ int cur;
+    for (;;) {
+        if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+        __syncthreads();
+        const int i = cur;
+        __syncthreads();
+        if (i >= n_items) break;
+        split_item<NK, NB, NC, FP16>(items[i], buf);
+        __syncthreads();
     }
 }
 
@@ -279,6 +324,57 @@ static hipError_t launch_split_f(const fc_grid *g, int64_t K, const double *d,
     if (nk == 2 && nb == 3) return launch_split_t<2, 3, FP16>(g, K, d, p_idx, keys, chi2_p, st);
     if (nk == 2 && nb == 4) return launch_split_t<2, 4, FP16>(g, K, d, p_idx, keys, chi2_p, st);
     return hipErrorInvalidValue;
+}
+
+template <int NK, int NB, bool FP16>
+static int serve_slots_split_t()
+{
+    static int slots = 0;
+    if (slots == 0)
+        slots = resident_slots_split(
+            reinterpret_cast<const void *>(&k_serve_split<NK, NB, kSplitColBlocks, FP16>));
+    return slots;
+}
+
+template <int NK, int NB, bool FP16>
+static hipError_t launch_serve_split_t(const ScanItem *items, int n_items, int *counter,
+                                       int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_serve_split<NK, NB, kSplitColBlocks, FP16>), dim3((unsigned)blocks),
+                       dim3(256), 0, st, items, n_items, counter);
+    return hipGetLastError();
+}
+
+int serve_split_univ_per_item() { return 16 * kSplitColBlocks * kWavesPerBlock; }
+
+#define FC_SPLIT_DISPATCH(EXPR_T)                                   \
+    if (fp16) {                                                     \
+        if (nk == 1 && nb == 1) return EXPR_T(1, 1, true);          \
+        if (nk == 1 && nb == 2) return EXPR_T(1, 2, true);          \
+        if (nk == 2 && nb == 3) return EXPR_T(2, 3, true);          \
+        if (nk == 2 && nb == 4) return EXPR_T(2, 4, true);          \
+    } else {                                                        \
+        if (nk == 1 && nb == 1) return EXPR_T(1, 1, false);         \
+        if (nk == 1 && nb == 2) return EXPR_T(1, 2, false);         \
+        if (nk == 2 && nb == 3) return EXPR_T(2, 3, false);         \
+        if (nk == 2 && nb == 4) return EXPR_T(2, 4, false);         \
+    }
+
+hipError_t launch_serve_split(int nk, int nb, bool fp16, const ScanItem *items, int n_items,
+                              int *counter, int blocks, hipStream_t st)
+{
+#define FC_T(a, b, c) launch_serve_split_t<a, b, c>(items, n_items, counter, blocks, st)
+    FC_SPLIT_DISPATCH(FC_T)
+#undef FC_T
+    return hipErrorInvalidValue;
+}
+
+int serve_slots_split(int nk, int nb, bool fp16)
+{
+#define FC_T(a, b, c) serve_slots_split_t<a, b, c>()
+    FC_SPLIT_DISPATCH(FC_T)
+#undef FC_T
+    return 512;
 }
 
 hipError_t launch_scan_split(const fc_grid *g, bool fp16, int64_t K, const double *d,

@@ -33,9 +33,15 @@ FC_STAT_FIXED = 1
 
 FC_MAX_BINS = 64
 
+FC_REQ_QUEUED = 0
+FC_REQ_RUNNING = 1
+FC_REQ_DONE = 2
+FC_REQ_FAILED = -1
+
 EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
             "fc_grid_inverse_cov", "fc_grid_info", "fc_grid_device_bytes", "fc_grid_destroy",
-            "fc_last_error")
+            "fc_last_error", "fc_server_create", "fc_server_submit", "fc_server_poll",
+            "fc_server_stats", "fc_server_destroy")
 
 
 class FCError(RuntimeError):
@@ -71,6 +77,15 @@ def lib():
         L.fc_grid_destroy.restype = None
         L.fc_last_error.argtypes = []
         L.fc_last_error.restype = ctypes.c_char_p
+        L.fc_server_create.argtypes = [ctypes.POINTER(_p), _p, _i32, _i32, ctypes.c_size_t,
+                                       ctypes.c_size_t, _i32, _p, _i32, _dbl, _dbl]
+        L.fc_server_submit.argtypes = [_p, _i32, _i64, _i64, _p, _p]
+        L.fc_server_poll.argtypes = [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _i32]
+        L.fc_server_stats.argtypes = [_p, _p, _p, _p, _p]
+        L.fc_server_destroy.argtypes = [_p]
+        L.fc_server_destroy.restype = None
+        for name in ("fc_server_create", "fc_server_submit", "fc_server_poll", "fc_server_stats"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
                      "fc_grid_inverse_cov", "fc_grid_info"):
             getattr(L, name).restype = ctypes.c_int
@@ -220,3 +235,79 @@ def fc_grid_device_bytes(grid: Grid) -> int:
 
 def fc_grid_destroy(grid: Grid):
     grid.destroy()
+
+
+class Server:
+    """Owning wrapper of an fc_server (FC request serving with continuous batching).
+
+    The grids passed in must stay alive while the server exists; the server
+    keeps references to their wrappers for that reason.
+    """
+
+    def __init__(self, grids, form=FC_FORM_FP32, hbm_budget=8 << 30, host_budget=2 << 30,
+                 alpha=(0.6827, 0.9, 0.95), n_bins=200, hist_hi=50.0, launch_evals=0.0):
+        self.grids = list(grids)
+        self.alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        self.n_bins = int(n_bins)
+        self.N = [fc_grid_info(g)["N"] for g in self.grids]
+        handles = (_p * len(self.grids))(*[g.handle for g in self.grids])
+        out = _p()
+        _check(lib().fc_server_create(ctypes.byref(out), handles, len(self.grids), int(form),
+                                      int(hbm_budget), int(host_budget), len(self.alpha),
+                                      _hp(self.alpha), self.n_bins, float(hist_hi),
+                                      float(launch_evals)))
+        self.handle = out.value
+        self.K = {}
+
+    def submit(self, grid: int, p: int, d) -> int:
+        """Queue a request; d is host [K][N] FP64.  Returns the request id."""
+        d = _host(d, np.float64)
+        if d.ndim != 2 or d.shape[1] != self.N[grid]:
+            raise ValueError("d must be [K][N] for the chosen grid")
+        req = ctypes.c_int64()
+        _check(lib().fc_server_submit(_p(self.handle), int(grid), int(p), int(d.shape[0]),
+                                      _hp(d), ctypes.byref(req)))
+        self.K[req.value] = int(d.shape[0])
+        return req.value
+
+    def poll(self, req: int, release: bool = True):
+        """(state, results or None).  Results: dict of numpy arrays + latency (s)."""
+        state = ctypes.c_int32()
+        K = self.K[req]
+        dchi2 = np.empty(K)
+        cmin = np.empty(K)
+        am = np.empty(K, dtype=np.int64)
+        cp = np.empty(K)
+        crit = np.empty(len(self.alpha))
+        hist = np.empty(self.n_bins + 1, dtype=np.int64)
+        lat = ctypes.c_double()
+        _check(lib().fc_server_poll(_p(self.handle), int(req), ctypes.byref(state), _hp(dchi2),
+                                    _hp(cmin), _hp(am), _hp(cp), _hp(crit), _hp(hist),
+                                    ctypes.byref(lat), 1 if release else 0))
+        if state.value != FC_REQ_DONE:
+            return state.value, None
+        if release:
+            del self.K[req]
+        return state.value, dict(dchi2=dchi2, chi2_min=cmin, argmin=am, chi2_p=cp, crit=crit,
+                                 hist=hist, latency=lat.value)
+
+    def stats(self):
+        done = ctypes.c_int64()
+        launches = ctypes.c_int64()
+        evals = ctypes.c_double()
+        used = ctypes.c_size_t()
+        _check(lib().fc_server_stats(_p(self.handle), ctypes.byref(done), ctypes.byref(launches),
+                                     ctypes.byref(evals), ctypes.byref(used)))
+        return dict(done=done.value, launches=launches.value, evals=evals.value,
+                    hbm_in_use=used.value)
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().fc_server_destroy(_p(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

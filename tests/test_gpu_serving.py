@@ -1,0 +1,160 @@
+"""Serving: FC requests with continuous batching against resident grids.
+
+Each request's results in the mix must equal, bit for bit, fc_scan +
+fc_critical_value on the same inputs alone; admission waits for memory
+instead of failing; a request that can never fit is refused.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import pytest
+
+import fcgen
+import oracle
+import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ALPHA = (0.6827, 0.9, 0.95)
+N_BINS, HIST_HI = 200, 50.0
+
+
+@pytest.fixture(scope="module")
+def fc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2002_07858_amd as fc
+    fc.lib()
+    return fc
+
+
+@pytest.fixture(scope="module")
+def grids(fc):
+    """Three resident grids: D=2 20x20 (N=38), D=2 100x100 (N=57), D=3 20^3 (N=57)."""
+    out = []
+    for name, n_axis in (("c1", None), ("c2", None), ("c3", (20, 20, 20))):
+        pr = fcgen.make_problem(name, K=1, true_subset=[0], n_axis=n_axis)
+        g = fc.fc_build_grid(pr.axes, pr.S)
+        fc.fc_build_covariance(g, pr.F, forms=fc.FC_FORM_FP32 | fc.FC_FORM_SPLIT_FP16)
+        out.append((pr, g))
+    yield out
+    for _, g in out:
+        g.destroy()
+
+
+def make_requests(grids, n, k_lo, k_hi, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for j in range(n):
+        gi = int(rng.integers(0, len(grids)))
+        pr, _ = grids[gi]
+        p = int(rng.integers(0, pr.G))
+        K = int(math.floor(math.exp(rng.uniform(math.log(k_lo), math.log(k_hi)))))
+        d = fcgen.universes(4, 1000 * seed + j, pr.S[p], pr.F, K)
+        reqs.append((gi, p, d))
+    return reqs
+
+
+def alone(fc, grid, form, p, d):
+    K = d.shape[0]
+    d_t = torch.as_tensor(d).cuda()
+    p_t = torch.full((K,), p, dtype=torch.int64, device="cuda")
+    o = {k: torch.empty(K, dtype=torch.float64, device="cuda") for k in ("dchi2", "chi2_min",
+                                                                       "chi2_p")}
+    o["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
+    fc.fc_scan(grid, form, d_t, p_t, o["dchi2"], o["chi2_min"], o["argmin"], o["chi2_p"])
+    seg = torch.tensor([0, K], dtype=torch.int64, device="cuda")
+    crit = torch.empty((1, len(ALPHA)), dtype=torch.float64, device="cuda")
+    hist = torch.empty((1, N_BINS + 1), dtype=torch.int64, device="cuda")
+    fc.fc_critical_value(seg, o["dchi2"], ALPHA, crit, N_BINS, HIST_HI, hist)
+    torch.cuda.synchronize()
+    r = {k: v.cpu().numpy() for k, v in o.items()}
+    r["crit"] = crit.cpu().numpy()[0]
+    r["hist"] = hist.cpu().numpy()[0]
+    return r
+
+
+def wait_all(server, ids, timeout=180.0):
+    res = {}
+    t0 = time.time()
+    while len(res) < len(ids):
+        for i in ids:
+            if i in res:
+                continue
+            st, r = server.poll(i)
+            assert st != -1, "request failed"
+            if r is not None:
+                res[i] = r
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(0.002)
+    return res
+
+
+@pytest.mark.parametrize("form_name", ["fp32", "split_fp16"])
+def test_mix_equals_alone(fc, grids, form_name):
+    form = {"fp32": fc.FC_FORM_FP32, "split_fp16": fc.FC_FORM_SPLIT_FP16}[form_name]
+    server = fc.Server([g for _, g in grids], form=form, hbm_budget=512 << 20,
+                       host_budget=512 << 20, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI,
+                       launch_evals=2e7)
+    reqs = make_requests(grids, 36, 300, 3000, seed=1)
+    ids = []
+    # arrivals spread out so that later requests join while earlier ones run
+    for k, (gi, p, d) in enumerate(reqs):
+        ids.append(server.submit(gi, p, d))
+        if k % 6 == 5:
+            time.sleep(0.003)
+    res = wait_all(server, ids)
+    st = server.stats()
+    server.destroy()
+    assert st["done"] == len(reqs)
+    assert st["launches"] >= 2
+    for i, (gi, p, d) in zip(ids, reqs):
+        ref = alone(fc, grids[gi][1], form, p, d)
+        for key in ("dchi2", "chi2_min", "argmin", "chi2_p", "crit", "hist"):
+            np.testing.assert_array_equal(res[i][key], ref[key], err_msg=key)
+        assert res[i]["latency"] > 0.0
+
+
+def test_served_results_match_oracle(fc, grids):
+    server = fc.Server([g for _, g in grids], form=fc.FC_FORM_FP32, hbm_budget=256 << 20,
+                       host_budget=256 << 20, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI)
+    reqs = make_requests(grids, 3, 200, 400, seed=2)
+    ids = [server.submit(gi, p, d) for gi, p, d in reqs]
+    res = wait_all(server, ids)
+    server.destroy()
+    for i, (gi, p, d) in zip(ids, reqs):
+        pr = grids[gi][0]
+        ref = oracle.scan(pr.S, pr.F, d, np.full(d.shape[0], p))
+        rep = parity.report(res[i], ref, parity.TOL["fp32"])
+        assert rep["e_rel"] <= parity.TOL["fp32"], rep
+        c_ref, h_ref = oracle.critical_value(res[i]["dchi2"], [0, d.shape[0]], ALPHA,
+                                             n_bins=N_BINS, hist_hi=HIST_HI)
+        np.testing.assert_array_equal(res[i]["crit"], c_ref[0])
+        np.testing.assert_array_equal(res[i]["hist"], h_ref[0])
+
+
+def test_admission_waits_for_memory_and_refuses_oversized(fc, grids):
+    # ~1.5 MB per request of 3000 universes at N = 57: a 4 MB budget holds two
+    server = fc.Server([g for _, g in grids], form=fc.FC_FORM_FP32, hbm_budget=4 << 20,
+                       host_budget=256 << 20, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI)
+    pr, _ = grids[1]
+    reqs = [(1, int(p), fcgen.universes(4, 500 + j, pr.S[p], pr.F, 3000))
+            for j, p in enumerate((5, 700, 9000, 123, 4567, 8888))]
+    ids = [server.submit(gi, p, d) for gi, p, d in reqs]
+    res = wait_all(server, ids)
+    assert len(res) == len(reqs)
+    big = fcgen.universes(4, 999, pr.S[10], pr.F, 12000)
+    with pytest.raises(fc.FCError) as ei:
+        server.submit(1, 10, big)
+    assert ei.value.code == fc.FC_ERR_NOMEM
+    with pytest.raises(fc.FCError):
+        server.submit(1, pr.G, reqs[0][2])          # true point out of range
+    server.destroy()
+    for i, (gi, p, d) in zip(ids, reqs):
+        ref = alone(fc, grids[gi][1], fc.FC_FORM_FP32, p, d)
+        np.testing.assert_array_equal(res[i]["dchi2"], ref["dchi2"])
