@@ -1,6 +1,6 @@
 """Benchmark of the FC grid-scan hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--form fp32]
+    python bench.py [--steps K] [--warmup W] [--form fp32] [--serving-requests R]
 
 Workload: D = 2 grid 100 x 100 (G = 10^4), N = 57 bins, 256 true points x
 2000 universes (512 000 universes, 5.12e9 universe x grid-point chi^2
@@ -10,7 +10,10 @@ toy oscillation model, resident in HBM before the timed region.
 
 One step = covariance factors for every grid point (FP64 Cholesky + inverse,
 stored in the scan form) + the scan of all universes (minimum, argmin,
-Delta chi^2) + critical values.  Prints one JSON line.
+Delta chi^2) + critical values.  A serving leg then replays a seeded Poisson
+stream of FC requests (K log-uniform in [500, 20000], three resident grids)
+through a plain FIFO loop and through the continuous-batching server and
+reports p50/p99 latency beside throughput.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -74,6 +77,138 @@ def cpu_baseline(pr, per_point: int, dev_out: dict, tol: float):
     return base, rep
 
 
+# ---------------------------------------------------------------------------
+# Serving: FC requests against the three resident grids (D=2 20x20 N=38,
+# D=2 100x100 N=57, D=3 60^3 N=57), Poisson arrivals, K log-uniform in
+# [500, 20000]; plain = one request at a time through fc_scan (FIFO),
+# batched = the continuous-batching server, in FP32 and split FP16.
+# ---------------------------------------------------------------------------
+def serving_requests(grids, n_req, seed=3):
+    import math
+    import fcgen
+    rng = fcgen.rng_for(4, 3, seed)
+    reqs = []
+    for j in range(n_req):
+        gi = int(rng.integers(0, len(grids)))
+        pr = grids[gi][0]
+        p = int(rng.integers(0, pr.G))
+        K = int(math.floor(math.exp(rng.uniform(math.log(500), math.log(20000)))))
+        d = fcgen.universes(4, j, pr.S[p], pr.F, K)
+        reqs.append((gi, p, d))
+    return reqs
+
+
+def run_plain(fc, grids, reqs, arrivals):
+    """FIFO, one request at a time: upload, fc_scan, fc_critical_value, copy back."""
+    import torch
+    lat, evals = [], 0.0
+    t0 = time.perf_counter()
+    for (gi, p, d), ta in zip(reqs, arrivals):
+        now = time.perf_counter() - t0
+        if now < ta:
+            time.sleep(ta - now)
+        g = grids[gi][1]
+        K = d.shape[0]
+        d_t = torch.as_tensor(d).cuda()
+        p_t = torch.full((K,), p, dtype=torch.int64, device="cuda")
+        o = [torch.empty(K, dtype=torch.float64, device="cuda") for _ in range(3)]
+        am = torch.empty(K, dtype=torch.int64, device="cuda")
+        fc.fc_scan(g, fc.FC_FORM_FP32, d_t, p_t, o[0], o[1], am, o[2])
+        seg = torch.tensor([0, K], dtype=torch.int64, device="cuda")
+        crit = torch.empty((1, len(ALPHA)), dtype=torch.float64, device="cuda")
+        hist = torch.empty((1, N_BINS + 1), dtype=torch.int64, device="cuda")
+        fc.fc_critical_value(seg, o[0], ALPHA, crit, N_BINS, HIST_HI, hist)
+        o[0].cpu(), crit.cpu(), hist.cpu()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0 - ta)
+        evals += K * grids[gi][0].G
+    wall = time.perf_counter() - t0
+    return lat, wall, evals
+
+
+def run_batched(fc, grids, reqs, arrivals, form, policy):
+    import threading
+    server = fc.Server([g for _, g in grids], form=form, hbm_budget=16 << 30,
+                       host_budget=4 << 30, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI,
+                       policy=policy)
+    ids = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for k, ((gi, p, d), ta) in enumerate(zip(reqs, arrivals)):
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            ids[k] = server.submit(gi, p, d)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat = {}
+    while len(lat) < len(reqs):
+        for k, i in enumerate(ids):
+            if i is None or k in lat:
+                continue
+            st, r = server.poll(i)
+            if st == fc.FC_REQ_FAILED:
+                raise RuntimeError("served request failed")
+            if r is not None:
+                lat[k] = r["latency"]
+        time.sleep(0.0005)
+        if time.perf_counter() - t0 > 600:
+            raise RuntimeError("serving run did not finish")
+    th.join()
+    wall = time.perf_counter() - t0
+    st = server.stats()
+    server.destroy()
+    return [lat[k] for k in range(len(reqs))], wall, st["evals"], st["launches"]
+
+
+def summarize(lat, wall, evals, n):
+    a = np.sort(np.asarray(lat)) * 1e3
+    return {"p50_ms": float(np.percentile(a, 50)), "p99_ms": float(np.percentile(a, 99)),
+            "mean_ms": float(a.mean()), "throughput_req_s": n / wall,
+            "evals_per_s": evals / wall}
+
+
+def serving_bench(n_req: int, loads=(0.8,)):
+    import fcgen
+    import paper_2002_07858_amd as fc
+    grids = []
+    for name in ("c1", "c2", "c3"):
+        pr = fcgen.make_problem(name, K=1, true_subset=[0])
+        g = fc.fc_build_grid(pr.axes, pr.S)
+        fc.fc_build_covariance(g, pr.F, forms=fc.FC_FORM_FP32 | fc.FC_FORM_SPLIT_FP16)
+        grids.append((pr, g))
+    log(f"[bench] serving: generating {n_req} requests")
+    reqs = serving_requests(grids, n_req)
+    # plain capacity: the first 40 requests back to back
+    n_cap = min(40, n_req)
+    lat, wall, _ = run_plain(fc, grids, reqs[:n_cap], [0.0] * n_cap)
+    capacity = n_cap / wall
+    out = {"requests": n_req, "grids": ["20x20 N=38", "100x100 N=57", "60^3 N=57"],
+           "K": "log-uniform [500, 20000]", "plain_capacity_req_s": capacity, "loads": {}}
+    rng = fcgen.rng_for(4, 3, 1)
+    gaps = rng.exponential(1.0, size=n_req)
+    for load in loads:
+        lam = load * capacity
+        arrivals = np.cumsum(gaps / lam) - gaps[0] / lam
+        log(f"[bench] serving load {load}: lambda {lam:.1f}/s")
+        res = {"lambda_req_s": lam}
+        lat, wall, ev = run_plain(fc, grids, reqs, arrivals)
+        res["plain_fp32"] = summarize(lat, wall, ev, n_req)
+        for name, form, policy in (
+                ("batched_fp32_fifo", fc.FC_FORM_FP32, fc.FC_SCHED_FIFO),
+                ("batched_fp32_fair", fc.FC_FORM_FP32, fc.FC_SCHED_FAIR),
+                ("batched_split_fp16_fifo", fc.FC_FORM_SPLIT_FP16, fc.FC_SCHED_FIFO)):
+            lat, wall, ev, launches = run_batched(fc, grids, reqs, arrivals, form, policy)
+            res[name] = summarize(lat, wall, ev, n_req)
+            res[name]["launches"] = launches
+        out["loads"][str(load)] = res
+    for _, g in grids:
+        g.destroy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +218,10 @@ def main():
     ap.add_argument("--cpu-per-point", type=int, default=100,
                     help="universes per true point in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests in the serving leg (0 to skip it)")
+    ap.add_argument("--serving-loads", default="0.8",
+                    help="comma-separated arrival rates as fractions of the plain capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the scan is "
@@ -182,6 +321,9 @@ def main():
         res["cpu_baseline"] = base
         res["err_vs_fp64"] = rep
     grid.destroy()
+    if args.serving_requests > 0:
+        res["serving"] = serving_bench(args.serving_requests,
+                                       tuple(float(x) for x in args.serving_loads.split(",")))
     print(json.dumps(res))
 
 

@@ -219,6 +219,11 @@ const char *fc_last_error(void);
  * ------------------------------------------------------------------------ */
 typedef struct fc_server fc_server; /* opaque, library-owned */
 
+enum fc_server_policy {
+    FC_SCHED_FAIR = 0,  /* every admitted request gets a slice of each launch (round robin) */
+    FC_SCHED_FIFO = 1   /* the oldest request takes all it can use, younger ones backfill   */
+};
+
 enum fc_request_state {
     FC_REQ_QUEUED = 0,   /* waiting for device memory                  */
     FC_REQ_RUNNING = 1,  /* admitted; items queued or running          */
@@ -239,11 +244,13 @@ enum fc_request_state {
  *   n_alpha, alpha, n_bins, hist_hi   critical-value settings applied to every
  *                request (as in fc_critical_value; n_bins >= 1)
  *   launch_evals target (universe x grid point) evaluations per batched
- *                launch; 0 selects a default of 1.5e8
+ *                launch; 0 selects a default (1.5e8 FP32, 4.5e8 split forms)
+ *   policy       FC_SCHED_FAIR or FC_SCHED_FIFO: how a launch's work is shared
+ *                among the admitted requests
  */
 int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_grids, int32_t form,
                      size_t hbm_budget, size_t host_budget, int32_t n_alpha, const double *alpha,
-                     int32_t n_bins, double hist_hi, double launch_evals);
+                     int32_t n_bins, double hist_hi, double launch_evals, int32_t policy);
 
 /*
  * fc_server_submit -- queue one request (returns at once).

@@ -150,6 +150,7 @@ struct fc_server {
     double alpha[8] = {0};
     double hist_hi = 0.0;
     double launch_evals = 0.0;
+    int policy = FC_SCHED_FAIR;
     // memory
     void *dev_base = nullptr;
     void *host_base = nullptr;
@@ -268,8 +269,9 @@ bool fc_server::launch(Cls &c)
     {
         std::lock_guard<std::mutex> lk(mu);
         const size_t na = c.active.size();
+        const size_t start = (policy == FC_SCHED_FAIR) ? c.rr : 0;  // FIFO: oldest first
         for (size_t k = 0; k < na; ++k) {
-            Req *r = reqs.at(c.active[(c.rr + k) % na]).get();
+            Req *r = reqs.at(c.active[(start + k) % na]).get();
             if (r->state == FC_REQ_RUNNING && !r->finishing) order.push_back(r);
         }
         if (na) c.rr = (c.rr + 1) % na;
@@ -280,10 +282,13 @@ bool fc_server::launch(Cls &c)
     int n = 0;
     double budget = launch_evals, scheduled = 0.0;
     std::vector<Req *> completing;
+    // FAIR: one range of grid points per request per round; FIFO: a request
+    // takes ranges until it is fully scheduled before the next one is served
     bool any = true;
     while (any && budget > 0.0 && n < kMaxItems) {
         any = false;
-        for (Req *r : order) {
+        for (size_t oi = 0; oi < order.size(); ++oi) {
+            Req *r = order[oi];
             const fc_grid *g = grids[r->grid];
             if (r->q_next >= g->G) continue;
             const int64_t ntiles = (r->K + c.upi - 1) / c.upi;
@@ -313,6 +318,7 @@ bool fc_server::launch(Cls &c)
             any = true;
             if (r->q_next >= g->G) completing.push_back(r);
             if (budget <= 0.0 || n >= kMaxItems) break;
+            if (policy == FC_SCHED_FIFO && r->q_next < g->G) --oi;  // stay on this request
         }
     }
     if (n == 0) return false;
@@ -466,7 +472,7 @@ extern "C" {
 
 int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_grids, int32_t form,
                      size_t hbm_budget, size_t host_budget, int32_t n_alpha, const double *alpha,
-                     int32_t n_bins, double hist_hi, double launch_evals)
+                     int32_t n_bins, double hist_hi, double launch_evals, int32_t policy)
 {
     if (!out) return fail(FC_ERR_INVALID_ARG, "fc_server_create: out is NULL");
     *out = nullptr;
@@ -484,6 +490,8 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
     if (hbm_budget < (size_t(1) << 20) || host_budget < (size_t(1) << 20))
         return fail(FC_ERR_INVALID_ARG, "fc_server_create: budgets must be >= 1 MiB");
     if (!(launch_evals >= 0.0)) return fail(FC_ERR_INVALID_ARG, "fc_server_create: launch_evals");
+    if (policy != FC_SCHED_FAIR && policy != FC_SCHED_FIFO)
+        return fail(FC_ERR_INVALID_ARG, "fc_server_create: bad policy %d", policy);
     for (int i = 0; i < n_grids; ++i) {
         if (!grids[i]) return fail(FC_ERR_INVALID_ARG, "fc_server_create: grid %d is NULL", i);
         if (!(grids[i]->forms & (uint32_t)form))
@@ -498,6 +506,7 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
     s->n_bins = n_bins;
     s->hist_hi = hist_hi;
     s->launch_evals = launch_evals > 0.0 ? launch_evals : (form == FC_FORM_FP32 ? 1.5e8 : 4.5e8);
+    s->policy = policy;
     s->grids.assign(grids, grids + n_grids);
     // one class per distinct kernel geometry
     for (int i = 0; i < n_grids; ++i) {

@@ -33,6 +33,9 @@ FC_STAT_FIXED = 1
 
 FC_MAX_BINS = 64
 
+FC_SCHED_FAIR = 0
+FC_SCHED_FIFO = 1
+
 FC_REQ_QUEUED = 0
 FC_REQ_RUNNING = 1
 FC_REQ_DONE = 2
@@ -78,7 +81,7 @@ def lib():
         L.fc_last_error.argtypes = []
         L.fc_last_error.restype = ctypes.c_char_p
         L.fc_server_create.argtypes = [ctypes.POINTER(_p), _p, _i32, _i32, ctypes.c_size_t,
-                                       ctypes.c_size_t, _i32, _p, _i32, _dbl, _dbl]
+                                       ctypes.c_size_t, _i32, _p, _i32, _dbl, _dbl, _i32]
         L.fc_server_submit.argtypes = [_p, _i32, _i64, _i64, _p, _p]
         L.fc_server_poll.argtypes = [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _i32]
         L.fc_server_stats.argtypes = [_p, _p, _p, _p, _p]
@@ -245,7 +248,8 @@ class Server:
     """
 
     def __init__(self, grids, form=FC_FORM_FP32, hbm_budget=8 << 30, host_budget=2 << 30,
-                 alpha=(0.6827, 0.9, 0.95), n_bins=200, hist_hi=50.0, launch_evals=0.0):
+                 alpha=(0.6827, 0.9, 0.95), n_bins=200, hist_hi=50.0, launch_evals=0.0,
+                 policy=FC_SCHED_FAIR):
         self.grids = list(grids)
         self.alpha = np.ascontiguousarray(alpha, dtype=np.float64)
         self.n_bins = int(n_bins)
@@ -255,7 +259,7 @@ class Server:
         _check(lib().fc_server_create(ctypes.byref(out), handles, len(self.grids), int(form),
                                       int(hbm_budget), int(host_budget), len(self.alpha),
                                       _hp(self.alpha), self.n_bins, float(hist_hi),
-                                      float(launch_evals)))
+                                      float(launch_evals), int(policy)))
         self.handle = out.value
         self.K = {}
 

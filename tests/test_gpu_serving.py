@@ -95,12 +95,13 @@ def wait_all(server, ids, timeout=180.0):
     return res
 
 
-@pytest.mark.parametrize("form_name", ["fp32", "split_fp16"])
-def test_mix_equals_alone(fc, grids, form_name):
+@pytest.mark.parametrize("form_name,policy", [("fp32", 0), ("split_fp16", 0), ("fp32", 1),
+                                             ("split_fp16", 1)])
+def test_mix_equals_alone(fc, grids, form_name, policy):
     form = {"fp32": fc.FC_FORM_FP32, "split_fp16": fc.FC_FORM_SPLIT_FP16}[form_name]
     server = fc.Server([g for _, g in grids], form=form, hbm_budget=512 << 20,
                        host_budget=512 << 20, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI,
-                       launch_evals=2e7)
+                       launch_evals=2e7, policy=policy)
     reqs = make_requests(grids, 36, 300, 3000, seed=1)
     ids = []
     # arrivals spread out so that later requests join while earlier ones run
