@@ -177,6 +177,33 @@ int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2
                       double hist_hi, int64_t *hist, hipStream_t stream);
 
 /*
+ * fc_data_scan -- the observed-data statistic (Section 1: the scan looks for
+ * the points compatible with the central data vector c; Algorithm 1's inner
+ * loop run once with c as the data):
+ *     dchi2_data[q] = chi2(c, q) - min_q' chi2(c, q')     for every q,
+ * in FP64 with the FP64 factor (needs FC_FORM_FP64, else FC_ERR_STATE).
+ *   central    host [N] FP64, or NULL for the vector given to fc_build_grid
+ *              (FC_ERR_STATE if there is none)
+ *   dchi2_data device out [G] FP64
+ *   chi2_min   host out: the minimum over the grid (NaN if every chi2 is NaN)
+ *   argmin     host out: the lowest q reaching it (-1 if all chi2 are NaN)
+ * Synchronises `stream`.
+ */
+int fc_data_scan(const fc_grid *g, const double *central, double *dchi2_data, double *chi2_min,
+                 int64_t *argmin, hipStream_t stream);
+
+/*
+ * fc_acceptance -- Feldman-Cousins acceptance of true points (Section 1):
+ *     accepted[k] = dchi2_data[p[k]] <= crit[k * crit_stride]
+ * (asynchronous).  p device [n_pts] int64 (outside [0, G): not accepted),
+ * crit device (e.g. one column of fc_critical_value's output, stride n_alpha),
+ * dchi2_data device [G] from fc_data_scan, accepted device out [n_pts] uint8.
+ */
+int fc_acceptance(const fc_grid *g, int64_t n_pts, const int64_t *p, const double *crit,
+                  int64_t crit_stride, const double *dchi2_data, uint8_t *accepted,
+                  hipStream_t stream);
+
+/*
  * fc_grid_inverse_cov -- write Sigma_q^{-1} = W_q^T W_q (FP64, from the FP64
  * factor) for q = q0 .. q0+nq-1 into device out [nq][N][N] (asynchronous).
  * Needs FC_FORM_FP64 built (else FC_ERR_STATE).

@@ -13,6 +13,8 @@ Functions follow arXiv:2002.07858:
   chi2                   -- Eq. (1) / Algorithm 2, as ||L^{-1}(a-b)||^2
   scan                   -- Algorithm 1 (strict-< running minimum, Delta chi^2)
   critical_value         -- Section 1 / Figure 1 (quantiles of Delta chi^2)
+  data_scan / acceptance -- Section 1 (Delta chi^2 of the observed data at every
+                            point, accepted where it is within the critical value)
 """
 from __future__ import annotations
 
@@ -201,6 +203,37 @@ def chi2_table(S, F, d, stat_mode=STAT_PEARSON, stat_diag=None, nthreads=None) -
     out = np.empty((K, G))
     if lib().fco_chi2_table(G, N, _ptr(S), _ptr(Lall), K, _ptr(d), _ptr(out), nt) != 0:
         raise OracleError("bad table arguments")
+    return out
+
+
+def data_scan(S, F, c, stat_mode=STAT_PEARSON, stat_diag=None, nthreads=None):
+    """Delta chi^2 of one data vector c at every grid point (Section 1).
+
+    chi^2(c, q) by Eq. (1) for every q, the minimum over the grid with
+    Algorithm 1's tie rule (the lowest q among equal values; NaN never wins),
+    and dchi2[q] = chi^2(c, q) - minimum.  Returns (dchi2 [G], chi2_min,
+    argmin); with every chi^2 NaN there is no minimum: NaN, NaN and -1.
+    """
+    t = chi2_table(S, F, _f64(c)[None, :], stat_mode, stat_diag, nthreads)[0]
+    ok = ~np.isnan(t)
+    if not ok.any():
+        return np.full_like(t, np.nan), float("nan"), -1
+    m = float(t[ok].min())
+    arg = int(np.flatnonzero(t == m)[0])
+    return t - m, m, arg
+
+
+def acceptance(dchi2_data, p, crit):
+    """Feldman-Cousins acceptance (Section 1): true point p[k] is in the region
+    when the data's Delta chi^2 there is not above its critical value crit[k].
+    Points outside the grid, and NaN on either side, are not accepted."""
+    dd = _f64(dchi2_data)
+    p = np.asarray(p, dtype=np.int64)
+    crit = _f64(crit)
+    out = np.zeros(p.shape[0], dtype=np.uint8)
+    for k in range(p.shape[0]):
+        if 0 <= p[k] < dd.shape[0] and dd[p[k]] <= crit[k]:
+            out[k] = 1
     return out
 
 

@@ -326,6 +326,65 @@ int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2
     return FC_OK;
 }
 
+int fc_data_scan(const fc_grid *g, const double *central, double *dchi2_data, double *chi2_min,
+                 int64_t *argmin, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_data_scan: grid is NULL");
+    if (!dchi2_data || !chi2_min || !argmin)
+        return fail(FC_ERR_INVALID_ARG, "fc_data_scan: NULL output");
+    if (!(g->forms & FC_FORM_FP64)) return fail(FC_ERR_STATE, "fc_data_scan: FP64 form not built");
+    const double *c = central ? central : (g->central.empty() ? nullptr : g->central.data());
+    if (!c) return fail(FC_ERR_STATE, "fc_data_scan: no central data vector");
+    double *dc = nullptr;
+    unsigned long long *scratch = nullptr;
+    unsigned long long hs[2] = {0, 0};
+    hipError_t e;
+    if ((e = hipMalloc(&dc, sizeof(double) * g->N)) != hipSuccess ||
+        (e = hipMalloc(&scratch, sizeof(unsigned long long) * 2)) != hipSuccess ||
+        (e = hipMemcpyAsync(dc, c, sizeof(double) * g->N, hipMemcpyHostToDevice, stream)) !=
+            hipSuccess ||
+        (e = fcx::launch_data_scan(g, dc, dchi2_data, scratch, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(hs, scratch, sizeof(hs), hipMemcpyDeviceToHost, stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess) {
+        if (dc) (void)hipFree(dc);
+        if (scratch) (void)hipFree(scratch);
+        return hip_fail(e, "fc_data_scan");
+    }
+    (void)hipFree(dc);
+    (void)hipFree(scratch);
+    // decode the ordered key of the minimum
+    if (hs[0] == ~0ull) {
+        *chi2_min = NAN;
+        *argmin = -1;
+    } else {
+        const unsigned long long b = (hs[0] >> 63) ? (hs[0] & 0x7fffffffffffffffull) : ~hs[0];
+        double v;
+        memcpy(&v, &b, sizeof(v));
+        *chi2_min = v;
+        *argmin = (int64_t)hs[1];
+    }
+    return FC_OK;
+}
+
+int fc_acceptance(const fc_grid *g, int64_t n_pts, const int64_t *p, const double *crit,
+                  int64_t crit_stride, const double *dchi2_data, uint8_t *accepted,
+                  hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_acceptance: grid is NULL");
+    if (n_pts < 0 || crit_stride < 1)
+        return fail(FC_ERR_INVALID_ARG, "fc_acceptance: bad n_pts or crit_stride");
+    if (n_pts == 0) return FC_OK;
+    if (!p || !crit || !dchi2_data || !accepted)
+        return fail(FC_ERR_INVALID_ARG, "fc_acceptance: NULL device pointer");
+    hipError_t e = fcx::launch_accept(n_pts, p, crit, crit_stride, dchi2_data, g->G, accepted,
+                                      stream);
+    if (e != hipSuccess) return hip_fail(e, "fc_acceptance");
+    return FC_OK;
+}
+
 int fc_grid_inverse_cov(const fc_grid *g, int64_t q0, int64_t nq, double *out, hipStream_t stream)
 {
     g_last_error.clear();

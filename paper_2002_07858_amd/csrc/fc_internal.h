@@ -207,6 +207,11 @@ int serve_split_univ_per_item();
 int serve_slots_fp32(int ns);
 int serve_slots_split(int nk, int nb, bool fp16);
 
+hipError_t launch_data_scan(const fc_grid *g, const double *c, double *chi2,
+                            unsigned long long *scratch, hipStream_t st);
+hipError_t launch_accept(int64_t n_pts, const int64_t *p, const double *crit, int64_t stride,
+                         const double *dchi2_data, int64_t G, uint8_t *accepted, hipStream_t st);
+
 // Scan launch geometry chosen by the host: universe tiles x grid chunks.
 struct ScanGeometry {
     int64_t n_utiles = 0;

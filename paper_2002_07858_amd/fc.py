@@ -42,8 +42,8 @@ FC_REQ_DONE = 2
 FC_REQ_FAILED = -1
 
 EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
-            "fc_grid_inverse_cov", "fc_grid_info", "fc_grid_device_bytes", "fc_grid_destroy",
-            "fc_last_error", "fc_server_create", "fc_server_submit", "fc_server_poll",
+            "fc_data_scan", "fc_acceptance", "fc_grid_inverse_cov", "fc_grid_info",
+            "fc_grid_device_bytes", "fc_grid_destroy", "fc_last_error", "fc_server_create", "fc_server_submit", "fc_server_poll",
             "fc_server_stats", "fc_server_destroy")
 
 
@@ -72,6 +72,8 @@ def lib():
         L.fc_build_covariance.argtypes = [_p, _p, _i32, _p, _u32, _p, _p]
         L.fc_scan.argtypes = [_p, _i32, _i64, _p, _p, _p, _p, _p, _p, _p]
         L.fc_critical_value.argtypes = [_i64, _p, _p, _i32, _p, _p, _i32, _dbl, _p, _p]
+        L.fc_data_scan.argtypes = [_p, _p, _p, _p, _p, _p]
+        L.fc_acceptance.argtypes = [_p, _i64, _p, _p, _i64, _p, _p, _p]
         L.fc_grid_inverse_cov.argtypes = [_p, _i64, _i64, _p, _p]
         L.fc_grid_info.argtypes = [_p, _p, _p, _p, _p]
         L.fc_grid_device_bytes.argtypes = [_p]
@@ -90,7 +92,7 @@ def lib():
         for name in ("fc_server_create", "fc_server_submit", "fc_server_poll", "fc_server_stats"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
-                     "fc_grid_inverse_cov", "fc_grid_info"):
+                     "fc_data_scan", "fc_acceptance", "fc_grid_inverse_cov", "fc_grid_info"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -118,7 +120,7 @@ def _dev(t, dtype_name: str, name: str):
     if t is None:
         return None
     import torch
-    want = {"f64": torch.float64, "i64": torch.int64}[dtype_name]
+    want = {"f64": torch.float64, "i64": torch.int64, "u8": torch.uint8}[dtype_name]
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a torch CUDA tensor")
     if t.dtype != want:
@@ -215,6 +217,28 @@ def fc_critical_value(seg_off, dchi2, alpha, crit, n_bins=200, hist_hi=50.0, his
                                    _dev(dchi2, "f64", "dchi2"), int(a.shape[0]), _hp(a),
                                    _dev(crit, "f64", "crit"), int(n_bins), float(hist_hi),
                                    _dev(hist, "i64", "hist"), _stream(stream)))
+
+
+def fc_data_scan(grid: Grid, dchi2_data, central=None, stream=None):
+    """Delta chi2 of the data vector at every grid point (synchronous).
+
+    ``dchi2_data`` is a float64 CUDA tensor [G]; ``central`` a host vector [N]
+    or None for the grid's own.  Returns (chi2_min, argmin).
+    """
+    c = None if central is None else _host(central, np.float64)
+    m = ctypes.c_double()
+    a = ctypes.c_int64()
+    _check(lib().fc_data_scan(grid._h, _hp(c), _dev(dchi2_data, "f64", "dchi2_data"),
+                              ctypes.byref(m), ctypes.byref(a), _stream(stream)))
+    return m.value, a.value
+
+
+def fc_acceptance(grid: Grid, p, crit, dchi2_data, accepted, crit_stride=1, stream=None):
+    """Enqueue accepted[k] = dchi2_data[p[k]] <= crit[k * crit_stride] (CUDA tensors)."""
+    n = int(p.numel())
+    _check(lib().fc_acceptance(grid._h, n, _dev(p, "i64", "p"), _dev(crit, "f64", "crit"),
+                               int(crit_stride), _dev(dchi2_data, "f64", "dchi2_data"),
+                               _dev(accepted, "u8", "accepted"), _stream(stream)))
 
 
 def fc_grid_inverse_cov(grid: Grid, q0: int, nq: int, out, stream=None):

@@ -353,3 +353,63 @@ def test_grid_linearisation_last_axis_fastest():
     ref = [(a, b, c) for a in axes[0] for b in axes[1] for c in axes[2]]
     assert seen == ref
     np.testing.assert_array_equal(fcgen.grid_points(axes), np.array(ref))
+
+
+# --------------------------------------------------------------------------
+# P11: the observed-data statistic and the acceptance region (Section 1)
+# --------------------------------------------------------------------------
+def test_p11_data_scan_exact_rational():
+    S, F, d, _ = _p1_problem()
+    Sn = np.array(S, dtype=np.float64)
+    Fn = np.array([[float(x) for x in row] for row in F])
+    Minv = [exact_fc.inverse(exact_fc.covariance(Sq, F)) for Sq in S]
+    for c in d:
+        exact = [exact_fc.chi2(c, Sq, M) for Sq, M in zip(S, Minv)]
+        best = min(exact)
+        arg = exact.index(best)                 # lowest q among exact ties
+        dd, cmin, am = oracle.data_scan(Sn, Fn, np.array(c, dtype=np.float64))
+        assert am == arg
+        assert abs(cmin - float(best)) <= 1e-14 * max(1.0, float(best))
+        for q in range(len(S)):
+            assert abs(dd[q] - float(exact[q] - best)) <= 1e-14 * max(1.0, float(exact[q]))
+    # c on the duplicated rows 2 == 5: chi^2 = 0 at both, q = 2 is the minimiser
+    dd, cmin, am = oracle.data_scan(Sn, Fn, Sn[5])
+    assert am == 2 and cmin == 0.0 and dd[2] == 0.0 and dd[5] == 0.0
+
+
+def test_p11_data_scan_all_nan():
+    pr = fcgen.make_problem("c1", K=1, true_subset=[0], n_axis=(4, 4))
+    c = pr.S[3].copy()
+    c[7] = np.nan
+    dd, cmin, am = oracle.data_scan(pr.S, pr.F, c)
+    assert am == -1 and math.isnan(cmin) and np.isnan(dd).all()
+
+
+def test_p11_acceptance_boundary_and_range():
+    dd = np.array([0.0, 1.5, 2.0, np.nan])
+    acc = oracle.acceptance(dd, [0, 1, 2, 3, 4, -1], [0.0, 1.4, 2.0, 10.0, 10.0, 10.0])
+    # equal is accepted, above is not, NaN and points off the grid are not
+    assert acc.tolist() == [1, 0, 1, 0, 0, 0]
+
+
+def test_p11_coverage_of_the_acceptance_region():
+    """Feldman-Cousins coverage: data drawn at the true point p fall inside the
+    region (Delta chi^2_data(p) <= x_alpha(p)) with probability alpha, because
+    the critical value is the alpha-quantile of the same statistic over
+    universes drawn at p.  A region built on chi^2 instead of Delta chi^2, a
+    wrong minimiser or the wrong quantile moves the fraction far from alpha."""
+    pr = fcgen.make_problem("c1", K=2000, true_subset=[0], n_axis=(10, 10))
+    p = int(pr.true_pts[0])
+    alpha = (0.6827, 0.9)
+    r = oracle.scan(pr.S, pr.F, pr.d, pr.p_idx)
+    crit, _ = oracle.critical_value(r["dchi2"], pr.seg_off, alpha, with_hist=False)
+    M = 300
+    data = fcgen.universes(pr.config, 10_000, pr.S[p], pr.F, M)
+    hits = np.zeros(len(alpha))
+    for m in range(M):
+        dd, _, _ = oracle.data_scan(pr.S, pr.F, data[m])
+        for a in range(len(alpha)):
+            hits[a] += oracle.acceptance(dd, [p], [crit[0, a]])[0]
+    for a, al in enumerate(alpha):
+        sigma = math.sqrt(al * (1 - al) / M + al * (1 - al) / 2000)
+        assert abs(hits[a] / M - al) <= 4 * sigma, (al, hits[a] / M)
