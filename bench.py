@@ -1,12 +1,15 @@
 """Benchmark of the FC grid-scan hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--form fp32] [--serving-requests R]
+    python bench.py [--steps K] [--warmup W] [--form fp32] [--workload c2]
+                    [--serving-requests R] [--copy-probe-mib M]
 
-Workload: D = 2 grid 100 x 100 (G = 10^4), N = 57 bins, 256 true points x
-2000 universes (512 000 universes, 5.12e9 universe x grid-point chi^2
+Default workload (c2): D = 2 grid 100 x 100 (G = 10^4), N = 57 bins, 256 true
+points x 2000 universes (512 000 universes, 5.12e9 universe x grid-point chi^2
 evaluations per step), FP32 scan, 0.6827 / 0.90 / 0.95 critical values and a
-200-bin histogram per true point.  Inputs are seeded synthetic data from the
-toy oscillation model, resident in HBM before the timed region.
+200-bin histogram per true point.  The other workloads: c1 (D = 2 20 x 20,
+N = 38, one true point x 1000 universes, FP64), c3 (D = 3 60^3, N = 57, 64 x
+4000) and c5 (D = 5 16^5, N = 57, 16 x 10 000).  Inputs are seeded synthetic
+data from the toy oscillation model, resident in HBM before the timed region.
 
 One step = covariance factors for every grid point (FP64 Cholesky + inverse,
 stored in the scan form) + the scan of all universes (minimum, argmin,
@@ -50,6 +53,51 @@ def split_flop_per_eval(N: int) -> int:
     return 3 * N * (N + 1)
 
 
+WORKLOADS = {
+    "c1": dict(desc="c1: D=2 grid 20x20 (G=400), N=38, 1 true point x 1000 universes",
+               steps=10, warmup=2, cpu_per_point=1000, serving=0),
+    "c2": dict(desc="c2: D=2 grid 100x100 (G=10000), N=57, 256 true points x 2000 universes",
+               steps=10, warmup=2, cpu_per_point=100, serving=200),
+    "c3": dict(desc="c3: D=3 grid 60^3 (G=216000), N=57, 64 true points x 4000 universes",
+               steps=3, warmup=1, cpu_per_point=8, serving=0),
+    "c5": dict(desc="c5: D=5 grid 16^5 (G=1048576), N=57, 16 true points x 10000 universes",
+               steps=2, warmup=1, cpu_per_point=4, serving=0),
+}
+
+# HBM traffic of the scan kernel per launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by the same counters over a copy of known size
+# (the profiles directory holds the summaries).  Valid only while the kernel
+# sources hash to the value the counters were taken with.
+TRAFFIC = {}
+TRAFFIC_SOURCES = ("paper_2002_07858_amd/csrc/k_scan.hip",
+                   "paper_2002_07858_amd/csrc/k_scan_split.hip",
+                   "paper_2002_07858_amd/csrc/fc_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def copy_probe(mib: int):
+    """A plain device-to-device copy of known size, for counter calibration."""
+    import torch
+    n = (mib << 20) // 4
+    x = torch.arange(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    assert bool((y[-16:] == x[-16:]).all())
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "launches": 3}))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -59,10 +107,11 @@ def cpu_baseline(pr, per_point: int, dev_out: dict, tol: float):
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import parity
-    idx = []
+    idx, seg = [], [0]
     for s in range(len(pr.seg_off) - 1):
-        lo = int(pr.seg_off[s])
-        idx += list(range(lo, lo + per_point))
+        lo, hi = int(pr.seg_off[s]), int(pr.seg_off[s + 1])
+        idx += list(range(lo, min(hi, lo + per_point)))
+        seg.append(len(idx))
     idx = np.array(idx)
     nt = oracle.default_threads()
     t0 = time.perf_counter()
@@ -70,8 +119,12 @@ def cpu_baseline(pr, per_point: int, dev_out: dict, tol: float):
     dt = time.perf_counter() - t0
     evals = len(idx) * pr.G
     rep = parity.report({k: v[idx] for k, v in dev_out.items()}, ref, tol)
+    # critical values of the sampled universes, device values vs oracle values
+    c_dev, _ = oracle.critical_value(dev_out["dchi2"][idx], seg, ALPHA, with_hist=False)
+    c_ref, _ = oracle.critical_value(ref["dchi2"], seg, ALPHA, with_hist=False)
+    rep["crit_abs_err_sample"] = float(np.abs(c_dev - c_ref).max())
     base = {"value": evals / dt, "unit": "evals/s", "cores": nt, "kind": "oracle",
-            "sample": f"first {per_point} universes of each of the {len(pr.seg_off) - 1} true "
+            "sample": f"first {min(per_point, int(pr.seg_off[1]))} universes of each of the {len(pr.seg_off) - 1} true "
                       f"points x all {pr.G} grid points ({evals:.3g} evals, {dt:.1f} s, "
                       f"FP64 Cholesky + forward substitution)"}
     return base, rep
@@ -212,17 +265,32 @@ def serving_bench(n_req: int, loads=(0.8,)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", default="fp32", choices=["fp32", "fp64", "split_bf16", "split_fp16"])
-    ap.add_argument("--cpu-per-point", type=int, default=100,
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--form", default=None, choices=["fp32", "fp64", "split_bf16", "split_fp16"],
+                    help="scan form (default fp32; fp64 for c1)")
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-per-point", type=int, default=None,
                     help="universes per true point in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=200,
-                    help="requests in the serving leg (0 to skip it)")
-    ap.add_argument("--serving-loads", default="0.8",
+    ap.add_argument("--serving-requests", type=int, default=None,
+                    help="requests in the serving leg (0 to skip it; default 200 for c2)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device copy of this size (counter calibration)")
+    ap.add_argument("--serving-loads", default="0.5,0.8",
                     help="comma-separated arrival rates as fractions of the plain capacity")
     args = ap.parse_args()
+    wl = WORKLOADS[args.workload]
+    if args.steps is None:
+        args.steps = wl["steps"]
+    if args.warmup is None:
+        args.warmup = wl["warmup"]
+    if args.form is None:
+        args.form = "fp64" if args.workload == "c1" else "fp32"
+    if args.cpu_per_point is None:
+        args.cpu_per_point = wl["cpu_per_point"]
+    if args.serving_requests is None:
+        args.serving_requests = wl["serving"]
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the scan is "
               "single-GPU by design; see the multi-GPU section of the design notes.",
@@ -234,12 +302,15 @@ def main():
     import paper_2002_07858_amd as fc
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        copy_probe(args.copy_probe_mib)
+        return
     fc.lib()
     form = {"fp32": fc.FC_FORM_FP32, "fp64": fc.FC_FORM_FP64, "split_bf16": fc.FC_FORM_SPLIT_BF16,
             "split_fp16": fc.FC_FORM_SPLIT_FP16}[args.form]
 
-    log("[bench] generating c2 inputs")
-    pr = fcgen.make_problem("c2")
+    log(f"[bench] generating {args.workload} inputs")
+    pr = fcgen.make_problem(args.workload)
     G, N, K = pr.G, pr.N, pr.K
     dev = torch.device("cuda")
     d_t = torch.as_tensor(pr.d).to(dev)
@@ -277,6 +348,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    first = None
     times = {"cov": [], "scan": [], "crit": []}
     log(f"[bench] timing {args.steps} steps")
     torch.cuda.synchronize()
@@ -284,6 +356,8 @@ def main():
     for i in range(args.steps):
         step(times)
         log(f"[bench] step {i}: scan {times['scan'][-1]:.2f} ms")
+        if first is None:
+            first = (outs["dchi2"].clone(), outs["argmin"].clone(), crit.clone())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
@@ -297,23 +371,31 @@ def main():
     roofline = {"bound": "alu" if args.form == "fp64" else "mfma", "achieved": achieved / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None}
+    tr = TRAFFIC.get((args.workload, args.form))
+    if tr is not None and tr["source_hash"] == kernel_source_hash():
+        roofline["traffic"] = tr["bytes_per_launch"]
+        roofline["traffic_GBps"] = tr["bytes_per_launch"] / (scan_ms * 1e-3) / 1e9
+        roofline["traffic_source"] = tr["profile"]
     if split:
         fp32_equiv = evals * fpe / (scan_ms * 1e-3)
         roofline["fp32_equivalent"] = {"achieved": fp32_equiv / 1e12, "peak": PEAK["fp32"] / 1e12,
                                        "frac": fp32_equiv / PEAK["fp32"]}
 
+    deterministic = bool(torch.equal(first[0], outs["dchi2"]) and
+                         torch.equal(first[1], outs["argmin"]) and
+                         torch.equal(first[2], crit)) if first is not None else None
     dev_out = {k: v.cpu().numpy() for k, v in outs.items()}
     res = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": DTYPE[args.form], "data": "synthetic",
-           "config": {"workload": "c2: D=2 grid 100x100 (G=10000), N=57, 256 true points x "
-                                  "2000 universes, per-point FP64 covariance factor, "
+           "config": {"workload": wl["desc"] + ", per-point FP64 covariance factor, "
                                   f"{args.form} scan, crit at 0.6827/0.9/0.95 + 200-bin hist",
                       "G": G, "N": N, "K_total": K, "evals_per_step": evals,
                       "form": args.form, "parallelism": "single-gpu"},
            "phases_ms": {k: float(np.mean(v)) for k, v in times.items()},
            "scan_evals_per_s": evals / (scan_ms * 1e-3),
+           "bitwise_deterministic": deterministic,
            "roofline": roofline}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")

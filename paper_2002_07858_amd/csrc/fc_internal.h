@@ -29,14 +29,16 @@
 // Per grid point the pairs are stored lane-major in groups of four,
 //     W[t/4][lane][t%4]                (ng = ceil(npair/4) groups of 1 KB)
 // so that every lane fetches its next four A values with one 16-byte access
-// and a wave reads 1 KB contiguously.  They are followed by the signal as an
-// unevaluated FP32 pair (S = hi + lo to 48 bits) in the lane order of the B
-// operand,
-//     Sh[g][s] = float(S_q[4s+g]),  Sl[g][s] = float(S_q[4s+g] - Sh[g][s])
-//     (g = 0..3, s = 0..15, zero past N; 256 B each)
-// so that the residual (dh - Sh) + (dl - Sl) carries an error relative to the
-// residual itself, with FP32 instructions only, and by zero padding up to a
-// whole number of 4 KB (256 x 16 B) pieces: one grid point's record is
+// and a wave reads 1 KB contiguously.  They are followed by the signal's FP32
+// part in the lane order of the B operand and by the W-image of its rounding
+// error in the lane order of the accumulators,
+//     Sh[g][s] = float(S_q[4s+g])                (g = 0..3, s = 0..15)
+//     C[e]     = float(-sum_k W_q[e-r0][k] (S_q[k] - Sh[k]))   (e = 0..63)
+// (zero past N / outside the real rows; 256 B each).  With d = dh + dl split
+// the same way, W_q (d - S_q) = W_q ((dh - Sh) + dl) + C up to rounding, so the
+// residual costs two FP32 instructions, its error is relative to the residual
+// itself, and C is the accumulators' initial value.  Zero padding follows up
+// to a whole number of 4 KB (256 x 16 B) pieces: one grid point's record is
 // rec_units(ns) 16-byte units, which the scan's 256 threads copy with the same
 // number of unpredicated loads each.
 // ---------------------------------------------------------------------------

@@ -181,15 +181,19 @@ __global__ __launch_bounds__(64) void k_cov_build(
                 for (int z = slot; z < 4; ++z) vals[z] = 0.0f;
                 Wq[gi * 64 + i] = make_float4(vals[0], vals[1], vals[2], vals[3]);
             }
-            // signal as an FP32 pair in B-operand lane order: element g*16 + s
-            // holds S_q[4s + g]
+            // FP32 part of the signal in B-operand lane order (element g*16 + s
+            // holds S_q[4s + g]); then, in accumulator order (element e is
+            // row e - r0), minus W_q times the signal's FP32 rounding error
             float *Sp = reinterpret_cast<float *>(rq + wu);
             {
                 const int g4 = i >> 4, s16 = i & 15, k = 4 * s16 + g4;
-                const double sv = (k < N) ? Sq[k] : 0.0;
-                const float hi = (float)sv;
-                Sp[i] = hi;
-                Sp[64 + i] = (float)(sv - (double)hi);
+                Sp[i] = (k < N) ? (float)Sq[k] : 0.0f;
+                const int rr = i - r0;
+                double cv = 0.0;
+                if (rr >= 0 && rr < N)
+                    for (int kk = 0; kk <= rr; ++kk)
+                        cv -= Wc[rr * kLdsStride + kk] * (Sq[kk] - (double)(float)Sq[kk]);
+                Sp[64 + i] = (float)cv;
             }
             for (int u = wu + 32 + i; u < ru; u += 64) rq[u] = make_uint4(0u, 0u, 0u, 0u);
         }

@@ -31,7 +31,8 @@ __device__ __forceinline__ float pick(const float4 &v, int c)
 }
 
 // Per grid point the block stages one record in LDS: the W_q fragments (NG
-// groups of 1 KB) followed by S_q in FP64 lane order (512 B).  Records are
+// groups of 1 KB), the FP32 part of S_q in B-operand order (256 B) and the
+// correction C_q = -W_q (S_q - float(S_q)) in accumulator order (256 B).  Records are
 // double-buffered: while the waves contract grid point q from one buffer, the
 // block's 256 threads copy record q+1 into the other with coalesced 16-byte
 // loads, and one barrier per grid point hands the buffers over.
@@ -121,20 +122,24 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 (*buf)[Fp32G
 
         const float4 *wl = reinterpret_cast<const float4 *>(&buf[slot][0]);
         const float *shl = reinterpret_cast<const float *>(&buf[slot][NWU]) + grp * 16;
+        // accumulators start at C_q: rows 4 grp .. 4 grp + 3 of each row block
+        const float4 *cl = reinterpret_cast<const float4 *>(&buf[slot][NWU]) + 16 + grp;
         v4f acc[NC][NB];
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
+        for (int b = 0; b < NB; ++b) {
+            const float4 cv = cl[4 * b];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) acc[c][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int c = 0; c < NC; ++c) acc[c][b] = v4f{cv.x, cv.y, cv.z, cv.w};
+        }
 
         float4 wv = wl[lane];
         int wg_loaded = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const float sh = shl[s], sl = shl[64 + s];
+            const float sh = shl[s];
             float r[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) r[c] = (dh[c][s] - sh) + (dl[c][s] - sl);
+            for (int c = 0; c < NC; ++c) r[c] = (dh[c][s] - sh) + dl[c][s];
 #pragma unroll
             for (int b = first_block_of_kstep(NS, s); b < NB; ++b) {
                 const int t = pair_index(NS, s, b);

@@ -161,11 +161,14 @@ def test_edge_cases(fc):
     e = torch.empty(0, dtype=torch.float64, device="cuda")
     ei = torch.empty(0, dtype=torch.int64, device="cuda")
     fc.fc_scan(g, 2, torch.empty((0, pr.N), dtype=torch.float64, device="cuda"), ei, e, e, ei, e)
-    # unfluctuated universes at on-grid points: chi2_min = dchi2 = 0 exactly
+    # unfluctuated universes at on-grid points: Delta chi2 = 0 exactly, chi2_min
+    # = 0 exactly in FP64; in FP32 the minimum is the square of the rounding
+    # left between W (S - float(S)) and its stored FP32 image (~1e-13 per row)
     ps = np.array([0, 17, 382, 399, 200])
     for form in (1, 2):
         dev = run_scan(fc, g, form, pr.S[ps], ps)
-        assert np.all(dev["dchi2"] == 0.0) and np.all(dev["chi2_min"] == 0.0)
+        assert np.all(dev["dchi2"] == 0.0)
+        assert np.all(dev["chi2_min"] == 0.0) if form == 1 else np.all(dev["chi2_min"] <= 1e-20)
         np.testing.assert_array_equal(dev["argmin"], ps)
     # NaN data: that universe only gets (inf, p, NaN); an out-of-range p gives NaN
     d = pr.d.copy()
