@@ -44,11 +44,148 @@ struct Fp32Geo {
     static constexpr int REC = rec_units(NS);    // W + 512 B of S + padding
 };
 
+// Per-universe state a wave carries through its range of grid points.
+template <int NS, int NC>
+struct Fp32Lane {
+    float dh[NC][NS], dl[NC][NS];  // B-operand sources d = dh + dl
+    int64_t p_own;                 // true point of the universe this lane reports
+    float best;                    // running minimum and its grid point
+    uint32_t qbest;
+    float cp;                      // chi2 at the true point, once seen
+    bool have_cp;
+};
+
+// One grid point: contract the record in buf[SLOT], fold chi2 into the
+// running minimum, and (if more) stage the next record into buf[SLOT ^ 1].
+// SLOT is a template argument so that every LDS address is a constant.
+template <int NS, int NC, int SLOT>
+__device__ __forceinline__ void fp32_point(int64_t q, bool more, const uint4 *__restrict__ R32,
+                                           uint4 (*buf)[Fp32Geo<NS>::REC], Fp32Lane<NS, NC> &L)
+{
+    constexpr int NB = Fp32Geo<NS>::NB;
+    constexpr int NWU = rec_w_units(NS);
+    constexpr int REC = rec_units(NS);
+    constexpr int THREADS = 64 * kWavesPerBlock;
+    constexpr int CPT = REC / THREADS;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int grp = lane >> 4;
+
+    // the thread's share of the next record, units tid, tid+256, tid+512, in
+    // named registers (an array here ends up in scratch memory); on the last
+    // point of the range the current record is read again and not stored
+    const uint4 *rq = R32 + (more ? q + 1 : q) * REC + tid;
+    const uint4 st0 = rq[0];
+    uint4 st1 = st0, st2 = st0;
+    if constexpr (CPT > 1) st1 = rq[THREADS];
+    if constexpr (CPT > 2) st2 = rq[2 * THREADS];
+
+    const float4 *wl = reinterpret_cast<const float4 *>(&buf[SLOT][0]);
+    const float *shl = reinterpret_cast<const float *>(&buf[SLOT][NWU]) + grp * 16;
+    // accumulators start at C_q: rows 4 grp .. 4 grp + 3 of each row block
+    const float4 *cl = reinterpret_cast<const float4 *>(&buf[SLOT][NWU]) + 16 + grp;
+    v4f acc[NC][NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const float4 cv = cl[4 * b];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c][b] = v4f{cv.x, cv.y, cv.z, cv.w};
+    }
+
+    float4 wv = wl[lane];
+    int wg_loaded = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const float sh = shl[s];
+        float r[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[c] = (L.dh[c][s] - sh) + L.dl[c][s];
+#pragma unroll
+        for (int b = first_block_of_kstep(NS, s); b < NB; ++b) {
+            const int t = pair_index(NS, s, b);
+            if ((t >> 2) != wg_loaded) {
+                wg_loaded = t >> 2;
+                wv = wl[wg_loaded * 64 + lane];
+            }
+            const float w = pick(wv, t & 3);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, r[c], acc[c][b], 0, 0, 0);
+        }
+    }
+
+    // sum of squares per universe column: FP32 chains of the 4 rows a lane
+    // holds per row block, a pairwise tree over the blocks, then the four
+    // lane groups (FP32 instructions only)
+    float part[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        float blk[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float a = acc[c][b][0] * acc[c][b][0];
+#pragma unroll
+            for (int j = 1; j < 4; ++j) a = fmaf(acc[c][b][j], acc[c][b][j], a);
+            blk[b] = a;
+        }
+        if constexpr (NB == 4)
+            part[c] = (blk[0] + blk[1]) + (blk[2] + blk[3]);
+        else if constexpr (NB == 3)
+            part[c] = (blk[0] + blk[1]) + blk[2];
+        else if constexpr (NB == 2)
+            part[c] = blk[0] + blk[1];
+        else
+            part[c] = blk[0];
+    }
+    float kk;
+    if constexpr (NC == 4) {
+        // reduce-scatter: lane l ends with column block l/16
+        const bool hi = lane >= 32;
+        float k0 = hi ? part[2] : part[0];
+        float k1 = hi ? part[3] : part[1];
+        const float s0 = hi ? part[0] : part[2];
+        const float s1 = hi ? part[1] : part[3];
+        k0 += __shfl_xor(s0, 32);
+        k1 += __shfl_xor(s1, 32);
+        const bool odd = grp & 1;
+        kk = odd ? k1 : k0;
+        const float ss = odd ? k0 : k1;
+        kk += __shfl_xor(ss, 16);
+    } else {
+        // lanes < 32 end with block 0, lanes >= 32 with block 1: swapping the
+        // upper half of part[0] with the lower half of part[1] leaves lane l
+        // both halves of its block; then rows of 16 lanes are paired
+        const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[0]),
+                                                        __float_as_uint(part[1]), false, false);
+        kk = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+        const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(kk),
+                                                          __float_as_uint(kk), false, false);
+        kk = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+    }
+    const float chi2 = kk;
+
+    if (q == L.p_own) {
+        L.cp = chi2;
+        L.have_cp = true;
+    }
+    if (chi2 < L.best) {
+        L.best = chi2;
+        L.qbest = (uint32_t)q;
+    }
+
+    if (more) {
+        uint4 *bq = &buf[SLOT ^ 1][tid];
+        bq[0] = st0;
+        if constexpr (CPT > 1) bq[THREADS] = st1;
+        if constexpr (CPT > 2) bq[2 * THREADS] = st2;
+    }
+    __syncthreads();
+}
+
 template <int NS, int NC>
 __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 (*buf)[Fp32Geo<NS>::REC])
 {
     static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
-    constexpr int NB = Fp32Geo<NS>::NB;
     constexpr int NG = Fp32Geo<NS>::NG;
     constexpr int UW = 16 * NC;            // universes per wave
     constexpr int NWU = rec_w_units(NS);   // 16-byte units of W per record
@@ -56,6 +193,7 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 (*buf)[Fp32G
     constexpr int THREADS = 64 * kWavesPerBlock;
     static_assert(REC % THREADS == 0, "records are whole 4 KB pieces");
     constexpr int CPT = REC / THREADS;     // units copied per thread
+    static_assert(CPT >= 1 && CPT <= 3, "records of at most three 4 KB pieces");
     static_assert(NG * 64 == NWU, "W groups");
 
     const uint4 *__restrict__ R32 = it.R;
@@ -70,14 +208,10 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 (*buf)[Fp32G
     if (qb >= qe) return;  // uniform per block
     const int grp = lane >> 4, col = lane & 15;
 
-    static_assert(CPT >= 1 && CPT <= 3, "records of at most three 4 KB pieces");
-    // the thread's share of a record, units tid, tid+256, tid+512, held in
-    // named registers (an array here ends up in scratch memory)
-    uint4 st0 = make_uint4(0u, 0u, 0u, 0u), st1 = st0, st2 = st0;
+    Fp32Lane<NS, NC> L;
     // B-operand sources as FP32 pairs d = dh + dl: universe u0+16c+col, bin
     // 4s+grp (zero past N and past K; waves past K still take part in the
     // copies and barriers)
-    float dh[NC][NS], dl[NC][NS];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const int64_t u = u0 + 16 * c + col;
@@ -85,23 +219,24 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 (*buf)[Fp32G
         for (int s = 0; s < NS; ++s) {
             const int k = 4 * s + grp;
             const double v = (u < K && k < N) ? d[u * N + k] : 0.0;
-            dh[c][s] = (float)v;
-            dl[c][s] = (float)(v - (double)dh[c][s]);
+            L.dh[c][s] = (float)v;
+            L.dl[c][s] = (float)(v - (double)L.dh[c][s]);
         }
     }
     // after the reduction, lane l holds column block cl of universe column col
     const int cl = (NC == 4) ? grp : (grp >> 1);
     const bool owner = (NC == 4) ? true : ((grp & 1) == 0);
     const int64_t u_own = u0 + 16 * cl + col;
-    const int64_t p_own = (u_own < K) ? (it.p_idx ? it.p_idx[u_own] : it.p) : -1;
-    float best = __builtin_inff();
-    uint32_t qbest = 0xffffffffu;
-    float cp = 0.0f;
-    bool have_cp = false;
+    L.p_own = (u_own < K) ? (it.p_idx ? it.p_idx[u_own] : it.p) : -1;
+    L.best = __builtin_inff();
+    L.qbest = 0xffffffffu;
+    L.cp = 0.0f;
+    L.have_cp = false;
 
     {
         const uint4 *rq = R32 + qb * REC + tid;
-        st0 = rq[0];
+        const uint4 st0 = rq[0];
+        uint4 st1 = st0, st2 = st0;
         if constexpr (CPT > 1) st1 = rq[THREADS];
         if constexpr (CPT > 2) st2 = rq[2 * THREADS];
         uint4 *bq = &buf[0][tid];
@@ -110,120 +245,19 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 (*buf)[Fp32G
         if constexpr (CPT > 2) bq[2 * THREADS] = st2;
     }
     __syncthreads();
-    int slot = 0;
-    for (int64_t q = qb; q < qe; ++q) {
-        const bool more = q + 1 < qe;
-        if (more) {
-            const uint4 *rq = R32 + (q + 1) * REC + tid;
-            st0 = rq[0];
-            if constexpr (CPT > 1) st1 = rq[THREADS];
-            if constexpr (CPT > 2) st2 = rq[2 * THREADS];
-        }
-
-        const float4 *wl = reinterpret_cast<const float4 *>(&buf[slot][0]);
-        const float *shl = reinterpret_cast<const float *>(&buf[slot][NWU]) + grp * 16;
-        // accumulators start at C_q: rows 4 grp .. 4 grp + 3 of each row block
-        const float4 *cl = reinterpret_cast<const float4 *>(&buf[slot][NWU]) + 16 + grp;
-        v4f acc[NC][NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const float4 cv = cl[4 * b];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c][b] = v4f{cv.x, cv.y, cv.z, cv.w};
-        }
-
-        float4 wv = wl[lane];
-        int wg_loaded = 0;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const float sh = shl[s];
-            float r[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) r[c] = (dh[c][s] - sh) + dl[c][s];
-#pragma unroll
-            for (int b = first_block_of_kstep(NS, s); b < NB; ++b) {
-                const int t = pair_index(NS, s, b);
-                if ((t >> 2) != wg_loaded) {
-                    wg_loaded = t >> 2;
-                    wv = wl[wg_loaded * 64 + lane];
-                }
-                const float w = pick(wv, t & 3);
-#pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, r[c], acc[c][b], 0, 0, 0);
-            }
-        }
-
-        // sum of squares per universe column: FP32 chains of the 4 rows a lane
-        // holds per row block, a pairwise tree over the blocks, then the four
-        // lane groups (FP32 instructions only)
-        float part[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            float blk[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                float a = acc[c][b][0] * acc[c][b][0];
-#pragma unroll
-                for (int j = 1; j < 4; ++j) a = fmaf(acc[c][b][j], acc[c][b][j], a);
-                blk[b] = a;
-            }
-            if constexpr (NB == 4)
-                part[c] = (blk[0] + blk[1]) + (blk[2] + blk[3]);
-            else if constexpr (NB == 3)
-                part[c] = (blk[0] + blk[1]) + blk[2];
-            else if constexpr (NB == 2)
-                part[c] = blk[0] + blk[1];
-            else
-                part[c] = blk[0];
-        }
-        const bool hi = lane >= 32;
-        float kk;
-        if constexpr (NC == 4) {
-            // reduce-scatter: lane l ends with column block l/16
-            float k0 = hi ? part[2] : part[0];
-            float k1 = hi ? part[3] : part[1];
-            const float s0 = hi ? part[0] : part[2];
-            const float s1 = hi ? part[1] : part[3];
-            k0 += __shfl_xor(s0, 32);
-            k1 += __shfl_xor(s1, 32);
-            const bool odd = grp & 1;
-            kk = odd ? k1 : k0;
-            const float ss = odd ? k0 : k1;
-            kk += __shfl_xor(ss, 16);
-        } else {
-            // lanes < 32 keep block 0, lanes >= 32 block 1; then pair groups
-            kk = hi ? part[1] : part[0];
-            const float s0 = hi ? part[0] : part[1];
-            kk += __shfl_xor(s0, 32);
-            kk += __shfl_xor(kk, 16);
-        }
-        const float chi2 = kk;
-
-        if (q == p_own) {
-            cp = chi2;
-            have_cp = true;
-        }
-        if (chi2 < best) {
-            best = chi2;
-            qbest = (uint32_t)q;
-        }
-
-        if (more) {
-            uint4 *bq = &buf[slot ^ 1][tid];
-            bq[0] = st0;
-            if constexpr (CPT > 1) bq[THREADS] = st1;
-            if constexpr (CPT > 2) bq[2 * THREADS] = st2;
-        }
-        __syncthreads();
-        slot ^= 1;
+    // grid points in pairs so that each one's LDS slot is a constant
+    int64_t q = qb;
+    for (; q + 1 < qe; q += 2) {
+        fp32_point<NS, NC, 0>(q, true, R32, buf, L);
+        fp32_point<NS, NC, 1>(q + 1, q + 2 < qe, R32, buf, L);
     }
+    if (q < qe) fp32_point<NS, NC, 0>(q, false, R32, buf, L);
 
     if (owner && u_own < K) {
-        if (have_cp) it.chi2_p[u_own] = (double)cp;
-        if (best < __builtin_inff()) {
+        if (L.have_cp) it.chi2_p[u_own] = (double)L.cp;
+        if (L.best < __builtin_inff()) {
             const unsigned long long key =
-                ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)qbest;
+                ((unsigned long long)__float_as_uint(L.best) << 32) | (unsigned long long)L.qbest;
             atomicMin(&it.keys[u_own], key);
         }
     }
