@@ -177,6 +177,37 @@ int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2
                       double hist_hi, int64_t *hist, hipStream_t stream);
 
 /*
+ * fc_generate_universes -- draw universes on the device (Section 2, steps 1
+ * and 2 of the per-universe procedure: the prediction at the true point is
+ * fluctuated into fake data).  Row r in [seg_off[k], seg_off[k+1]) is universe
+ * j = u_first[k] + (r - seg_off[k]) of true point p[k]:
+ *     d[r][i] = n_i + S_p[i] * sum_{l <= i} L_F[i][l] g_l,
+ *     n_i ~ Poisson(S_p[i]),  g ~ N(0, I),  L_F = chol(F),
+ * so Cov(d) = diag(S_p) + F o (S_p S_p^T), the covariance of the scan.
+ * Random numbers: Philox4x64-10 (Salmon et al., SC'11) with key (seed, 0);
+ * block b of purpose t (0 Poisson, 1 normal) for (p, j, bin i) has counter
+ * (j, p, i << 32 | t << 28 | b, 0); word w -> uniform ((w >> 11) + 0.5) 2^-53.
+ * Poisson: multiplication method below mean 10, Hormann's PTRS from 10 up;
+ * normal: Box-Muller from the bin's normal block.  A universe depends only on
+ * (seed, p, j): any split into calls or batches gives identical rows.
+ *   n_pts, p       device int64 [n_pts] true points (outside [0, G): rows NaN,
+ *                  p_idx -1, counts -1)
+ *   seg_off        device int64 [n_pts+1], non-decreasing, seg_off[0] = 0,
+ *                  seg_off[n_pts] = K (rows are assigned by it)
+ *   u_first        device int64 [n_pts] first universe index, or NULL (all 0)
+ *   K              host: number of rows
+ *   d              device out [K][N] FP64
+ *   p_idx          device out [K] int64 (the row's true point), or NULL
+ *   counts         device out [K][N] int32 (the Poisson parts), or NULL
+ * Needs fc_build_covariance (FC_ERR_STATE) with F positive definite
+ * (FC_ERR_NOT_PD).  Asynchronous.
+ */
+int fc_generate_universes(const fc_grid *g, int64_t n_pts, const int64_t *p,
+                          const int64_t *seg_off, const int64_t *u_first, uint64_t seed,
+                          int64_t K, double *d, int64_t *p_idx, int32_t *counts,
+                          hipStream_t stream);
+
+/*
  * fc_data_scan -- the observed-data statistic (Section 1: the scan looks for
  * the points compatible with the central data vector c; Algorithm 1's inner
  * loop run once with c as the data):

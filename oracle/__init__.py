@@ -15,6 +15,10 @@ Functions follow arXiv:2002.07858:
   critical_value         -- Section 1 / Figure 1 (quantiles of Delta chi^2)
   data_scan / acceptance -- Section 1 (Delta chi^2 of the observed data at every
                             point, accepted where it is within the critical value)
+  universes              -- Section 2, steps 1-2 (the prediction at p fluctuated:
+                            Poisson counts plus correlated fractional systematics),
+                            from a counter-based stream (Philox4x64-10) and
+                            Hormann's PTRS Poisson sampler
 """
 from __future__ import annotations
 
@@ -71,9 +75,19 @@ def lib():
         L.fco_scan_finish.argtypes = [_i64, _p, _p, _p]
         L.fco_chi2_table.argtypes = [_i64, _i32, _p, _p, _i64, _p, _p, _i32]
         L.fco_critical_value.argtypes = [_i64, _p, _p, _i32, _p, _p, _i32, _dbl, _p]
+        _u64 = ctypes.c_uint64
+        L.fco_philox4x64.argtypes = [_p, _p, _p]
+        L.fco_philox4x64.restype = None
+        L.fco_uniform.argtypes = [_u64]
+        L.fco_uniform.restype = _dbl
+        L.fco_poisson.argtypes = [_dbl, _u64, _i64, _i64, _i32]
+        L.fco_poisson.restype = _i64
+        L.fco_normal.argtypes = [_u64, _i64, _i64, _i32]
+        L.fco_normal.restype = _dbl
+        L.fco_universes.argtypes = [_i64, _i32, _p, _p, _i64, _p, _p, _p, _u64, _p, _p, _i32]
         for name in ("fco_grid_coords", "fco_covariance", "fco_cholesky", "fco_factor_range",
                      "fco_scan", "fco_scan_init", "fco_scan_range", "fco_scan_finish",
-                     "fco_chi2_table", "fco_critical_value"):
+                     "fco_chi2_table", "fco_critical_value", "fco_universes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -235,6 +249,51 @@ def acceptance(dchi2_data, p, crit):
         if 0 <= p[k] < dd.shape[0] and dd[p[k]] <= crit[k]:
             out[k] = 1
     return out
+
+
+def philox4x64(ctr, key) -> list:
+    """Philox4x64-10 block for a 4-word counter and 2-word key."""
+    c = np.asarray(ctr, dtype=np.uint64)
+    k = np.asarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().fco_philox4x64(_ptr(c), _ptr(k), _ptr(out))
+    return [int(x) for x in out]
+
+
+def uniform(w: int) -> float:
+    return float(lib().fco_uniform(int(w)))
+
+
+def poisson(lam: float, seed: int, p: int, j: int, i: int) -> int:
+    """Poisson draw for (true point p, universe j, bin i); -1 for an invalid mean."""
+    return int(lib().fco_poisson(float(lam), int(seed), int(p), int(j), int(i)))
+
+
+def normal(seed: int, p: int, j: int, i: int) -> float:
+    return float(lib().fco_normal(int(seed), int(p), int(j), int(i)))
+
+
+def universes(S, F, p, seg_off, seed, u_first=None, nthreads=None):
+    """Universes of true points p[k] into rows seg_off[k]..seg_off[k+1]-1.
+
+    d_i = Poisson(S_p[i]) + S_p[i] * (chol(F) g)_i; returns (d [K][N],
+    counts [K][N] int32).
+    """
+    S = _f64(S)
+    G, N = S.shape
+    LF = cholesky(F)
+    p = _i64a(p)
+    seg_off = _i64a(seg_off)
+    uf = None if u_first is None else _i64a(u_first)
+    K = int(seg_off[-1]) if seg_off.shape[0] else 0
+    d = np.empty((K, N))
+    counts = np.empty((K, N), dtype=np.int32)
+    rc = lib().fco_universes(G, N, _ptr(S), _ptr(_f64(LF)), p.shape[0], _ptr(p), _ptr(seg_off),
+                             _ptr(uf), int(seed), _ptr(d), _ptr(counts),
+                             nthreads or default_threads())
+    if rc != 0:
+        raise OracleError("bad universe arguments")
+    return d, counts
 
 
 def critical_value(x, seg_off, alpha, n_bins=200, hist_hi=50.0, with_hist=True):

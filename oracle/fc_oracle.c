@@ -345,3 +345,146 @@ int fco_critical_value(int64_t n_seg, const int64_t *seg_off, const double *x,
     }
     return 0;
 }
+
+/* ---- universes: counter-based stream, Poisson and normal variates -------- */
+
+/* 64 x 64 -> 128-bit product split into high and low words. */
+static void fco_mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+/* Philox4x64 with 10 rounds (Salmon et al., SC'11). */
+void fco_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0, lo0, hi1, lo1;
+        fco_mulhilo64(0xD2E7470EE14C6C93ull, x0, &hi0, &lo0);
+        fco_mulhilo64(0xCA5A826395121157ull, x2, &hi1, &lo1);
+        x0 = hi1 ^ x1 ^ k0;
+        x1 = lo1;
+        x2 = hi0 ^ x3 ^ k1;
+        x3 = lo0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+double fco_uniform(uint64_t w)
+{
+    return ((double)(w >> 11) + 0.5) * 0x1.0p-53;
+}
+
+static void fco_block(uint64_t seed, int64_t p, int64_t j, int32_t i, uint32_t purpose,
+                      uint32_t b, uint64_t out[4])
+{
+    const uint64_t ctr[4] = {(uint64_t)j, (uint64_t)p,
+                             ((uint64_t)(uint32_t)i << 32) | ((uint64_t)purpose << 28) | b, 0};
+    const uint64_t key[2] = {seed, 0};
+    fco_philox4x64(ctr, key, out);
+}
+
+int64_t fco_poisson(double lambda, uint64_t seed, int64_t p, int64_t j, int32_t i)
+{
+    if (!(lambda >= 0.0) || isinf(lambda)) return -1;
+    if (lambda == 0.0) return 0;
+    uint64_t w[4];
+    if (lambda < 10.0) {
+        /* multiplication method: count uniforms until their product first
+         * falls to exp(-lambda) or below */
+        const double L = exp(-lambda);
+        double prod = 1.0;
+        int64_t k = 0;
+        for (uint32_t b = 0; b < 256; ++b) {
+            fco_block(seed, p, j, i, 0, b, w);
+            for (int e = 0; e < 4; ++e) {
+                prod *= fco_uniform(w[e]);
+                if (prod <= L) return k;
+                ++k;
+            }
+        }
+        return k;
+    }
+    /* PTRS: transformed rejection with squeeze (Hormann 1993) */
+    const double slam = sqrt(lambda), loglam = log(lambda);
+    const double bb = 0.931 + 2.53 * slam;
+    const double aa = -0.059 + 0.02483 * bb;
+    const double inv_alpha = 1.1239 + 1.1328 / (bb - 3.4);
+    const double vr = 0.9277 - 3.6224 / (bb - 2.0);
+    for (uint32_t t = 0; t < 512; ++t) {
+        if ((t & 1) == 0) fco_block(seed, p, j, i, 0, t >> 1, w);
+        const double U = fco_uniform(w[2 * (t & 1)]) - 0.5;
+        const double V = fco_uniform(w[2 * (t & 1) + 1]);
+        const double us = 0.5 - fabs(U);
+        const double kf = floor((2.0 * aa / us + bb) * U + lambda + 0.43);
+        if (us >= 0.07 && V <= vr) return (int64_t)kf;
+        if (kf < 0.0 || (us < 0.013 && V > us)) continue;
+        const double lhs = log(V * inv_alpha / (aa / (us * us) + bb));
+        const double rhs = -lambda + kf * loglam - lgamma(kf + 1.0);
+        if (lhs <= rhs) return (int64_t)kf;
+    }
+    return (int64_t)floor(lambda);
+}
+
+double fco_normal(uint64_t seed, int64_t p, int64_t j, int32_t i)
+{
+    uint64_t w[4];
+    fco_block(seed, p, j, i, 1, 0, w);
+    const double u0 = fco_uniform(w[0]), u1 = fco_uniform(w[1]);
+    return sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
+}
+
+struct fco_univ_ctx {
+    int32_t N;
+    const double *S, *LF;
+    int64_t n_pts;
+    const int64_t *p, *seg_off, *u_first;
+    uint64_t seed;
+    double *d;
+    int32_t *counts;
+};
+
+static void fco_univ_task(void *vctx, int64_t lo, int64_t hi)
+{
+    struct fco_univ_ctx *c = (struct fco_univ_ctx *)vctx;
+    const int32_t N = c->N;
+    double g[64];
+    for (int64_t k = lo; k < hi; ++k) {
+        const int64_t p = c->p[k];
+        const double *Sp = c->S + p * N;
+        for (int64_t r = c->seg_off[k]; r < c->seg_off[k + 1]; ++r) {
+            const int64_t j = (c->u_first ? c->u_first[k] : 0) + (r - c->seg_off[k]);
+            for (int32_t i = 0; i < N; ++i) g[i] = fco_normal(c->seed, p, j, i);
+            for (int32_t i = 0; i < N; ++i) {
+                const int64_t n = fco_poisson(Sp[i], c->seed, p, j, i);
+                double z = 0.0;
+                for (int32_t l = 0; l <= i; ++l) z += c->LF[i * N + l] * g[l];
+                c->d[r * N + i] = (n < 0) ? NAN : (double)n + Sp[i] * z;
+                if (c->counts) c->counts[r * N + i] = (int32_t)n;
+            }
+        }
+    }
+}
+
+int fco_universes(int64_t G, int32_t N, const double *S, const double *LF, int64_t n_pts,
+                  const int64_t *p, const int64_t *seg_off, const int64_t *u_first,
+                  uint64_t seed, double *d, int32_t *counts, int32_t nthreads)
+{
+    if (G < 1 || N < 1 || N > 64 || n_pts < 0 || !S || !LF || !seg_off || (n_pts && !p) || !d)
+        return -1;
+    for (int64_t k = 0; k < n_pts; ++k)
+        if (p[k] < 0 || p[k] >= G || seg_off[k + 1] < seg_off[k] ||
+            (u_first && u_first[k] < 0))
+            return -1;
+    struct fco_univ_ctx c = {N, S, LF, n_pts, p, seg_off, u_first, seed, d, counts};
+    fco_parallel(n_pts, nthreads, fco_univ_task, &c);
+    return 0;
+}

@@ -95,6 +95,36 @@ int fco_critical_value(int64_t n_seg, const int64_t *seg_off, const double *x,
                        int32_t n_alpha, const double *alpha, double *crit,
                        int32_t n_bins, double hist_hi, int64_t *hist);
 
+/* ---- universes (Section 2, steps 1-2: fluctuate the prediction at p) -----
+ *
+ * Counter-based stream, the same definition on every side:
+ *   Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of
+ *     (hi0,lo0) = mulhilo(0xD2E7470EE14C6C93, x0), (hi1,lo1) = mulhilo(0xCA5A826395121157, x2),
+ *     x = (hi1 ^ x1 ^ k0, lo1, hi0 ^ x3 ^ k1, lo0),
+ *   the key advancing by (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B) after each round.
+ *   Key (seed, 0).  Block b of purpose t for true point p, universe j, bin i
+ *   has counter (j, p, i << 32 | t << 28 | b, 0); t = 0 Poisson, t = 1 normal.
+ *   A 64-bit word w gives the uniform ((w >> 11) + 0.5) * 2^-53 in (0, 1).
+ * Poisson(lambda): lambda = 0 -> 0; lambda < 10: multiplication method (the
+ *   product of uniforms, words in block order, first at or below
+ *   exp(-lambda); at most 1024 uniforms); lambda >= 10: Hormann's transformed
+ *   rejection with squeeze (PTRS, 1993), attempt t taking words 2(t%2),
+ *   2(t%2)+1 of block t/2, at most 512 attempts, then floor(lambda).
+ *   lambda < 0, NaN or inf -> -1 (no value).
+ * Normal: sqrt(-2 ln u0) cos(2 pi u1) from words 0, 1 of the bin's normal block.
+ * Universe: d_i = n_i + S_p[i] * sum_{l <= i} LF[i][l] g_l, LF = chol(F),
+ *   summed in increasing l (n_i = -1 gives d_i = NaN). */
+void fco_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+double fco_uniform(uint64_t w);
+int64_t fco_poisson(double lambda, uint64_t seed, int64_t p, int64_t j, int32_t i);
+double fco_normal(uint64_t seed, int64_t p, int64_t j, int32_t i);
+/* Universes of n_pts true points: rows seg_off[k] .. seg_off[k+1]-1 are
+ * universes u_first[k] + 0, 1, ... of point p[k] (u_first may be NULL = 0).
+ * LF is chol(F) [N][N].  counts may be NULL.  Returns -1 on a bad argument. */
+int fco_universes(int64_t G, int32_t N, const double *S, const double *LF, int64_t n_pts,
+                  const int64_t *p, const int64_t *seg_off, const int64_t *u_first,
+                  uint64_t seed, double *d, int32_t *counts, int32_t nthreads);
+
 #ifdef __cplusplus
 }
 #endif

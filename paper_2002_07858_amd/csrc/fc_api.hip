@@ -44,10 +44,15 @@ void free_forms(fc_grid *g)
     if (g->R32) (void)hipFree(g->R32);
     if (g->RB16) (void)hipFree(g->RB16);
     if (g->RH16) (void)hipFree(g->RH16);
+    if (g->F64) (void)hipFree(g->F64);
+    if (g->LF64) (void)hipFree(g->LF64);
     g->W64 = nullptr;
     g->R32 = nullptr;
     g->RB16 = nullptr;
     g->RH16 = nullptr;
+    g->F64 = nullptr;
+    g->LF64 = nullptr;
+    g->lf_ok = 0;
     g->forms = 0;
 }
 
@@ -65,6 +70,7 @@ size_t grid_bytes(const fc_grid *g)
     if (g->R32) b += sizeof(uint4) * (size_t)g->G * fcx::rec_units(g->ns);
     if (g->RB16) b += (size_t)g->G * split_record_bytes(g);
     if (g->RH16) b += (size_t)g->G * split_record_bytes(g);
+    if (g->F64) b += 2 * sizeof(double) * (size_t)g->N * g->N;  // F and its factor
     return b;
 }
 
@@ -180,18 +186,20 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
         return fail(FC_ERR_INVALID_ARG, "fc_build_covariance: stat_diag has a non-finite entry");
 
     free_forms(g);
-    double *dF = nullptr, *dstat = nullptr;
+    double *dF = nullptr, *dstat = nullptr, *dLF = nullptr;
     unsigned long long *dbad = nullptr;
     double *W64 = nullptr;
     uint4 *R32 = nullptr, *RB16 = nullptr, *RH16 = nullptr;
     hipError_t e = hipSuccess;
     auto cleanup = [&]() {
         if (dF) (void)hipFree(dF);
+        if (dLF) (void)hipFree(dLF);
         if (dstat) (void)hipFree(dstat);
         if (dbad) (void)hipFree(dbad);
     };
     const size_t nt = (size_t)N * (N + 1) / 2;
     if ((e = hipMalloc(&dF, sizeof(double) * N * N)) != hipSuccess ||
+        (e = hipMalloc(&dLF, sizeof(double) * N * N)) != hipSuccess ||
         (e = hipMalloc(&dstat, sizeof(double) * N)) != hipSuccess ||
         (e = hipMalloc(&dbad, sizeof(unsigned long long))) != hipSuccess ||
         ((forms & FC_FORM_FP64) &&
@@ -211,7 +219,7 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
         return hip_fail(e, "fc_build_covariance: hipMalloc");
     }
     const unsigned long long none = ~0ull;
-    unsigned long long hbad = none;
+    unsigned long long hbad = none, hlf = 0;
     if ((e = hipMemcpyAsync(dF, frac_cov, sizeof(double) * N * N, hipMemcpyHostToDevice,
                             stream)) != hipSuccess ||
         (stat_mode == FC_STAT_FIXED &&
@@ -224,6 +232,11 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
             hipSuccess ||
         (e = hipMemcpyAsync(&hbad, dbad, sizeof(hbad), hipMemcpyDeviceToHost, stream)) !=
             hipSuccess ||
+        // the factor of F itself, for drawing universes (dbad reused as the flag)
+        (e = fcx::launch_chol_frac(dF, N, dLF, reinterpret_cast<int *>(dbad), stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&hlf, dbad, sizeof(int), hipMemcpyDeviceToHost, stream)) !=
+            hipSuccess ||
         (e = hipStreamSynchronize(stream)) != hipSuccess) {
         cleanup();
         if (W64) (void)hipFree(W64);
@@ -232,8 +245,8 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
         if (RH16) (void)hipFree(RH16);
         return hip_fail(e, "fc_build_covariance: build");
     }
-    cleanup();
     if (hbad != none) {
+        cleanup();
         if (W64) (void)hipFree(W64);
         if (R32) (void)hipFree(R32);
         if (RB16) (void)hipFree(RB16);
@@ -247,6 +260,11 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
     g->R32 = R32;
     g->RB16 = RB16;
     g->RH16 = RH16;
+    g->F64 = dF;
+    g->LF64 = dLF;
+    g->lf_ok = ((int)hlf == 1) ? 1 : 0;
+    dF = dLF = nullptr;  // kept on the grid
+    cleanup();
     g->forms = forms;
     g->bytes = grid_bytes(g);
     return FC_OK;
@@ -382,6 +400,27 @@ int fc_acceptance(const fc_grid *g, int64_t n_pts, const int64_t *p, const doubl
     hipError_t e = fcx::launch_accept(n_pts, p, crit, crit_stride, dchi2_data, g->G, accepted,
                                       stream);
     if (e != hipSuccess) return hip_fail(e, "fc_acceptance");
+    return FC_OK;
+}
+
+int fc_generate_universes(const fc_grid *g, int64_t n_pts, const int64_t *p,
+                          const int64_t *seg_off, const int64_t *u_first, uint64_t seed,
+                          int64_t K, double *d, int64_t *p_idx, int32_t *counts,
+                          hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_generate_universes: grid is NULL");
+    if (n_pts < 0 || K < 0) return fail(FC_ERR_INVALID_ARG, "fc_generate_universes: n_pts/K < 0");
+    if (!g->F64) return fail(FC_ERR_STATE, "fc_generate_universes: covariance not built");
+    if (!g->lf_ok)
+        return fail(FC_ERR_NOT_PD, "fc_generate_universes: fractional covariance not positive "
+                                   "definite");
+    if (K == 0) return FC_OK;
+    if (n_pts < 1 || !p || !seg_off || !d)
+        return fail(FC_ERR_INVALID_ARG, "fc_generate_universes: NULL device pointer or no points");
+    hipError_t e = fcx::launch_gen_universes(g, n_pts, p, seg_off, u_first, seed, K, d, p_idx,
+                                             counts, stream);
+    if (e != hipSuccess) return hip_fail(e, "fc_generate_universes");
     return FC_OK;
 }
 

@@ -151,6 +151,9 @@ struct fc_grid {
     double *off = nullptr;  // device [64] per-bin offset o (grid mean of S), zero past N
     double *dev = nullptr;  // device [64] per-bin max |S - o|
     int ed16 = 0;           // power-of-two scale of (d - o) in the split-FP16 form
+    double *F64 = nullptr;  // device [N][N] fractional covariance of the last build
+    double *LF64 = nullptr; // device [N][N] its Cholesky factor (universe generation)
+    int lf_ok = 0;          // 1 if F is positive definite (LF64 valid)
     size_t bytes = 0;
     int ns = 0, ng = 0;     // FP32 fragment geometry
 };
@@ -209,6 +212,11 @@ int serve_split_univ_per_item();
 int serve_slots_fp32(int ns);
 int serve_slots_split(int nk, int nb, bool fp16);
 
+hipError_t launch_chol_frac(const double *F, int N, double *LF, int *flag, hipStream_t st);
+hipError_t launch_gen_universes(const fc_grid *g, int64_t n_pts, const int64_t *p,
+                                const int64_t *seg_off, const int64_t *u_first, uint64_t seed,
+                                int64_t K, double *d, int64_t *p_idx, int32_t *counts,
+                                hipStream_t st);
 hipError_t launch_data_scan(const fc_grid *g, const double *c, double *chi2,
                             unsigned long long *scratch, hipStream_t st);
 hipError_t launch_accept(int64_t n_pts, const int64_t *p, const double *crit, int64_t stride,

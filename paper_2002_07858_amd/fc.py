@@ -42,7 +42,7 @@ FC_REQ_DONE = 2
 FC_REQ_FAILED = -1
 
 EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
-            "fc_data_scan", "fc_acceptance", "fc_grid_inverse_cov", "fc_grid_info",
+            "fc_generate_universes", "fc_data_scan", "fc_acceptance", "fc_grid_inverse_cov", "fc_grid_info",
             "fc_grid_device_bytes", "fc_grid_destroy", "fc_last_error", "fc_server_create", "fc_server_submit", "fc_server_poll",
             "fc_server_stats", "fc_server_destroy")
 
@@ -72,6 +72,8 @@ def lib():
         L.fc_build_covariance.argtypes = [_p, _p, _i32, _p, _u32, _p, _p]
         L.fc_scan.argtypes = [_p, _i32, _i64, _p, _p, _p, _p, _p, _p, _p]
         L.fc_critical_value.argtypes = [_i64, _p, _p, _i32, _p, _p, _i32, _dbl, _p, _p]
+        L.fc_generate_universes.argtypes = [_p, _i64, _p, _p, _p, ctypes.c_uint64, _i64, _p, _p,
+                                            _p, _p]
         L.fc_data_scan.argtypes = [_p, _p, _p, _p, _p, _p]
         L.fc_acceptance.argtypes = [_p, _i64, _p, _p, _i64, _p, _p, _p]
         L.fc_grid_inverse_cov.argtypes = [_p, _i64, _i64, _p, _p]
@@ -92,7 +94,7 @@ def lib():
         for name in ("fc_server_create", "fc_server_submit", "fc_server_poll", "fc_server_stats"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
-                     "fc_data_scan", "fc_acceptance", "fc_grid_inverse_cov", "fc_grid_info"):
+                     "fc_generate_universes", "fc_data_scan", "fc_acceptance", "fc_grid_inverse_cov", "fc_grid_info"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -120,7 +122,8 @@ def _dev(t, dtype_name: str, name: str):
     if t is None:
         return None
     import torch
-    want = {"f64": torch.float64, "i64": torch.int64, "u8": torch.uint8}[dtype_name]
+    want = {"f64": torch.float64, "i64": torch.int64, "u8": torch.uint8,
+            "i32": torch.int32}[dtype_name]
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a torch CUDA tensor")
     if t.dtype != want:
@@ -217,6 +220,22 @@ def fc_critical_value(seg_off, dchi2, alpha, crit, n_bins=200, hist_hi=50.0, his
                                    _dev(dchi2, "f64", "dchi2"), int(a.shape[0]), _hp(a),
                                    _dev(crit, "f64", "crit"), int(n_bins), float(hist_hi),
                                    _dev(hist, "i64", "hist"), _stream(stream)))
+
+
+def fc_generate_universes(grid: Grid, p, seg_off, seed: int, d, p_idx=None, counts=None,
+                          u_first=None, stream=None):
+    """Enqueue universes of true points p[k] into rows seg_off[k]..seg_off[k+1]-1 of d.
+
+    p, seg_off, u_first: int64 CUDA tensors; d: float64 [K][N]; p_idx int64 [K]
+    and counts int32 [K][N] optional outputs.
+    """
+    K = int(d.shape[0])
+    _check(lib().fc_generate_universes(grid._h, int(p.numel()), _dev(p, "i64", "p"),
+                                       _dev(seg_off, "i64", "seg_off"),
+                                       _dev(u_first, "i64", "u_first"),
+                                       ctypes.c_uint64(int(seed) % 2**64), K,
+                                       _dev(d, "f64", "d"), _dev(p_idx, "i64", "p_idx"),
+                                       _dev(counts, "i32", "counts"), _stream(stream)))
 
 
 def fc_data_scan(grid: Grid, dchi2_data, central=None, stream=None):

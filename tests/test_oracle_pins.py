@@ -413,3 +413,90 @@ def test_p11_coverage_of_the_acceptance_region():
     for a, al in enumerate(alpha):
         sigma = math.sqrt(al * (1 - al) / M + al * (1 - al) / 2000)
         assert abs(hits[a] / M - al) <= 4 * sigma, (al, hits[a] / M)
+
+
+# --------------------------------------------------------------------------
+# P12: universes (Section 2, steps 1-2) from the counter-based stream
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("key,ctr", [((123, 456), (6, 0, 0, 0)),
+                                     ((2**64 - 1, 5), (2**64 - 2, 2**64 - 1, 3, 9)),
+                                     ((0, 0), (2**64 - 1, 2**64 - 1, 0, 0))])
+def test_p12_philox_matches_numpy(key, ctr):
+    # numpy's Philox (4x64, 10 rounds) advances its counter before each block
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                          counter=np.array(ctr, dtype=np.uint64))
+    ref = [int(x) for x in bg.random_raw(4)]
+    c = list(ctr)
+    for w in range(4):                       # counter + 1 with carry
+        c[w] = (c[w] + 1) % 2**64
+        if c[w]:
+            break
+    assert oracle.philox4x64(c, key) == ref
+
+
+def test_p12_uniform_open_interval():
+    assert oracle.uniform(0) == 2.0**-54
+    assert oracle.uniform(2**64 - 1) == 1.0 - 2.0**-54
+    assert oracle.uniform(2**63) == 0.5 + 2.0**-54
+
+
+@pytest.mark.parametrize("lam", [0.5, 3.0, 9.99, 10.0, 37.5, 300.0, 2000.0])
+def test_p12_poisson_distribution(lam):
+    """Chi-square goodness of fit against the Poisson pmf (scipy), both the
+    multiplication branch (lambda < 10) and PTRS (lambda >= 10)."""
+    n = 20000
+    x = np.array([oracle.poisson(lam, 99, 3, j, 5) for j in range(n)])
+    assert x.min() >= 0
+    assert abs(x.mean() - lam) <= 5 * math.sqrt(lam / n)
+    lo = int(max(0, lam - 7 * math.sqrt(lam) - 2))
+    hi = int(lam + 7 * math.sqrt(lam) + 3)
+    ks = np.arange(lo, hi + 1)
+    expct = scipy.stats.poisson.pmf(ks, lam) * n
+    obs = np.array([(x == k).sum() for k in ks])
+    sel = expct >= 5
+    rest_o, rest_e = n - obs[sel].sum(), n - expct[sel].sum()
+    chi = ((obs[sel] - expct[sel]) ** 2 / expct[sel]).sum()
+    dof = int(sel.sum()) - 1
+    if rest_e >= 5:
+        chi += (rest_o - rest_e) ** 2 / rest_e
+        dof += 1
+    assert scipy.stats.chi2.sf(chi, dof) > 1e-3
+
+
+def test_p12_poisson_special_means():
+    assert all(oracle.poisson(0.0, 1, 0, j, 0) == 0 for j in range(50))
+    for bad in (-1.0, float("nan"), float("inf")):
+        assert oracle.poisson(bad, 1, 0, 0, 0) == -1
+
+
+def test_p12_normal_distribution():
+    g = np.array([oracle.normal(7, 1, j, 2) for j in range(20000)])
+    assert scipy.stats.kstest(g, "norm").pvalue > 1e-3
+    # different bins / points / seeds are different streams
+    h = np.array([oracle.normal(7, 1, j, 3) for j in range(20000)])
+    assert abs(np.corrcoef(g, h)[0, 1]) < 0.03
+
+
+def test_p12_universes_covariance_and_batching():
+    """Universes around S(p) have mean S(p) and covariance diag(S) + F o (S S^T)
+    (Poisson plus fractional systematics); rows depend only on (p, j), so any
+    split into batches gives the same values."""
+    pr = fcgen.make_problem("c1", K=1, true_subset=[0], n_axis=(4, 4))
+    p = 9
+    M = 20000
+    d, counts = oracle.universes(pr.S, pr.F, [p], [0, M], seed=11)
+    s = pr.S[p]
+    Sig = np.diag(s) + pr.F * np.outer(s, s)
+    r = d - s
+    se_mean = np.sqrt(np.diag(Sig) / M)
+    assert np.all(np.abs(r.mean(axis=0)) <= 5 * se_mean)
+    C = np.cov(r, rowvar=False)
+    se = np.sqrt((np.outer(np.diag(Sig), np.diag(Sig)) + Sig ** 2) / M)
+    assert np.all(np.abs(C - Sig) <= 5 * se)
+    assert counts.min() >= 0 and np.all(counts == np.round(counts))
+    # the Poisson part alone has variance S
+    assert np.all(np.abs(counts.var(axis=0) - s) <= 5 * s * math.sqrt(2.0 / M))
+    # batching: rows 300..499 drawn on their own equal the same rows of the whole
+    d2, c2 = oracle.universes(pr.S, pr.F, [p], [0, 200], seed=11, u_first=[300])
+    np.testing.assert_array_equal(d2, d[300:500])
+    np.testing.assert_array_equal(c2, counts[300:500])
