@@ -208,6 +208,38 @@ int fc_generate_universes(const fc_grid *g, int64_t n_pts, const int64_t *p,
                           hipStream_t stream);
 
 /*
+ * fc_region -- Feldman-Cousins confidence region with per-point universe
+ * counts.  Section 2 builds the Delta chi^2 distribution of every true point
+ * from universes drawn at it; the paper's closing section proposes letting
+ * the universe count differ per point so that large counts go only to points
+ * near the eventual contour.  In rounds, on the device:
+ *   - every point starts with K0 universes (fc_generate_universes' stream,
+ *     universe indices 0 .. K0-1, this seed), scanned in `form`;
+ *   - per point: crit[a] = x_(ceil(alpha_a K)) over its K values, and the band
+ *     [x_(j - delta), x_(j + delta)], j = ceil(alpha_a K), delta =
+ *     ceil(z sqrt(K alpha_a (1 - alpha_a))), ranks clamped to [1, K];
+ *   - a point whose data value dchi2_data[p] lies inside some band is
+ *     undecided; undecided points below K_max double K (universes K .. 2K-1,
+ *     at most K_max) and the round repeats until none is left to refine.
+ * Then accepted[k][a] = dchi2_data[p_k] <= crit[k][a] (NaN: not accepted).
+ *   pts          host [n_pts] grid indices, or NULL with n_pts = G (every point)
+ *   K0, K_max    1 <= K0 <= K_max <= 2^24; z >= 0 (band half-width in sigmas)
+ *   n_alpha      1..4 fractions in (0, 1] (host)
+ *   dchi2_data   device [G] from fc_data_scan
+ *   crit         device out [n_pts][n_alpha] FP64
+ *   accepted     device out [n_pts][n_alpha] uint8
+ *   K_used       host out [n_pts]: universes each point ended with
+ *   n_rounds, n_evals  host out: rounds run, universe x grid-point evaluations
+ * Needs the form built and F positive definite (fc_generate_universes).
+ * Device memory: n_pts * K_max doubles plus a batch of 2^19 universes.
+ * Synchronous (the refinement decisions are taken on the host).
+ */
+int fc_region(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t *pts, int64_t K0,
+              int64_t K_max, double z, uint64_t seed, int32_t n_alpha, const double *alpha,
+              const double *dchi2_data, double *crit, uint8_t *accepted, int64_t *K_used,
+              int32_t *n_rounds, double *n_evals, hipStream_t stream);
+
+/*
  * fc_data_scan -- the observed-data statistic (Section 1: the scan looks for
  * the points compatible with the central data vector c; Algorithm 1's inner
  * loop run once with c as the data):

@@ -15,6 +15,9 @@ Functions follow arXiv:2002.07858:
   critical_value         -- Section 1 / Figure 1 (quantiles of Delta chi^2)
   data_scan / acceptance -- Section 1 (Delta chi^2 of the observed data at every
                             point, accepted where it is within the critical value)
+  region                 -- Section 2's construction for a set of true points with
+                            per-point universe counts, refined near the contour
+                            (the closing section's proposal)
   universes              -- Section 2, steps 1-2 (the prediction at p fluctuated:
                             Poisson counts plus correlated fractional systematics),
                             from a counter-based stream (Philox4x64-10) and
@@ -23,6 +26,7 @@ Functions follow arXiv:2002.07858:
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -294,6 +298,61 @@ def universes(S, F, p, seg_off, seed, u_first=None, nthreads=None):
     if rc != 0:
         raise OracleError("bad universe arguments")
     return d, counts
+
+
+def region(S, F, pts, K0, K_max, z, seed, alpha, dchi2_data, stat_mode=STAT_PEARSON,
+           stat_diag=None, nthreads=None):
+    """Feldman-Cousins region over true points pts with per-point universe counts.
+
+    Section 2 builds each point's Delta chi^2 distribution from universes drawn
+    at it; the closing section proposes spending universes only near the
+    contour.  Rounds: every point starts with universes 0..K0-1; after each
+    round a point's critical values are x_(j), j = ceil(alpha K), over its K
+    values, and its band is [x_(j - delta), x_(j + delta)] with delta =
+    ceil(z sqrt(K alpha (1 - alpha))) (ranks clamped to [1, K]); a point whose
+    data value dchi2_data[p] falls inside a band, and has K < K_max, draws
+    universes K..2K-1 (at most K_max) for the next round.  Returns crit
+    [n][n_alpha], accepted [n][n_alpha] (dchi2_data[p] <= crit), K_used,
+    rounds and evals (universe x grid-point evaluations).
+    """
+    S = _f64(S)
+    G = S.shape[0]
+    pts = _i64a(pts)
+    n = pts.shape[0]
+    alpha = _f64(np.atleast_1d(alpha))
+    dd = _f64(dchi2_data)[pts]
+    vals = [np.empty(0) for _ in range(n)]
+    K = np.zeros(n, dtype=np.int64)
+    K_new = np.full(n, K0, dtype=np.int64)
+    crit = np.full((n, alpha.shape[0]), np.nan)
+    rounds, evals = 0, 0.0
+    while True:
+        act = np.flatnonzero(K_new > K)
+        if act.shape[0] == 0:
+            break
+        rounds += 1
+        seg = np.concatenate([[0], np.cumsum(K_new[act] - K[act])]).astype(np.int64)
+        d, _ = universes(S, F, pts[act], seg, seed, u_first=K[act], nthreads=nthreads)
+        r = scan(S, F, d, np.repeat(pts[act], np.diff(seg)), stat_mode, stat_diag, nthreads)
+        for i, k in enumerate(act):
+            vals[k] = np.concatenate([vals[k], r["dchi2"][seg[i]:seg[i + 1]]])
+        evals += float(seg[-1]) * G
+        K = K_new.copy()
+        off = np.concatenate([[0], np.cumsum(K)]).astype(np.int64)
+        crit, _ = critical_value(np.concatenate(vals), off, alpha, with_hist=False)
+        for k in range(n):
+            xs = np.sort(vals[k])                       # NaN last
+            undecided = False
+            for a in range(alpha.shape[0]):
+                j = min(max(int(math.ceil(alpha[a] * K[k])), 1), int(K[k]))
+                delta = int(math.ceil(z * math.sqrt(K[k] * alpha[a] * (1.0 - alpha[a]))))
+                lo_r, hi_r = max(1, j - delta), min(int(K[k]), j + delta)
+                if xs[lo_r - 1] <= dd[k] <= xs[hi_r - 1]:
+                    undecided = True
+            if undecided and K[k] < K_max:
+                K_new[k] = min(2 * K[k], K_max)
+    accepted = (dd[:, None] <= crit).astype(np.uint8)
+    return dict(crit=crit, accepted=accepted, K_used=K, rounds=rounds, evals=evals)
 
 
 def critical_value(x, seg_off, alpha, n_bins=200, hist_hi=50.0, with_hist=True):

@@ -424,6 +424,52 @@ int fc_generate_universes(const fc_grid *g, int64_t n_pts, const int64_t *p,
     return FC_OK;
 }
 
+int fc_region(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t *pts, int64_t K0,
+              int64_t K_max, double z, uint64_t seed, int32_t n_alpha, const double *alpha,
+              const double *dchi2_data, double *crit, uint8_t *accepted, int64_t *K_used,
+              int32_t *n_rounds, double *n_evals, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_region: grid is NULL");
+    if (form != FC_FORM_FP64 && form != FC_FORM_FP32 && form != FC_FORM_SPLIT_BF16 &&
+        form != FC_FORM_SPLIT_FP16)
+        return fail(FC_ERR_INVALID_ARG, "fc_region: bad form %d", form);
+    if (!(g->forms & (uint32_t)form))
+        return fail(FC_ERR_STATE, "fc_region: form %d was not built for this grid", form);
+    if (!g->lf_ok)
+        return fail(FC_ERR_NOT_PD, "fc_region: fractional covariance not positive definite");
+    if (pts ? n_pts < 1 : n_pts != g->G)
+        return fail(FC_ERR_INVALID_ARG, "fc_region: n_pts must be >= 1 (or G with pts NULL)");
+    if (pts)
+        for (int64_t k = 0; k < n_pts; ++k)
+            if (pts[k] < 0 || pts[k] >= g->G)
+                return fail(FC_ERR_INVALID_ARG, "fc_region: pts[%lld] outside the grid",
+                            (long long)k);
+    if (K0 < 1 || K_max < K0 || K_max > (int64_t(1) << 24))
+        return fail(FC_ERR_INVALID_ARG, "fc_region: need 1 <= K0 <= K_max <= 2^24");
+    if (!(z >= 0.0) || !std::isfinite(z)) return fail(FC_ERR_INVALID_ARG, "fc_region: bad z");
+    if (n_alpha < 1 || n_alpha > 4 || !alpha)
+        return fail(FC_ERR_INVALID_ARG, "fc_region: n_alpha must be 1..4");
+    for (int a = 0; a < n_alpha; ++a)
+        if (!(alpha[a] > 0.0 && alpha[a] <= 1.0))
+            return fail(FC_ERR_INVALID_ARG, "fc_region: alpha[%d] not in (0,1]", a);
+    if (!dchi2_data || !crit || !accepted || !K_used || !n_rounds || !n_evals)
+        return fail(FC_ERR_INVALID_ARG, "fc_region: NULL argument");
+    hipError_t e = hipSuccess;
+    const int rc = fcx::region_run(g, form, n_pts, pts, K0, K_max, z, seed, n_alpha, alpha,
+                                   dchi2_data, crit, accepted, K_used, n_rounds, n_evals, stream,
+                                   &e);
+    if (rc != FC_OK) {
+        if (rc == FC_ERR_NOMEM) {
+            (void)hipGetLastError();
+            return fail(FC_ERR_NOMEM, "fc_region: device allocation failed (%s)",
+                        hipGetErrorString(e));
+        }
+        return hip_fail(e, "fc_region");
+    }
+    return FC_OK;
+}
+
 int fc_grid_inverse_cov(const fc_grid *g, int64_t q0, int64_t nq, double *out, hipStream_t stream)
 {
     g_last_error.clear();

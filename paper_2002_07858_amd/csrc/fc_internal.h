@@ -212,6 +212,16 @@ int serve_split_univ_per_item();
 int serve_slots_fp32(int ns);
 int serve_slots_split(int nk, int nb, bool fp16);
 
+hipError_t launch_crit_gapped(int64_t n_seg, const int64_t *seg_lo, const int64_t *seg_hi,
+                              const double *x, int n_alpha, const double *alpha, double *crit,
+                              hipStream_t st);
+hipError_t launch_select_ranks(int64_t n_seg, const int64_t *seg_lo, const int64_t *seg_hi,
+                               const double *x, int n_q, const int64_t *ranks, double *out,
+                               hipStream_t st);
+int region_run(const fc_grid *g, int form, int64_t n_pts, const int64_t *pts_host, int64_t K0,
+               int64_t K_max, double z, uint64_t seed, int n_alpha, const double *alpha,
+               const double *dchi2_data, double *crit, uint8_t *accepted, int64_t *K_used,
+               int32_t *n_rounds, double *n_evals, hipStream_t st, hipError_t *err);
 hipError_t launch_chol_frac(const double *F, int N, double *LF, int *flag, hipStream_t st);
 hipError_t launch_gen_universes(const fc_grid *g, int64_t n_pts, const int64_t *p,
                                 const int64_t *seg_off, const int64_t *u_first, uint64_t seed,

@@ -31,10 +31,15 @@ __device__ __forceinline__ double from_order_key(unsigned long long k)
     return __longlong_as_double((long long)b);
 }
 
-__global__ __launch_bounds__(256) void k_crit(const int64_t *__restrict__ seg_off,
+// Segment s is x[seg_lo[s] .. seg_hi[s]).  The order statistics taken are
+// ranks ceil(alpha K) (alpha mode), or ranks[s][a] (1-based, clamped to
+// [1, K]) when a rank table is given.
+__global__ __launch_bounds__(256) void k_crit(const int64_t *__restrict__ seg_lo,
+                                             const int64_t *__restrict__ seg_hi,
                                              const double *__restrict__ x, int n_alpha,
-                                             AlphaArgs alpha, double *__restrict__ crit,
-                                             int n_bins, double hist_hi, int64_t *__restrict__ hist)
+                                             AlphaArgs alpha, const int64_t *__restrict__ ranks,
+                                             double *__restrict__ crit, int n_bins,
+                                             double hist_hi, int64_t *__restrict__ hist)
 {
     __shared__ unsigned int cnt[kMaxAlpha][256];
     __shared__ unsigned long long prefix[kMaxAlpha];
@@ -43,7 +48,7 @@ __global__ __launch_bounds__(256) void k_crit(const int64_t *__restrict__ seg_of
 
     const int64_t sgi = blockIdx.x;
     const int tid = threadIdx.x;
-    const int64_t lo = seg_off[sgi], hi = seg_off[sgi + 1];
+    const int64_t lo = seg_lo[sgi], hi = seg_hi[sgi];
     const bool valid = lo >= 0 && hi >= lo;
     const int64_t K = valid ? hi - lo : 0;
 
@@ -72,7 +77,8 @@ __global__ __launch_bounds__(256) void k_crit(const int64_t *__restrict__ seg_of
         return;
     }
     if (tid < n_alpha) {
-        long long j = (long long)ceil(alpha.a[tid] * (double)K);
+        long long j = ranks ? (long long)ranks[sgi * n_alpha + tid]
+                            : (long long)ceil(alpha.a[tid] * (double)K);
         if (j < 1) j = 1;
         if (j > K) j = K;
         rank[tid] = j - 1;  // 0-based
@@ -116,8 +122,30 @@ hipError_t launch_crit(int64_t n_seg, const int64_t *seg_off, const double *x, i
     AlphaArgs aa;
     for (int a = 0; a < kMaxAlpha; ++a) aa.a[a] = (a < n_alpha) ? alpha[a] : 1.0;
     const size_t lds = hist ? sizeof(unsigned int) * (size_t)(n_bins + 1) : 0;
-    hipLaunchKernelGGL(k_crit, dim3((unsigned)n_seg), dim3(256), lds, st, seg_off, x, n_alpha, aa,
-                       crit, n_bins, hist_hi, hist);
+    hipLaunchKernelGGL(k_crit, dim3((unsigned)n_seg), dim3(256), lds, st, seg_off, seg_off + 1, x,
+                       n_alpha, aa, nullptr, crit, n_bins, hist_hi, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_crit_gapped(int64_t n_seg, const int64_t *seg_lo, const int64_t *seg_hi,
+                              const double *x, int n_alpha, const double *alpha, double *crit,
+                              hipStream_t st)
+{
+    AlphaArgs aa;
+    for (int a = 0; a < kMaxAlpha; ++a) aa.a[a] = (a < n_alpha) ? alpha[a] : 1.0;
+    hipLaunchKernelGGL(k_crit, dim3((unsigned)n_seg), dim3(256), 0, st, seg_lo, seg_hi, x, n_alpha,
+                       aa, nullptr, crit, 0, 1.0, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_ranks(int64_t n_seg, const int64_t *seg_lo, const int64_t *seg_hi,
+                               const double *x, int n_q, const int64_t *ranks, double *out,
+                               hipStream_t st)
+{
+    AlphaArgs aa;
+    for (int a = 0; a < kMaxAlpha; ++a) aa.a[a] = 1.0;
+    hipLaunchKernelGGL(k_crit, dim3((unsigned)n_seg), dim3(256), 0, st, seg_lo, seg_hi, x, n_q, aa,
+                       ranks, out, 0, 1.0, nullptr);
     return hipGetLastError();
 }
 

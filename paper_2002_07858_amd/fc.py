@@ -42,7 +42,8 @@ FC_REQ_DONE = 2
 FC_REQ_FAILED = -1
 
 EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
-            "fc_generate_universes", "fc_data_scan", "fc_acceptance", "fc_grid_inverse_cov", "fc_grid_info",
+            "fc_generate_universes", "fc_region", "fc_data_scan", "fc_acceptance",
+            "fc_grid_inverse_cov", "fc_grid_info",
             "fc_grid_device_bytes", "fc_grid_destroy", "fc_last_error", "fc_server_create", "fc_server_submit", "fc_server_poll",
             "fc_server_stats", "fc_server_destroy")
 
@@ -74,6 +75,8 @@ def lib():
         L.fc_critical_value.argtypes = [_i64, _p, _p, _i32, _p, _p, _i32, _dbl, _p, _p]
         L.fc_generate_universes.argtypes = [_p, _i64, _p, _p, _p, ctypes.c_uint64, _i64, _p, _p,
                                             _p, _p]
+        L.fc_region.argtypes = [_p, _i32, _i64, _p, _i64, _i64, _dbl, ctypes.c_uint64, _i32, _p,
+                                _p, _p, _p, _p, _p, _p, _p]
         L.fc_data_scan.argtypes = [_p, _p, _p, _p, _p, _p]
         L.fc_acceptance.argtypes = [_p, _i64, _p, _p, _i64, _p, _p, _p]
         L.fc_grid_inverse_cov.argtypes = [_p, _i64, _i64, _p, _p]
@@ -94,7 +97,8 @@ def lib():
         for name in ("fc_server_create", "fc_server_submit", "fc_server_poll", "fc_server_stats"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
-                     "fc_generate_universes", "fc_data_scan", "fc_acceptance", "fc_grid_inverse_cov", "fc_grid_info"):
+                     "fc_generate_universes", "fc_region", "fc_data_scan", "fc_acceptance",
+            "fc_grid_inverse_cov", "fc_grid_info"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -236,6 +240,29 @@ def fc_generate_universes(grid: Grid, p, seg_off, seed: int, d, p_idx=None, coun
                                        ctypes.c_uint64(int(seed) % 2**64), K,
                                        _dev(d, "f64", "d"), _dev(p_idx, "i64", "p_idx"),
                                        _dev(counts, "i32", "counts"), _stream(stream)))
+
+
+def fc_region(grid: Grid, form: int, dchi2_data, crit, accepted, pts=None, K0=256, K_max=4096,
+              z=2.0, seed=0, alpha=(0.6827, 0.9, 0.95), stream=None):
+    """Feldman-Cousins region with per-point universe counts (synchronous).
+
+    pts: host grid indices or None (every point); dchi2_data float64 CUDA [G];
+    crit float64 CUDA [n_pts][n_alpha]; accepted uint8 CUDA [n_pts][n_alpha].
+    Returns dict(K_used=np.ndarray, rounds=int, evals=float).
+    """
+    G = fc_grid_info(grid)["G"]
+    pa = None if pts is None else _host(pts, np.int64)
+    n_pts = G if pa is None else int(pa.shape[0])
+    a = _host(np.atleast_1d(alpha), np.float64)
+    K_used = np.zeros(n_pts, dtype=np.int64)
+    rounds = ctypes.c_int32()
+    evals = ctypes.c_double()
+    _check(lib().fc_region(grid._h, int(form), n_pts, _hp(pa), int(K0), int(K_max), float(z),
+                           ctypes.c_uint64(int(seed) % 2**64), int(a.shape[0]), _hp(a),
+                           _dev(dchi2_data, "f64", "dchi2_data"), _dev(crit, "f64", "crit"),
+                           _dev(accepted, "u8", "accepted"), _hp(K_used), ctypes.byref(rounds),
+                           ctypes.byref(evals), _stream(stream)))
+    return dict(K_used=K_used, rounds=rounds.value, evals=evals.value)
 
 
 def fc_data_scan(grid: Grid, dchi2_data, central=None, stream=None):

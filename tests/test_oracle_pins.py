@@ -500,3 +500,60 @@ def test_p12_universes_covariance_and_batching():
     d2, c2 = oracle.universes(pr.S, pr.F, [p], [0, 200], seed=11, u_first=[300])
     np.testing.assert_array_equal(d2, d[300:500])
     np.testing.assert_array_equal(c2, counts[300:500])
+
+
+# --------------------------------------------------------------------------
+# P13: the region with per-point universe counts
+# --------------------------------------------------------------------------
+def _region_problem():
+    pr = fcgen.make_problem("c1", K=1, true_subset=[0], n_axis=(6, 6))
+    c = fcgen.universes(pr.config, 40000, pr.S[14], pr.F, 1)[0]
+    dd, _, _ = oracle.data_scan(pr.S, pr.F, c)
+    return pr, dd
+
+
+def test_p13_region_refining_everything_equals_one_draw():
+    """With an unbounded band (it spans every value of the point) and a data
+    value inside every point's range, each point is refined to K_max; the
+    universes drawn in doubling rounds must give exactly the values of drawing
+    0..K_max-1 at once (the stream depends only on (seed, p, j))."""
+    pr, _ = _region_problem()
+    dd = np.full(pr.G, 1.0)
+    pts = np.array([0, 7, 14, 20])
+    r = oracle.region(pr.S, pr.F, pts, 16, 128, 1e9, 3, (0.6827, 0.9), dd)
+    assert np.all(r["K_used"] == 128) and r["rounds"] == 4
+    assert r["evals"] == float((16 + 16 + 32 + 64) * len(pts) * pr.G)
+    seg = np.arange(len(pts) + 1) * 128
+    d, _ = oracle.universes(pr.S, pr.F, pts, seg, 3)
+    s = oracle.scan(pr.S, pr.F, d, np.repeat(pts, 128))
+    crit, _ = oracle.critical_value(s["dchi2"], seg, (0.6827, 0.9), with_hist=False)
+    np.testing.assert_array_equal(r["crit"], crit)
+    np.testing.assert_array_equal(r["accepted"], (dd[pts][:, None] <= crit).astype(np.uint8))
+
+
+def test_p13_region_without_refinement():
+    pr, dd = _region_problem()
+    r = oracle.region(pr.S, pr.F, np.arange(pr.G), 40, 40, 0.0, 5, (0.9,), dd)
+    assert r["rounds"] == 1 and np.all(r["K_used"] == 40)
+    # a zero-width band still refines a point whose value equals x_(j)
+    r2 = oracle.region(pr.S, pr.F, np.arange(pr.G), 40, 80, 0.0, 5, (0.9,), dd)
+    hit = np.flatnonzero(r2["K_used"] == 80)
+    assert np.all(np.abs(dd[hit] - r["crit"][hit, 0]) == 0.0)
+
+
+def test_p13_region_coverage():
+    """Data drawn at the true point are inside its region with probability
+    alpha, also when the point's universe count adapts to the data."""
+    pr = fcgen.make_problem("c1", K=1, true_subset=[0], n_axis=(5, 5))
+    p = 12
+    M = 200
+    data = fcgen.universes(pr.config, 50000, pr.S[p], pr.F, M)
+    alpha = (0.6827, 0.9)
+    hits = np.zeros(2)
+    for m in range(M):
+        dd, _, _ = oracle.data_scan(pr.S, pr.F, data[m])
+        r = oracle.region(pr.S, pr.F, [p], 50, 800, 2.0, 100 + m, alpha, dd)
+        hits += r["accepted"][0]
+    for a, al in enumerate(alpha):
+        sigma = math.sqrt(al * (1 - al) / M + al * (1 - al) / 50)
+        assert abs(hits[a] / M - al) <= 4 * sigma, (al, hits[a] / M)
