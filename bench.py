@@ -13,7 +13,9 @@ data from the toy oscillation model, resident in HBM before the timed region.
 
 One step = covariance factors for every grid point (FP64 Cholesky + inverse,
 stored in the scan form) + the scan of all universes (minimum, argmin,
-Delta chi^2) + critical values.  A serving leg then replays a seeded Poisson
+Delta chi^2) + critical values.  A region leg then builds the whole FC
+surface (every grid point a true point, universes drawn on the device, counts
+refined near the contour), and a serving leg replays a seeded Poisson
 stream of FC requests (K log-uniform in [500, 20000], three resident grids)
 through a plain FIFO loop and through the continuous-batching server and
 reports p50/p99 latency beside throughput.  Prints one JSON line.
@@ -262,6 +264,41 @@ def serving_bench(n_req: int, loads=(0.8,)):
     return out
 
 
+# ---------------------------------------------------------------------------
+# Full-surface FC: every grid point a true point, universes drawn on the
+# device, per-point universe counts refined near the contour (fc_region).
+# ---------------------------------------------------------------------------
+def region_bench(pr, form_name: str, K0=256, K_max=4096, z=2.0):
+    import torch
+    import fcgen
+    import paper_2002_07858_amd as fc
+    form = {"fp32": fc.FC_FORM_FP32, "fp64": fc.FC_FORM_FP64, "split_bf16": fc.FC_FORM_SPLIT_BF16,
+            "split_fp16": fc.FC_FORM_SPLIT_FP16}[form_name]
+    c = fcgen.universes(pr.config, 77777, pr.S[pr.G // 2 + 17], pr.F, 1)[0]
+    g = fc.fc_build_grid(pr.axes, pr.S, central=c)
+    fc.fc_build_covariance(g, pr.F, pr.stat_mode, pr.stat_diag, forms=form | fc.FC_FORM_FP64)
+    dd = torch.empty(pr.G, dtype=torch.float64, device="cuda")
+    fc.fc_data_scan(g, dd)
+    crit = torch.empty((pr.G, len(ALPHA)), dtype=torch.float64, device="cuda")
+    acc = torch.empty((pr.G, len(ALPHA)), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = fc.fc_region(g, form, dd, crit, acc, K0=K0, K_max=K_max, z=z, seed=2020,
+                        alpha=ALPHA)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.destroy()
+    Ku = info["K_used"]
+    counts = {int(k): int((Ku == k).sum()) for k in np.unique(Ku)}
+    uniform = float(pr.G) * K_max * pr.G
+    return {"grid_points": pr.G, "form": form_name, "K0": K0, "K_max": K_max, "z": z,
+            "seconds": dt, "rounds": info["rounds"], "evals": info["evals"],
+            "evals_per_s": info["evals"] / dt, "points_per_K": counts,
+            "mean_K": float(Ku.mean()),
+            "evals_vs_uniform_K_max": info["evals"] / uniform,
+            "region_points": [int(x) for x in acc.sum(dim=0).cpu().tolist()]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +312,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=None,
                     help="requests in the serving leg (0 to skip it; default 200 for c2)")
+    ap.add_argument("--region", type=int, default=None,
+                    help="1: also run the full-surface region leg (default on for c2)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (counter calibration)")
     ap.add_argument("--serving-loads", default="0.5,0.8",
@@ -291,6 +330,8 @@ def main():
         args.cpu_per_point = wl["cpu_per_point"]
     if args.serving_requests is None:
         args.serving_requests = wl["serving"]
+    if args.region is None:
+        args.region = 1 if args.workload == "c2" else 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the scan is "
               "single-GPU by design; see the multi-GPU section of the design notes.",
@@ -403,6 +444,9 @@ def main():
         res["cpu_baseline"] = base
         res["err_vs_fp64"] = rep
     grid.destroy()
+    if args.region:
+        log("[bench] full-surface region")
+        res["region"] = region_bench(pr, args.form)
     if args.serving_requests > 0:
         res["serving"] = serving_bench(args.serving_requests,
                                        tuple(float(x) for x in args.serving_loads.split(",")))

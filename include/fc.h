@@ -177,6 +177,29 @@ int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2
                       double hist_hi, int64_t *hist, hipStream_t stream);
 
 /*
+ * fc_scan_fixed_m -- Algorithm 1 as printed: one matrix M for the whole grid
+ * scan of a universe, and its iteration (Section 2, step 5: update M at the
+ * minimiser and scan again until the minimiser repeats).  Per universe k,
+ * M = Sigma_m^{-1} with m = p_idx[k] first; after a scan with minimiser
+ * q_min != m (and fewer than max_iter re-scans done) m = q_min and the
+ * universe is scanned again.  With the last M:
+ *     chi2(d, q) = (d - S_q)^T M (d - S_q)   for every q (min: strict "<" in
+ *     grid order, lowest q among equal values),  dchi2 = chi2(d, S_p) - min.
+ * max_iter = 0 is the fixed-matrix scan.  FP64 (needs FC_FORM_FP64): chi2 is
+ * formed as |y|^2 + |t_q|^2 - 2 y.t_q in the space whitened by W_m, the cross
+ * term on the FP64 matrix cores.
+ *   d, p_idx   device [K][N] FP64, [K] int64 (0 <= p < G, else FC_ERR_INVALID_ARG)
+ *   dchi2, chi2_min, chi2_p  device out [K] FP64; argmin device out [K] int64
+ *   m_final    device out [K] int64 (the m of the last scan), or NULL
+ *   iters      device out [K] int32 (re-scans done), or NULL
+ * K <= 2^30, 0 <= max_iter <= 64.  Synchronous (universes are grouped by m
+ * on the host between scans).
+ */
+int fc_scan_fixed_m(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
+                    int32_t max_iter, double *dchi2, double *chi2_min, int64_t *argmin,
+                    double *chi2_p, int64_t *m_final, int32_t *iters, hipStream_t stream);
+
+/*
  * fc_generate_universes -- draw universes on the device (Section 2, steps 1
  * and 2 of the per-universe procedure: the prediction at the true point is
  * fluctuated into fake data).  Row r in [seg_off[k], seg_off[k+1]) is universe

@@ -15,6 +15,8 @@ Functions follow arXiv:2002.07858:
   critical_value         -- Section 1 / Figure 1 (quantiles of Delta chi^2)
   data_scan / acceptance -- Section 1 (Delta chi^2 of the observed data at every
                             point, accepted where it is within the critical value)
+  scan_fixed_m           -- Algorithm 1 as printed (one matrix M for the whole grid,
+                            M = Sigma_p^{-1}) and its iteration (Section 2, step 5)
   region                 -- Section 2's construction for a set of true points with
                             per-point universe counts, refined near the contour
                             (the closing section's proposal)
@@ -89,9 +91,12 @@ def lib():
         L.fco_normal.argtypes = [_u64, _i64, _i64, _i32]
         L.fco_normal.restype = _dbl
         L.fco_universes.argtypes = [_i64, _i32, _p, _p, _i64, _p, _p, _p, _u64, _p, _p, _i32]
+        L.fco_scan_fixed_m.argtypes = [_i64, _i32, _p, _p, _i32, _p, _i64, _p, _p, _i32, _p, _p,
+                                       _p, _p, _p, _p, _i32]
         for name in ("fco_grid_coords", "fco_covariance", "fco_cholesky", "fco_factor_range",
                      "fco_scan", "fco_scan_init", "fco_scan_range", "fco_scan_finish",
-                     "fco_chi2_table", "fco_critical_value", "fco_universes"):
+                     "fco_chi2_table", "fco_critical_value", "fco_universes",
+                     "fco_scan_fixed_m"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -252,6 +257,30 @@ def acceptance(dchi2_data, p, crit):
     for k in range(p.shape[0]):
         if 0 <= p[k] < dd.shape[0] and dd[p[k]] <= crit[k]:
             out[k] = 1
+    return out
+
+
+def scan_fixed_m(S, F, d, p_idx, max_iter=0, stat_mode=STAT_PEARSON, stat_diag=None,
+                 nthreads=None) -> dict:
+    """Algorithm 1 with one M per universe: M = Sigma_m^{-1}, m = the true point,
+    re-scanned with m = q_min up to max_iter times while q_min != m."""
+    S = _f64(S)
+    d = _f64(d)
+    p_idx = _i64a(p_idx)
+    G, N = S.shape
+    K = d.shape[0]
+    out = {k: np.empty(K) for k in ("dchi2", "chi2_min", "chi2_p")}
+    out["argmin"] = np.empty(K, dtype=np.int64)
+    out["m_final"] = np.empty(K, dtype=np.int64)
+    out["iters"] = np.empty(K, dtype=np.int32)
+    sd = None if stat_diag is None else _f64(stat_diag)
+    rc = lib().fco_scan_fixed_m(G, N, _ptr(S), _ptr(_f64(F)), int(stat_mode), _ptr(sd), K,
+                                _ptr(d), _ptr(p_idx), int(max_iter), _ptr(out["dchi2"]),
+                                _ptr(out["chi2_min"]), _ptr(out["argmin"]), _ptr(out["chi2_p"]),
+                                _ptr(out["m_final"]), _ptr(out["iters"]),
+                                nthreads or default_threads())
+    if rc != 0:
+        raise OracleError("bad arguments or covariance not positive definite")
     return out
 
 

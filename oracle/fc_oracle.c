@@ -488,3 +488,88 @@ int fco_universes(int64_t G, int32_t N, const double *S, const double *LF, int64
     fco_parallel(n_pts, nthreads, fco_univ_task, &c);
     return 0;
 }
+
+/* ---- one matrix per universe (Algorithm 1 as printed), iterated (step 5) --- */
+struct fco_fixed_ctx {
+    int64_t G;
+    int32_t N;
+    const double *S, *F, *stat_diag;
+    int32_t stat_mode;
+    const double *d;
+    const int64_t *p_idx;
+    int32_t max_iter;
+    double *dchi2, *chi2_min, *chi2_p;
+    int64_t *argmin, *m_final;
+    int32_t *iters;
+    int failed;
+};
+
+static void fco_fixed_task(void *vctx, int64_t lo, int64_t hi)
+{
+    struct fco_fixed_ctx *c = (struct fco_fixed_ctx *)vctx;
+    const int32_t N = c->N;
+    double *A = (double *)malloc(sizeof(double) * N * N);
+    double *L = (double *)malloc(sizeof(double) * N * N);
+    if (!A || !L) {
+        c->failed = 1;
+        free(A);
+        free(L);
+        return;
+    }
+    for (int64_t k = lo; k < hi; ++k) {
+        const double *dk = c->d + k * N;
+        const int64_t p = c->p_idx[k];
+        int64_t m = p;
+        int32_t it = 0;
+        double best, cp;
+        int64_t qmin;
+        for (;;) {
+            /* M = Sigma_m^{-1}, used through the Cholesky factor of Sigma_m */
+            fco_covariance(N, c->S + m * N, c->F, c->stat_mode, c->stat_diag, A);
+            if (fco_cholesky(N, A, L) != 0) {
+                c->failed = 1;
+                break;
+            }
+            best = INFINITY;
+            qmin = p;
+            cp = NAN;
+            for (int64_t q = 0; q < c->G; ++q) {
+                const double v = fco_chi2(N, L, dk, c->S + q * N);
+                if (q == p) cp = v;
+                if (v < best) {
+                    best = v;
+                    qmin = q;
+                }
+            }
+            if (it == c->max_iter || qmin == m) break;
+            m = qmin;
+            ++it;
+        }
+        c->dchi2[k] = cp - best;
+        c->chi2_min[k] = best;
+        c->argmin[k] = qmin;
+        c->chi2_p[k] = cp;
+        c->m_final[k] = m;
+        c->iters[k] = it;
+    }
+    free(A);
+    free(L);
+}
+
+int fco_scan_fixed_m(int64_t G, int32_t N, const double *S, const double *F, int32_t stat_mode,
+                     const double *stat_diag, int64_t K, const double *d, const int64_t *p_idx,
+                     int32_t max_iter, double *dchi2, double *chi2_min, int64_t *argmin,
+                     double *chi2_p, int64_t *m_final, int32_t *iters, int32_t nthreads)
+{
+    if (G <= 0 || N <= 0 || N > 256 || !S || !F || K < 0 || max_iter < 0 ||
+        (stat_mode == 1 && !stat_diag))
+        return -1;
+    if (K > 0 && (!d || !p_idx || !dchi2 || !chi2_min || !argmin || !chi2_p || !m_final || !iters))
+        return -1;
+    for (int64_t k = 0; k < K; ++k)
+        if (p_idx[k] < 0 || p_idx[k] >= G) return -1;
+    struct fco_fixed_ctx c = {G, N, S, F, stat_diag, stat_mode, d, p_idx, max_iter,
+                              dchi2, chi2_min, chi2_p, argmin, m_final, iters, 0};
+    fco_parallel(K, nthreads, fco_fixed_task, &c);
+    return c.failed ? -2 : 0;
+}

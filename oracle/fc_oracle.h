@@ -95,6 +95,19 @@ int fco_critical_value(int64_t n_seg, const int64_t *seg_off, const double *x,
                        int32_t n_alpha, const double *alpha, double *crit,
                        int32_t n_bins, double hist_hi, int64_t *hist);
 
+/* Algorithm 1 as printed, with one matrix M for the whole grid: per universe
+ * M = Sigma_m^{-1} with m the true point; with max_iter > 0, step 5 of the
+ * procedure in Section 2: after a scan, if the minimiser q_min differs from
+ * m, set m = q_min and scan again (at most max_iter times).  chi2(d, q) =
+ * (d - S_q)^T M (d - S_q) via the Cholesky factor of Sigma_m; Delta chi2 =
+ * chi2(d, S_p) - min, both with the last M.  Outputs per universe: dchi2,
+ * chi2_min, argmin, chi2_p, m_final, iters (re-scans done).  Returns -2 if a
+ * covariance is not positive definite. */
+int fco_scan_fixed_m(int64_t G, int32_t N, const double *S, const double *F, int32_t stat_mode,
+                     const double *stat_diag, int64_t K, const double *d, const int64_t *p_idx,
+                     int32_t max_iter, double *dchi2, double *chi2_min, int64_t *argmin,
+                     double *chi2_p, int64_t *m_final, int32_t *iters, int32_t nthreads);
+
 /* ---- universes (Section 2, steps 1-2: fluctuate the prediction at p) -----
  *
  * Counter-based stream, the same definition on every side:

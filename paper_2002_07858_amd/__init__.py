@@ -10,7 +10,8 @@ from .fc import (FC_ERR_DEVICE, FC_ERR_INVALID_ARG, FC_ERR_NOMEM, FC_ERR_NOT_PD,
                  FC_REQ_DONE, FC_REQ_FAILED, FC_REQ_QUEUED, FC_REQ_RUNNING, FC_SCHED_FAIR,
                  FC_SCHED_FIFO,
                  FC_STAT_PEARSON, FCError, Grid, Server, fc_acceptance, fc_build_covariance,
-                 fc_build_grid, fc_critical_value, fc_data_scan, fc_generate_universes, fc_region, fc_grid_destroy, fc_grid_device_bytes, fc_grid_info,
+                 fc_build_grid, fc_critical_value, fc_data_scan, fc_generate_universes, fc_region,
+                 fc_scan_fixed_m, fc_grid_destroy, fc_grid_device_bytes, fc_grid_info,
                  fc_grid_inverse_cov, fc_last_error, fc_scan, lib)
 from .driver import ScanOutputs, scan_problem
 

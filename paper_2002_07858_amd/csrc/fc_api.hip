@@ -11,6 +11,8 @@
 
 #include "fc_internal.h"
 
+#include <vector>
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -467,6 +469,38 @@ int fc_region(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t *pts,
         }
         return hip_fail(e, "fc_region");
     }
+    return FC_OK;
+}
+
+int fc_scan_fixed_m(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
+                    int32_t max_iter, double *dchi2, double *chi2_min, int64_t *argmin,
+                    double *chi2_p, int64_t *m_final, int32_t *iters, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_scan_fixed_m: grid is NULL");
+    if (!(g->forms & FC_FORM_FP64))
+        return fail(FC_ERR_STATE, "fc_scan_fixed_m: needs the FP64 form");
+    if (K < 0 || K > (int64_t(1) << 30))
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_fixed_m: K=%lld not in 0..2^30", (long long)K);
+    if (max_iter < 0 || max_iter > 64)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_fixed_m: max_iter=%d not in 0..64", max_iter);
+    if (K == 0) return FC_OK;
+    if (!d || !p_idx || !dchi2 || !chi2_min || !argmin || !chi2_p)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_fixed_m: NULL device pointer");
+    // true points are read back for the grouping: check them there
+    std::vector<int64_t> hp(K);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(hp.data(), p_idx, sizeof(int64_t) * K, hipMemcpyDeviceToHost,
+                            stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return hip_fail(e, "fc_scan_fixed_m: read p_idx");
+    for (int64_t k = 0; k < K; ++k)
+        if (hp[k] < 0 || hp[k] >= g->G)
+            return fail(FC_ERR_INVALID_ARG, "fc_scan_fixed_m: p_idx[%lld]=%lld outside the grid",
+                        (long long)k, (long long)hp[k]);
+    if ((e = fcx::fixed_run(g, K, d, p_idx, max_iter, dchi2, chi2_min, argmin, chi2_p, m_final,
+                            iters, stream)) != hipSuccess)
+        return hip_fail(e, "fc_scan_fixed_m");
     return FC_OK;
 }
 

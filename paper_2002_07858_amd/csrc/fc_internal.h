@@ -218,6 +218,10 @@ hipError_t launch_crit_gapped(int64_t n_seg, const int64_t *seg_lo, const int64_
 hipError_t launch_select_ranks(int64_t n_seg, const int64_t *seg_lo, const int64_t *seg_hi,
                                const double *x, int n_q, const int64_t *ranks, double *out,
                                hipStream_t st);
+int resident_slots(const void *kernel, int block_threads);
+hipError_t fixed_run(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
+                     int max_iter, double *dchi2, double *chi2_min, int64_t *argmin,
+                     double *chi2_p, int64_t *m_final, int32_t *iters, hipStream_t st);
 int region_run(const fc_grid *g, int form, int64_t n_pts, const int64_t *pts_host, int64_t K0,
                int64_t K_max, double z, uint64_t seed, int n_alpha, const double *alpha,
                const double *dchi2_data, double *crit, uint8_t *accepted, int64_t *K_used,

@@ -394,7 +394,7 @@ __global__ __launch_bounds__(256) void k_finalize(int64_t K, const int64_t *__re
 // ---------------------------------------------------------------------------
 // Resident block slots of a kernel on the current device: CUs x blocks per CU
 // from the occupancy calculator.
-static int resident_slots(const void *kernel, int block_threads)
+int resident_slots(const void *kernel, int block_threads)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

@@ -42,7 +42,8 @@ FC_REQ_DONE = 2
 FC_REQ_FAILED = -1
 
 EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
-            "fc_generate_universes", "fc_region", "fc_data_scan", "fc_acceptance",
+            "fc_scan_fixed_m", "fc_generate_universes", "fc_region", "fc_data_scan",
+            "fc_acceptance",
             "fc_grid_inverse_cov", "fc_grid_info",
             "fc_grid_device_bytes", "fc_grid_destroy", "fc_last_error", "fc_server_create", "fc_server_submit", "fc_server_poll",
             "fc_server_stats", "fc_server_destroy")
@@ -75,6 +76,7 @@ def lib():
         L.fc_critical_value.argtypes = [_i64, _p, _p, _i32, _p, _p, _i32, _dbl, _p, _p]
         L.fc_generate_universes.argtypes = [_p, _i64, _p, _p, _p, ctypes.c_uint64, _i64, _p, _p,
                                             _p, _p]
+        L.fc_scan_fixed_m.argtypes = [_p, _i64, _p, _p, _i32, _p, _p, _p, _p, _p, _p, _p]
         L.fc_region.argtypes = [_p, _i32, _i64, _p, _i64, _i64, _dbl, ctypes.c_uint64, _i32, _p,
                                 _p, _p, _p, _p, _p, _p, _p]
         L.fc_data_scan.argtypes = [_p, _p, _p, _p, _p, _p]
@@ -97,7 +99,8 @@ def lib():
         for name in ("fc_server_create", "fc_server_submit", "fc_server_poll", "fc_server_stats"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
-                     "fc_generate_universes", "fc_region", "fc_data_scan", "fc_acceptance",
+                     "fc_scan_fixed_m", "fc_generate_universes", "fc_region", "fc_data_scan",
+            "fc_acceptance",
             "fc_grid_inverse_cov", "fc_grid_info"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -224,6 +227,18 @@ def fc_critical_value(seg_off, dchi2, alpha, crit, n_bins=200, hist_hi=50.0, his
                                    _dev(dchi2, "f64", "dchi2"), int(a.shape[0]), _hp(a),
                                    _dev(crit, "f64", "crit"), int(n_bins), float(hist_hi),
                                    _dev(hist, "i64", "hist"), _stream(stream)))
+
+
+def fc_scan_fixed_m(grid: Grid, d, p_idx, dchi2, chi2_min, argmin, chi2_p, max_iter=0,
+                    m_final=None, iters=None, stream=None):
+    """One matrix per universe scan (M = Sigma_m^-1, m = p, iterated up to
+    max_iter times at the minimiser); synchronous; torch CUDA tensors."""
+    K = int(d.shape[0])
+    _check(lib().fc_scan_fixed_m(grid._h, K, _dev(d, "f64", "d"), _dev(p_idx, "i64", "p_idx"),
+                                 int(max_iter), _dev(dchi2, "f64", "dchi2"),
+                                 _dev(chi2_min, "f64", "chi2_min"), _dev(argmin, "i64", "argmin"),
+                                 _dev(chi2_p, "f64", "chi2_p"), _dev(m_final, "i64", "m_final"),
+                                 _dev(iters, "i32", "iters"), _stream(stream)))
 
 
 def fc_generate_universes(grid: Grid, p, seg_off, seed: int, d, p_idx=None, counts=None,

@@ -557,3 +557,58 @@ def test_p13_region_coverage():
     for a, al in enumerate(alpha):
         sigma = math.sqrt(al * (1 - al) / M + al * (1 - al) / 50)
         assert abs(hits[a] / M - al) <= 4 * sigma, (al, hits[a] / M)
+
+
+# --------------------------------------------------------------------------
+# P14: one matrix for the whole grid (Algorithm 1 as printed) and its
+# iteration (Section 2, step 5)
+# --------------------------------------------------------------------------
+def _exact_fixed(S, F, d, p, max_iter):
+    """Exact rational Algorithm 1 with M = Sigma_m^{-1} (Gauss-Jordan inverse),
+    m starting at p and moved to q_min while it changes (at most max_iter)."""
+    m, it = p, 0
+    while True:
+        Minv = exact_fc.inverse(exact_fc.covariance(S[m], F))
+        vals = [exact_fc.chi2(d, Sq, Minv) for Sq in S]
+        best, qmin = None, p
+        for q, v in enumerate(vals):
+            if best is None or v < best:
+                best, qmin = v, q
+        if it == max_iter or qmin == m:
+            return vals[p] - best, best, qmin, vals[p], m, it
+        m, it = qmin, it + 1
+
+
+@pytest.mark.parametrize("max_iter", [0, 1, 10])
+def test_p14_fixed_matrix_exact_rational(max_iter):
+    S, F, d, p = _p1_problem()
+    Sn = np.array(S, dtype=np.float64)
+    Fn = np.array([[float(x) for x in row] for row in F])
+    dn = np.array(d, dtype=np.float64)
+    r = oracle.scan_fixed_m(Sn, Fn, dn, np.array(p), max_iter)
+    n_moved = 0
+    for k in range(len(d)):
+        dc, cmin, am, cp, m, it = _exact_fixed(S, F, d[k], p[k], max_iter)
+        scale = max(1.0, float(cp))
+        assert r["argmin"][k] == am and r["m_final"][k] == m and r["iters"][k] == it
+        assert abs(r["dchi2"][k] - float(dc)) <= 1e-14 * scale
+        assert abs(r["chi2_min"][k] - float(cmin)) <= 1e-14 * scale
+        assert abs(r["chi2_p"][k] - float(cp)) <= 1e-14 * scale
+        n_moved += it > 0
+    if max_iter > 0:
+        assert n_moved > 0          # the iteration is exercised
+
+
+def test_p14_fixed_matrix_reduces_to_per_point_scan():
+    """With a covariance that does not depend on q (fixed statistical term,
+    no fractional systematics) every variant is Algorithm 1 with that one
+    matrix, so all must equal the per-point scan exactly."""
+    pr = fcgen.make_problem("c1", K=300, true_subset=[0], n_axis=(9, 9))
+    stat = np.linspace(40.0, 400.0, pr.N)
+    F0 = np.zeros((pr.N, pr.N))
+    ref = oracle.scan(pr.S, F0, pr.d, pr.p_idx, oracle.STAT_FIXED, stat)
+    for it in (0, 3):
+        r = oracle.scan_fixed_m(pr.S, F0, pr.d, pr.p_idx, it, oracle.STAT_FIXED, stat)
+        for key in ("dchi2", "chi2_min", "argmin", "chi2_p"):
+            np.testing.assert_array_equal(r[key], ref[key])
+        assert np.all(r["iters"] <= 1)
