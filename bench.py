@@ -13,7 +13,9 @@ data from the toy oscillation model, resident in HBM before the timed region.
 
 One step = covariance factors for every grid point (FP64 Cholesky + inverse,
 stored in the scan form) + the scan of all universes (minimum, argmin,
-Delta chi^2) + critical values.  A region leg then builds the whole FC
+Delta chi^2) + critical values.  A one-matrix leg runs Algorithm 1 as
+printed (one M per universe, and its iteration) on the FP64 matrix cores; a
+region leg then builds the whole FC
 surface (every grid point a true point, universes drawn on the device, counts
 refined near the contour), and a serving leg replays a seeded Poisson
 stream of FC requests (K log-uniform in [500, 20000], three resident grids)
@@ -265,6 +267,56 @@ def serving_bench(n_req: int, loads=(0.8,)):
 
 
 # ---------------------------------------------------------------------------
+# One matrix per universe scan (Algorithm 1 as printed) and its iteration
+# (Section 2, step 5): a GEMM on the FP64 matrix cores.
+# ---------------------------------------------------------------------------
+def fixed_bench(pr, d_t, p_t):
+    import torch
+    import paper_2002_07858_amd as fc
+    g = fc.fc_build_grid(pr.axes, pr.S)
+    fc.fc_build_covariance(g, pr.F, pr.stat_mode, pr.stat_diag, forms=fc.FC_FORM_FP64)
+    K = int(d_t.shape[0])
+    o = {k: torch.empty(K, dtype=torch.float64, device="cuda") for k in ("dchi2", "chi2_min",
+                                                                       "chi2_p")}
+    o["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
+    it = torch.empty(K, dtype=torch.int32, device="cuda")
+    out = {}
+    for name, max_iter in (("fixed", 0), ("iterated", 10)):
+        fc.fc_scan_fixed_m(g, d_t, p_t, o["dchi2"], o["chi2_min"], o["argmin"], o["chi2_p"],
+                           max_iter, iters=it)                        # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fc.fc_scan_fixed_m(g, d_t, p_t, o["dchi2"], o["chi2_min"], o["argmin"], o["chi2_p"],
+                           max_iter, iters=it)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        scans = float(K + int(it.sum().item()))
+        evals = scans * pr.G
+        flops = evals * 2 * pr.N                         # the y.t_q cross term
+        r = {"seconds": dt, "universe_scans": scans, "evals": evals, "evals_per_s": evals / dt,
+             "roofline": {"bound": "mfma", "achieved": flops / dt / 1e12, "peak": 78.6,
+                          "unit": "TFLOP/s", "frac": flops / dt / 78.6e12}}
+        if max_iter:
+            r["iterations_hist"] = np.bincount(it.cpu().numpy()).tolist()
+        out[name] = r
+    g.destroy()
+    # the iterated results, for the CPU-baseline leg's error report
+    return out, {k: v.cpu().numpy() for k, v in o.items()}
+
+
+def fixed_err(pr, dev, n_sample=60):
+    """CPU-baseline leg: the iterated one-matrix results against the oracle on
+    a sample of universes."""
+    import oracle
+    idx = np.random.default_rng(5).choice(pr.K, n_sample, replace=False)
+    ref = oracle.scan_fixed_m(pr.S, pr.F, pr.d[idx], pr.p_idx[idx], 10)
+    scale = np.maximum(1.0, ref["chi2_p"])
+    return {"n": int(n_sample),
+            "e_rel": float((np.abs(dev["dchi2"][idx] - ref["dchi2"]) / scale).max()),
+            "argmin_agree": float((dev["argmin"][idx] == ref["argmin"]).mean())}
+
+
+# ---------------------------------------------------------------------------
 # Full-surface FC: every grid point a true point, universes drawn on the
 # device, per-point universe counts refined near the contour (fc_region).
 # ---------------------------------------------------------------------------
@@ -312,6 +364,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=None,
                     help="requests in the serving leg (0 to skip it; default 200 for c2)")
+    ap.add_argument("--fixed", type=int, default=None,
+                    help="1: also run the one-matrix scan leg (default on for c2)")
     ap.add_argument("--region", type=int, default=None,
                     help="1: also run the full-surface region leg (default on for c2)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -332,6 +386,8 @@ def main():
         args.serving_requests = wl["serving"]
     if args.region is None:
         args.region = 1 if args.workload == "c2" else 0
+    if args.fixed is None:
+        args.fixed = 1 if args.workload == "c2" else 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the scan is "
               "single-GPU by design; see the multi-GPU section of the design notes.",
@@ -444,6 +500,11 @@ def main():
         res["cpu_baseline"] = base
         res["err_vs_fp64"] = rep
     grid.destroy()
+    if args.fixed:
+        log("[bench] one-matrix scan")
+        res["fixed_matrix"], fixed_dev = fixed_bench(pr, d_t, p_t)
+        if not args.no_cpu_baseline:
+            res["fixed_matrix"]["iterated"]["err_vs_oracle"] = fixed_err(pr, fixed_dev)
     if args.region:
         log("[bench] full-surface region")
         res["region"] = region_bench(pr, args.form)

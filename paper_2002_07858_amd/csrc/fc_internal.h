@@ -125,6 +125,30 @@ __host__ __device__ constexpr int split_rec_units(int nk, int nb)
     return 256 * ceil_div(split_scale_unit(nk, nb) + 1, 256);
 }
 
+// Copy one record into LDS with direct global -> LDS loads: thread tid moves
+// 16-byte units tid, tid + 256, ...; each wave's 64 lanes land contiguously
+// at its own base, so the LDS image equals the global record.  The loads are
+// waited for (vmcnt) before the barrier that hands the buffer over.
+#ifdef __HIPCC__
+template <int CPT, int THREADS>
+__device__ __forceinline__ void record_to_lds(const uint4 *__restrict__ rec, uint4 *dst, int tid)
+{
+    // wave-uniform LDS base (M0) and a 32-bit lane offset on a uniform record base
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+    const unsigned lane_off = (unsigned)tid * 16u;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(reinterpret_cast<const char *>(rec + c * THREADS) + lane_off),
+            (__attribute__((address_space(3))) void *)(dst + c * THREADS + wbase), 16, 0, 0);
+}
+
+__device__ __forceinline__ void wait_record_loads()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt not waited for
+}
+#endif
+
 // Packed lower-triangle index for the FP64 factor.
 __host__ __device__ inline int64_t tri_index(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
 

@@ -55,12 +55,13 @@ struct Fp32Lane {
     bool have_cp;
 };
 
-// One grid point: contract the record in buf[SLOT], fold chi2 into the
-// running minimum, and (if more) stage the next record into buf[SLOT ^ 1].
-// SLOT is a template argument so that every LDS address is a constant.
-template <int NS, int NC, int SLOT>
+// One grid point: contract the record in `cur`, fold chi2 into the running
+// minimum, and (if more) bring the next record into `nxt`.  The two LDS
+// buffers are separate objects so that the compiler can tell the copy into
+// one from the reads of the other.
+template <int NS, int NC>
 __device__ __forceinline__ void fp32_point(int64_t q, bool more, const uint4 *__restrict__ R32,
-                                           uint4 (*buf)[Fp32Geo<NS>::REC], Fp32Lane<NS, NC> &L)
+                                           const uint4 *cur, uint4 *nxt, Fp32Lane<NS, NC> &L)
 {
     constexpr int NB = Fp32Geo<NS>::NB;
     constexpr int NWU = rec_w_units(NS);
@@ -71,19 +72,13 @@ __device__ __forceinline__ void fp32_point(int64_t q, bool more, const uint4 *__
     const int lane = tid & 63;
     const int grp = lane >> 4;
 
-    // the thread's share of the next record, units tid, tid+256, tid+512, in
-    // named registers (an array here ends up in scratch memory); on the last
-    // point of the range the current record is read again and not stored
-    const uint4 *rq = R32 + (more ? q + 1 : q) * REC + tid;
-    const uint4 st0 = rq[0];
-    uint4 st1 = st0, st2 = st0;
-    if constexpr (CPT > 1) st1 = rq[THREADS];
-    if constexpr (CPT > 2) st2 = rq[2 * THREADS];
+    if (more) record_to_lds<CPT, THREADS>(R32 + (q + 1) * REC, nxt, tid);
+    __builtin_amdgcn_sched_barrier(0);  // issue the copy before the contraction
 
-    const float4 *wl = reinterpret_cast<const float4 *>(&buf[SLOT][0]);
-    const float *shl = reinterpret_cast<const float *>(&buf[SLOT][NWU]) + grp * 16;
+    const float4 *wl = reinterpret_cast<const float4 *>(cur);
+    const float *shl = reinterpret_cast<const float *>(cur + NWU) + grp * 16;
     // accumulators start at C_q: rows 4 grp .. 4 grp + 3 of each row block
-    const float4 *cl = reinterpret_cast<const float4 *>(&buf[SLOT][NWU]) + 16 + grp;
+    const float4 *cl = reinterpret_cast<const float4 *>(cur + NWU) + 16 + grp;
     v4f acc[NC][NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -173,17 +168,12 @@ __device__ __forceinline__ void fp32_point(int64_t q, bool more, const uint4 *__
         L.qbest = (uint32_t)q;
     }
 
-    if (more) {
-        uint4 *bq = &buf[SLOT ^ 1][tid];
-        bq[0] = st0;
-        if constexpr (CPT > 1) bq[THREADS] = st1;
-        if constexpr (CPT > 2) bq[2 * THREADS] = st2;
-    }
+    if (more) wait_record_loads();
     __syncthreads();
 }
 
 template <int NS, int NC>
-__device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 (*buf)[Fp32Geo<NS>::REC])
+__device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4 *buf1)
 {
     static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
     constexpr int NG = Fp32Geo<NS>::NG;
@@ -233,25 +223,16 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 (*buf)[Fp32G
     L.cp = 0.0f;
     L.have_cp = false;
 
-    {
-        const uint4 *rq = R32 + qb * REC + tid;
-        const uint4 st0 = rq[0];
-        uint4 st1 = st0, st2 = st0;
-        if constexpr (CPT > 1) st1 = rq[THREADS];
-        if constexpr (CPT > 2) st2 = rq[2 * THREADS];
-        uint4 *bq = &buf[0][tid];
-        bq[0] = st0;
-        if constexpr (CPT > 1) bq[THREADS] = st1;
-        if constexpr (CPT > 2) bq[2 * THREADS] = st2;
-    }
+    record_to_lds<CPT, THREADS>(R32 + qb * REC, buf0, tid);
+    wait_record_loads();
     __syncthreads();
-    // grid points in pairs so that each one's LDS slot is a constant
+    // grid points in pairs so that each one's LDS buffer is fixed
     int64_t q = qb;
     for (; q + 1 < qe; q += 2) {
-        fp32_point<NS, NC, 0>(q, true, R32, buf, L);
-        fp32_point<NS, NC, 1>(q + 1, q + 2 < qe, R32, buf, L);
+        fp32_point<NS, NC>(q, true, R32, buf0, buf1, L);
+        fp32_point<NS, NC>(q + 1, q + 2 < qe, R32, buf1, buf0, L);
     }
-    if (q < qe) fp32_point<NS, NC, 0>(q, false, R32, buf, L);
+    if (q < qe) fp32_point<NS, NC>(q, false, R32, buf0, buf1, L);
 
     if (owner && u_own < K) {
         if (L.have_cp) it.chi2_p[u_own] = (double)L.cp;
@@ -269,7 +250,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
     int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
 {
-    __shared__ uint4 buf[2][Fp32Geo<NS>::REC];
+    __shared__ uint4 buf0[Fp32Geo<NS>::REC], buf1[Fp32Geo<NS>::REC];
     ScanItem it;
     it.R = R32;
     it.d = d;
@@ -286,7 +267,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     it.u0 = utile * (int64_t)(16 * NC * kWavesPerBlock);
     it.qb = qchunk * q_per_chunk;
     it.qe = (it.qb + q_per_chunk < G) ? it.qb + q_per_chunk : G;
-    fp32_item<NS, NC>(it, buf);
+    fp32_item<NS, NC>(it, buf0, buf1);
 }
 
 // Serving: a persistent-style launch over a table of items (any mix of
@@ -297,7 +278,7 @@ template <int NS, int NC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_serve_fp32(
     const ScanItem *__restrict__ items, int n_items, int *__restrict__ counter)
 {
-    __shared__ uint4 buf[2][Fp32Geo<NS>::REC];
+    __shared__ uint4 buf0[Fp32Geo<NS>::REC], buf1[Fp32Geo<NS>::REC];
     __shared__ int cur;
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
@@ -305,7 +286,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int i = cur;
         __syncthreads();
         if (i >= n_items) break;
-        fp32_item<NS, NC>(items[i], buf);
+        fp32_item<NS, NC>(items[i], buf0, buf1);
         __syncthreads();
     }
 }

@@ -57,15 +57,125 @@ __device__ __forceinline__ void split8(const float (&x)[8], uint4 &hi, uint4 &lo
     }
 }
 
+// Per-universe state a wave carries through its range of grid points.
+template <int NK, int NC>
+struct SplitLane {
+    uint4 dhi[NC][NK], dlo[NC][NK];  // B operands: 2^ed (d - o) split hi + lo
+    int64_t p_own;
+    float best;
+    uint32_t qbest;
+    float cp;
+    bool have_cp;
+};
+
+// One grid point: contract the record in `cur`, fold chi2 into the running
+// minimum, and (if more) bring the next record into `nxt` (separate LDS
+// objects, see the FP32 form).
 template <int NK, int NB, int NC, bool FP16>
-__device__ __forceinline__ void split_item(const ScanItem &it,
-                                           uint4 (*buf)[split_rec_units(NK, NB)])
+__device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *__restrict__ R16,
+                                            const uint4 *cur, uint4 *nxt, SplitLane<NK, NC> &L)
+{
+    constexpr int REC = split_rec_units(NK, NB);
+    constexpr int UU = split_u_unit(NK, NB);
+    constexpr int SU = split_scale_unit(NK, NB);
+    constexpr int THREADS = 64 * kWavesPerBlock;
+    constexpr int CPT = REC / THREADS;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int grp = lane >> 4;
+
+    if (more) record_to_lds<CPT, THREADS>(R16 + (q + 1) * REC, nxt, tid);
+    __builtin_amdgcn_sched_barrier(0);  // issue the copy before the contraction
+
+    // every accumulator starts at -2^(eq+ed) u_q for its rows
+    const float4 *ul = reinterpret_cast<const float4 *>(cur + UU) + grp * 4;
+    v4f acc[NC][NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const float4 c0 = ul[b];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c][b] = v4f{c0.x, c0.y, c0.z, c0.w};
+    }
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+#pragma unroll
+        for (int b = 2 * s; b < NB; ++b) {
+            const int t = split_pair_index(NK, NB, s, b);
+            const uint4 wh = cur[t * 128 + lane];
+            const uint4 wl = cur[t * 128 + 64 + lane];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                acc[c][b] = mfma16x16x32<FP16>(wh, L.dhi[c][s], acc[c][b]);
+                acc[c][b] = mfma16x16x32<FP16>(wh, L.dlo[c][s], acc[c][b]);
+                acc[c][b] = mfma16x16x32<FP16>(wl, L.dhi[c][s], acc[c][b]);
+            }
+        }
+    }
+
+    // acc = 2^(eq+ed) z: squared and summed per universe column
+    const float unscale = __uint_as_float(cur[SU].x);
+    float part[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        float blk[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float a = acc[c][b][0] * acc[c][b][0];
+#pragma unroll
+            for (int j = 1; j < 4; ++j) a = fmaf(acc[c][b][j], acc[c][b][j], a);
+            blk[b] = a;
+        }
+        if constexpr (NB == 4)
+            part[c] = (blk[0] + blk[1]) + (blk[2] + blk[3]);
+        else if constexpr (NB == 3)
+            part[c] = (blk[0] + blk[1]) + blk[2];
+        else if constexpr (NB == 2)
+            part[c] = blk[0] + blk[1];
+        else
+            part[c] = blk[0];
+    }
+    float kk;
+    if constexpr (NC == 4) {
+        // lanes < 32 gather blocks 0 and 1, lanes >= 32 blocks 2 and 3 (the
+        // upper half of one operand swapped with the lower half of the other);
+        // then pairs of 16-lane rows leave row g with block g
+        const auto h0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[0]),
+                                                         __float_as_uint(part[2]), false, false);
+        const auto h1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[1]),
+                                                         __float_as_uint(part[3]), false, false);
+        const float k0 = __uint_as_float(h0[0]) + __uint_as_float(h0[1]);
+        const float k1 = __uint_as_float(h1[0]) + __uint_as_float(h1[1]);
+        const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(k0),
+                                                          __float_as_uint(k1), false, false);
+        kk = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+    } else {
+        const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[0]),
+                                                        __float_as_uint(part[1]), false, false);
+        kk = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+        const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(kk),
+                                                          __float_as_uint(kk), false, false);
+        kk = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+    }
+    const float chi2 = kk * unscale;
+
+    if (q == L.p_own) {
+        L.cp = chi2;
+        L.have_cp = true;
+    }
+    if (chi2 < L.best) {
+        L.best = chi2;
+        L.qbest = (uint32_t)q;
+    }
+    if (more) wait_record_loads();
+    __syncthreads();
+}
+
+template <int NK, int NB, int NC, bool FP16>
+__device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint4 *buf1)
 {
     static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
     constexpr int UW = 16 * NC;
     constexpr int REC = split_rec_units(NK, NB);
-    constexpr int UU = split_u_unit(NK, NB);
-    constexpr int SU = split_scale_unit(NK, NB);
     constexpr int THREADS = 64 * kWavesPerBlock;
     static_assert(REC % THREADS == 0, "records are whole 4 KB pieces");
     constexpr int CPT = REC / THREADS;
@@ -85,9 +195,9 @@ __device__ __forceinline__ void split_item(const ScanItem &it,
     if (qb >= qe) return;  // uniform per block
     const int grp = lane >> 4, col = lane & 15;
 
+    SplitLane<NK, NC> L;
     // the universes, split once: B operand of k-step s for column block c holds
     // bins 32s + 8*grp + e of universe u0 + 16c + col, as 2^ed (d - o)
-    uint4 dhi[NC][NK], dlo[NC][NK];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const int64_t u = u0 + 16 * c + col;
@@ -99,137 +209,34 @@ __device__ __forceinline__ void split_item(const ScanItem &it,
                 const int k = 32 * s + 8 * grp + e;
                 x[e] = (u < K && k < N) ? (float)ldexp(d[u * N + k] - off[k], ed) : 0.0f;
             }
-            split8<FP16>(x, dhi[c][s], dlo[c][s]);
+            split8<FP16>(x, L.dhi[c][s], L.dlo[c][s]);
         }
     }
+    // after the reduction, lane l holds column block cl of universe column col
     const int cl = (NC == 4) ? grp : (grp >> 1);
     const bool owner = (NC == 4) ? true : ((grp & 1) == 0);
     const int64_t u_own = u0 + 16 * cl + col;
-    const int64_t p_own = (u_own < K) ? (it.p_idx ? it.p_idx[u_own] : it.p) : -1;
-    float best = __builtin_inff();
-    uint32_t qbest = 0xffffffffu;
-    float cp = 0.0f;
-    bool have_cp = false;
+    L.p_own = (u_own < K) ? (it.p_idx ? it.p_idx[u_own] : it.p) : -1;
+    L.best = __builtin_inff();
+    L.qbest = 0xffffffffu;
+    L.cp = 0.0f;
+    L.have_cp = false;
 
-    uint4 st0 = make_uint4(0u, 0u, 0u, 0u), st1 = st0, st2 = st0, st3 = st0;
-    {
-        const uint4 *rq = R16 + qb * REC + tid;
-        st0 = rq[0];
-        if constexpr (CPT > 1) st1 = rq[THREADS];
-        if constexpr (CPT > 2) st2 = rq[2 * THREADS];
-        if constexpr (CPT > 3) st3 = rq[3 * THREADS];
-        uint4 *bq = &buf[0][tid];
-        bq[0] = st0;
-        if constexpr (CPT > 1) bq[THREADS] = st1;
-        if constexpr (CPT > 2) bq[2 * THREADS] = st2;
-        if constexpr (CPT > 3) bq[3 * THREADS] = st3;
-    }
+    record_to_lds<CPT, THREADS>(R16 + qb * REC, buf0, tid);
+    wait_record_loads();
     __syncthreads();
-    int slot = 0;
-    for (int64_t q = qb; q < qe; ++q) {
-        const bool more = q + 1 < qe;
-        if (more) {
-            const uint4 *rq = R16 + (q + 1) * REC + tid;
-            st0 = rq[0];
-            if constexpr (CPT > 1) st1 = rq[THREADS];
-            if constexpr (CPT > 2) st2 = rq[2 * THREADS];
-            if constexpr (CPT > 3) st3 = rq[3 * THREADS];
-        }
-        const uint4 *rb = &buf[slot][0];
-
-        // every accumulator starts at -2^(eq+ed) u_q for its rows
-        const float4 *ul = reinterpret_cast<const float4 *>(rb + UU) + grp * 4;
-        v4f acc[NC][NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const float4 c0 = ul[b];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c][b] = v4f{c0.x, c0.y, c0.z, c0.w};
-        }
-#pragma unroll
-        for (int s = 0; s < NK; ++s) {
-#pragma unroll
-            for (int b = 2 * s; b < NB; ++b) {
-                const int t = split_pair_index(NK, NB, s, b);
-                const uint4 wh = rb[t * 128 + lane];
-                const uint4 wl = rb[t * 128 + 64 + lane];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    acc[c][b] = mfma16x16x32<FP16>(wh, dhi[c][s], acc[c][b]);
-                    acc[c][b] = mfma16x16x32<FP16>(wh, dlo[c][s], acc[c][b]);
-                    acc[c][b] = mfma16x16x32<FP16>(wl, dhi[c][s], acc[c][b]);
-                }
-            }
-        }
-
-        // acc = 2^(eq+ed) z: squared and summed per universe column
-        const float unscale = __uint_as_float(rb[SU].x);
-        float part[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            float blk[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                float a = acc[c][b][0] * acc[c][b][0];
-#pragma unroll
-                for (int j = 1; j < 4; ++j) a = fmaf(acc[c][b][j], acc[c][b][j], a);
-                blk[b] = a;
-            }
-            if constexpr (NB == 4)
-                part[c] = (blk[0] + blk[1]) + (blk[2] + blk[3]);
-            else if constexpr (NB == 3)
-                part[c] = (blk[0] + blk[1]) + blk[2];
-            else if constexpr (NB == 2)
-                part[c] = blk[0] + blk[1];
-            else
-                part[c] = blk[0];
-        }
-        const bool hi = lane >= 32;
-        float kk;
-        if constexpr (NC == 4) {
-            float k0 = hi ? part[2] : part[0];
-            float k1 = hi ? part[3] : part[1];
-            const float s0 = hi ? part[0] : part[2];
-            const float s1 = hi ? part[1] : part[3];
-            k0 += __shfl_xor(s0, 32);
-            k1 += __shfl_xor(s1, 32);
-            const bool odd = grp & 1;
-            kk = odd ? k1 : k0;
-            const float ss = odd ? k0 : k1;
-            kk += __shfl_xor(ss, 16);
-        } else {
-            kk = hi ? part[1] : part[0];
-            const float s0 = hi ? part[0] : part[1];
-            kk += __shfl_xor(s0, 32);
-            kk += __shfl_xor(kk, 16);
-        }
-        const float chi2 = kk * unscale;
-
-        if (q == p_own) {
-            cp = chi2;
-            have_cp = true;
-        }
-        if (chi2 < best) {
-            best = chi2;
-            qbest = (uint32_t)q;
-        }
-
-        if (more) {
-            uint4 *bq = &buf[slot ^ 1][tid];
-            bq[0] = st0;
-            if constexpr (CPT > 1) bq[THREADS] = st1;
-            if constexpr (CPT > 2) bq[2 * THREADS] = st2;
-            if constexpr (CPT > 3) bq[3 * THREADS] = st3;
-        }
-        __syncthreads();
-        slot ^= 1;
+    int64_t q = qb;
+    for (; q + 1 < qe; q += 2) {
+        split_point<NK, NB, NC, FP16>(q, true, R16, buf0, buf1, L);
+        split_point<NK, NB, NC, FP16>(q + 1, q + 2 < qe, R16, buf1, buf0, L);
     }
+    if (q < qe) split_point<NK, NB, NC, FP16>(q, false, R16, buf0, buf1, L);
 
     if (owner && u_own < K) {
-        if (have_cp) it.chi2_p[u_own] = (double)cp;
-        if (best < __builtin_inff()) {
+        if (L.have_cp) it.chi2_p[u_own] = (double)L.cp;
+        if (L.best < __builtin_inff()) {
             const unsigned long long key =
-                ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)qbest;
+                ((unsigned long long)__float_as_uint(L.best) << 32) | (unsigned long long)L.qbest;
             atomicMin(&it.keys[u_own], key);
         }
     }
@@ -241,7 +248,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     int ed, const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
     int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
 {
-    __shared__ uint4 buf[2][split_rec_units(NK, NB)];
+    __shared__ uint4 buf0[split_rec_units(NK, NB)], buf1[split_rec_units(NK, NB)];
     ScanItem it;
     it.R = R16;
     it.d = d;
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     it.u0 = utile * (int64_t)(16 * NC * kWavesPerBlock);
     it.qb = qchunk * q_per_chunk;
     it.qe = (it.qb + q_per_chunk < G) ? it.qb + q_per_chunk : G;
-    split_item<NK, NB, NC, FP16>(it, buf);
+    split_item<NK, NB, NC, FP16>(it, buf0, buf1);
 }
 
 // Serving: persistent-style launch over a finite table of items (see the
@@ -267,7 +274,7 @@ template <int NK, int NB, int NC, bool FP16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_serve_split(
     const ScanItem *__restrict__ items, int n_items, int *__restrict__ counter)
 {
-    __shared__ uint4 buf[2][split_rec_units(NK, NB)];
+    __shared__ uint4 buf0[split_rec_units(NK, NB)], buf1[split_rec_units(NK, NB)];
     __shared__ int cur;
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int i = cur;
         __syncthreads();
         if (i >= n_items) break;
-        split_item<NK, NB, NC, FP16>(items[i], buf);
+        split_item<NK, NB, NC, FP16>(items[i], buf0, buf1);
         __syncthreads();
     }
 }
