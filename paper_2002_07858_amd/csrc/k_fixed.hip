@@ -22,7 +22,8 @@
 // GEMM kernel: a 256-thread block owns 64 universes of one group (4 column
 // blocks of 16) and a chunk of grid points; each wave contracts 16 grid
 // points per step against the block's universes, whose y fragments stay in
-// registers; the t tile (64 points x 4*NS bins) is double-buffered in LDS.
+// registers; the t tile (64 points x 4*NS bins) is double-buffered in LDS and
+// brought in by direct global -> LDS loads while the previous tile is used.
 // Per-chunk minima (value, q) are merged by a small kernel with Algorithm 1's
 // rule (smallest value, then lowest q).
 #include "fc_internal.h"
@@ -73,7 +74,8 @@ __global__ __launch_bounds__(256) void k_fixed_t(const double *__restrict__ W64,
                                                  const double *__restrict__ off,
                                                  const int64_t *__restrict__ m_of_slot, int N,
                                                  int np, int64_t G, int64_t n_slots,
-                                                 double *__restrict__ T, double *__restrict__ b)
+                                                 int64_t b_stride, double *__restrict__ T,
+                                                 double *__restrict__ b)
 {
     const int lane = threadIdx.x & 63;
     const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(256) void k_fixed_t(const double *__restrict__ W64,
     if (lane < np) T[e * np + lane] = t;
     double s = t * t;
     for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w);
-    if (lane == 0) b[e] = s;
+    if (lane == 0) b[ms * b_stride + q] = s;
 }
 
 struct FxTileDesc {
@@ -107,14 +109,15 @@ template <int NS>
 __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_fixed_min(
     const FxTileDesc *__restrict__ tiles, int64_t n_tiles, const double *__restrict__ Y,
     const double *__restrict__ a, const int64_t *__restrict__ p_of_row,
-    const double *__restrict__ T, const double *__restrict__ b, int64_t G, int64_t q_per_chunk,
-    int n_chunks, double *__restrict__ cand_v, int64_t *__restrict__ cand_q,
+    const double *__restrict__ T, const double *__restrict__ b, int64_t b_stride, int64_t G,
+    int64_t q_per_chunk, int n_chunks, double *__restrict__ cand_v, int64_t *__restrict__ cand_q,
     double *__restrict__ cp)
 {
-    constexpr int NP = 4 * NS;        // padded bins
-    constexpr int LD = NP + 1;        // LDS row stride (doubles), odd: no bank conflicts
-    __shared__ double tl[2][kFxTile * LD];
-    __shared__ double bl[2][kFxTile];
+    constexpr int NP = 4 * NS;             // padded bins
+    constexpr int TU = kFxTile * NP / 2;   // 16-byte units of a t tile (rows contiguous)
+    constexpr int TC = (TU + kFxThreads - 1) / kFxThreads;
+    __shared__ uint4 t0[TC * kFxThreads], t1[TC * kFxThreads];
+    __shared__ uint4 b0[kFxTile / 2], b1[kFxTile / 2];
     __shared__ double red_v[4][kFxTile];
     __shared__ int64_t red_q[4][kFxTile];
 
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
     const int64_t qb = (int64_t)chunk * q_per_chunk;
     const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
     const double *Tm = T + (int64_t)td.slot * G * NP;
-    const double *bm = b + (int64_t)td.slot * G;
+    const double *bm = b + (int64_t)td.slot * b_stride;  // 16-byte aligned rows
 
     // B operand: y of universe column 16c + col, bins 4s + grp (rows past the
     // tile read as zero and are never reported)
@@ -151,25 +154,44 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
         bq[c] = INT64_MAX;
     }
 
-    // stage the t tile of grid points q0 .. q0+63 (zero rows past qe)
-    auto stage = [&](int buf, int64_t q0) {
-        for (int e = tid; e < kFxTile * NP; e += kFxThreads) {
-            const int rr = e / NP, cc = e % NP;
-            const int64_t q = q0 + rr;
-            tl[buf][rr * LD + cc] = (q < qe) ? Tm[q * NP + cc] : 0.0;
+    // the t tile of grid points q0 .. q0+63 (and their b) into LDS with
+    // direct global -> LDS loads; rows at or past qe are not loaded (their
+    // LDS rows hold stale values, and their results are never used)
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+    auto stage = [&](uint4 *tdst, uint4 *bdst, int64_t q0) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(Tm + q0 * NP);
+#pragma unroll
+        for (int c = 0; c < TC; ++c) {
+            const int unit = c * kFxThreads + tid;
+            if (unit < TU && q0 + unit / (NP / 2) < qe)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(src + unit),
+                    (__attribute__((address_space(3))) void *)(tdst + c * kFxThreads + wbase), 16,
+                    0, 0);
         }
-        if (tid < kFxTile) {
-            const int64_t q = q0 + tid;
-            bl[buf][tid] = (q < qe) ? bm[q] : 0.0;
-        }
+        // b in pairs of rows (rows are padded so a pair may pass qe)
+        if (tid < kFxTile / 2 && q0 + 2 * tid < qe)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(reinterpret_cast<const uint4 *>(bm + q0) + tid),
+                (__attribute__((address_space(3))) void *)(bdst), 16, 0, 0);
     };
-    if (qb < qe) stage(0, qb);
+    if (qb < qe) stage(t0, b0, qb);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
     int buf = 0;
     for (int64_t q0 = qb; q0 < qe; q0 += kFxTile) {
-        if (q0 + kFxTile < qe) stage(buf ^ 1, q0 + kFxTile);
+        const bool more = q0 + kFxTile < qe;
+        if (more) {
+            if (buf)
+                stage(t0, b0, q0 + kFxTile);
+            else
+                stage(t1, b1, q0 + kFxTile);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // issue the copy before the contraction
+        const double *tl = reinterpret_cast<const double *>(buf ? t1 : t0);
+        const double *bl = reinterpret_cast<const double *>(buf ? b1 : b0);
         // A operand: t of grid point 16 wave + col ... rows of this wave
-        const double *trow = &tl[buf][(16 * wave + col) * LD];
+        const double *trow = tl + (16 * wave + col) * NP;
         v4d acc[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -187,7 +209,7 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
             const int qr = 16 * wave + grp + 4 * j;
             const int64_t q = q0 + qr;
             if (q < qe) {
-                const double bqv = bl[buf][qr];
+                const double bqv = bl[qr];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const double v = (av[c] + bqv) - 2.0 * acc[c][j];
@@ -199,6 +221,7 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
                 }
             }
         }
+        if (more) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
         buf ^= 1;
     }
@@ -291,25 +314,27 @@ struct Buf {
 template <int NS>
 hipError_t launch_fixed_min_ns(const FxTileDesc *tiles, int64_t n_tiles, const double *Y,
                                const double *a, const int64_t *p_of_row, const double *T,
-                               const double *b, int64_t G, int64_t q_per_chunk, int n_chunks,
-                               double *cand_v, int64_t *cand_q, double *cp, hipStream_t st)
+                               const double *b, int64_t b_stride, int64_t G, int64_t q_per_chunk,
+                               int n_chunks, double *cand_v, int64_t *cand_q, double *cp,
+                               hipStream_t st)
 {
     hipLaunchKernelGGL((k_fixed_min<NS>), dim3((unsigned)(n_tiles * n_chunks)), dim3(kFxThreads),
-                       0, st, tiles, n_tiles, Y, a, p_of_row, T, b, G, q_per_chunk, n_chunks,
-                       cand_v, cand_q, cp);
+                       0, st, tiles, n_tiles, Y, a, p_of_row, T, b, b_stride, G, q_per_chunk,
+                       n_chunks, cand_v, cand_q, cp);
     return hipGetLastError();
 }
 
 hipError_t launch_fixed_min(int ns, const FxTileDesc *tiles, int64_t n_tiles, const double *Y,
                             const double *a, const int64_t *p_of_row, const double *T,
-                            const double *b, int64_t G, int64_t q_per_chunk, int n_chunks,
-                            double *cand_v, int64_t *cand_q, double *cp, hipStream_t st)
+                            const double *b, int64_t b_stride, int64_t G, int64_t q_per_chunk,
+                            int n_chunks, double *cand_v, int64_t *cand_q, double *cp,
+                            hipStream_t st)
 {
     switch (ns) {
 #define FC_CASE(n)                                                                                \
     case n:                                                                                       \
-        return launch_fixed_min_ns<n>(tiles, n_tiles, Y, a, p_of_row, T, b, G, q_per_chunk,       \
-                                      n_chunks, cand_v, cand_q, cp, st);
+        return launch_fixed_min_ns<n>(tiles, n_tiles, Y, a, p_of_row, T, b, b_stride, G,          \
+                                      q_per_chunk, n_chunks, cand_v, cand_q, cp, st);
         FC_CASE(1) FC_CASE(2) FC_CASE(3) FC_CASE(4) FC_CASE(5) FC_CASE(6) FC_CASE(7) FC_CASE(8)
         FC_CASE(9) FC_CASE(10) FC_CASE(11) FC_CASE(12) FC_CASE(13) FC_CASE(14) FC_CASE(15)
         FC_CASE(16)
@@ -331,7 +356,8 @@ static hipError_t fixed_round(const fc_grid *g, int64_t R, const std::vector<int
     const int N = g->N, ns = (N + 3) / 4, np = 4 * ns;
     const int64_t G = g->G;
     // groups: runs of equal m; matrix slots batched so that t fits a budget
-    const size_t t_bytes_per_slot = sizeof(double) * (size_t)G * (np + 1);
+    const int64_t b_stride = G + (G & 1) + 2;  // even (16-byte rows) plus a pair of slack
+    const size_t t_bytes_per_slot = sizeof(double) * ((size_t)G * np + b_stride);
     const size_t budget = size_t(4) << 30;
     const int64_t slots_max = std::max<int64_t>(1, (int64_t)(budget / t_bytes_per_slot));
     Buf &dOrder = bufs[0], &dM = bufs[1], &dP = bufs[2], &dY = bufs[3], &dA = bufs[4],
@@ -378,7 +404,7 @@ static hipError_t fixed_round(const fc_grid *g, int64_t R, const std::vector<int
             (e = dY.need(sizeof(double) * nr * np)) != hipSuccess ||
             (e = dA.need(sizeof(double) * nr)) != hipSuccess ||
             (e = dT.need(sizeof(double) * (size_t)n_slots * G * np)) != hipSuccess ||
-            (e = dB.need(sizeof(double) * (size_t)n_slots * G)) != hipSuccess ||
+            (e = dB.need(sizeof(double) * (size_t)n_slots * b_stride)) != hipSuccess ||
             (e = dSlotM.need(sizeof(int64_t) * n_slots)) != hipSuccess ||
             (e = dTiles.need(sizeof(FxTileDesc) * n_tiles)) != hipSuccess ||
             (e = dCv.need(sizeof(double) * nr * n_chunks)) != hipSuccess ||
@@ -403,11 +429,11 @@ static hipError_t fixed_round(const fc_grid *g, int64_t R, const std::vector<int
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_fixed_t, dim3((unsigned)((n_slots * G + 3) / 4)), dim3(256), 0, st,
                            g->W64, g->S64, g->off, dSlotM.as<int64_t>(), N, np, G, n_slots,
-                           dT.as<double>(), dB.as<double>());
+                           b_stride, dT.as<double>(), dB.as<double>());
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = launch_fixed_min(ns, dTiles.as<FxTileDesc>(), n_tiles, dY.as<double>(),
                                   dA.as<double>(), dP.as<int64_t>(), dT.as<double>(),
-                                  dB.as<double>(), G, qpc, n_chunks, dCv.as<double>(),
+                                  dB.as<double>(), b_stride, G, qpc, n_chunks, dCv.as<double>(),
                                   dCq.as<int64_t>(), dCp.as<double>(), st)) != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_fixed_finish, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st,
