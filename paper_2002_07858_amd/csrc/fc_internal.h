@@ -70,7 +70,7 @@ __host__ __device__ constexpr int n_pairs_from_ns(int ns)
 }
 __host__ __device__ constexpr int n_groups_from_ns(int ns) { return ceil_div(n_pairs_from_ns(ns), 4); }
 __host__ __device__ constexpr int rec_w_units(int ns) { return n_groups_from_ns(ns) * 64; }
-__host__ __device__ constexpr int rec_units(int ns) { return 256 * ceil_div(rec_w_units(ns) + 32, 256); }
+__host__ __device__ constexpr int rec_units(int ns) { return rec_w_units(ns) + 32; }
 // Index of pair (s, b) in the fragment order (s outer, b inner).
 __host__ __device__ constexpr int pair_index(int ns, int s, int b)
 {
@@ -96,7 +96,6 @@ __host__ __device__ constexpr int pair_index(int ns, int s, int b)
 //     [pair][hi | lo][lane]           npair * 128 units
 //     c[g][b][j] FP32, -2^(eq+ed) * u_q[16b + 4g + j]           16 units
 //     {2^-2(eq+ed), 0, 0, 0}                                       1 unit
-//     zero padding to a whole number of 256 units
 // c is the initial accumulator of every row block, so that the MFMA chain
 // ends at 2^(eq+ed) z and chi^2 = 2^-2(eq+ed) sum z'^2.  eq is chosen per grid
 // point so that max |W_q| 2^eq lies in [2^13, 2^14); ed per grid so that
@@ -122,25 +121,28 @@ __host__ __device__ constexpr int split_u_unit(int nk, int nb) { return split_np
 __host__ __device__ constexpr int split_scale_unit(int nk, int nb) { return split_u_unit(nk, nb) + 16; }
 __host__ __device__ constexpr int split_rec_units(int nk, int nb)
 {
-    return 256 * ceil_div(split_scale_unit(nk, nb) + 1, 256);
+    return split_scale_unit(nk, nb) + 1;
 }
 
-// Copy one record into LDS with direct global -> LDS loads: thread tid moves
-// 16-byte units tid, tid + 256, ...; each wave's 64 lanes land contiguously
-// at its own base, so the LDS image equals the global record.  The loads are
+// Copy one record of REC 16-byte units into LDS with direct global -> LDS
+// loads: thread tid moves units tid, tid + 256, ...; each wave's 64 lanes land
+// contiguously at its own base, so the LDS image equals the global record.  The loads are
 // waited for (vmcnt) before the barrier that hands the buffer over.
 #ifdef __HIPCC__
-template <int CPT, int THREADS>
+template <int REC, int THREADS>
 __device__ __forceinline__ void record_to_lds(const uint4 *__restrict__ rec, uint4 *dst, int tid)
 {
-    // wave-uniform LDS base (M0) and a 32-bit lane offset on a uniform record base
+    // wave-uniform LDS base (M0) and a 32-bit lane offset on a uniform record base;
+    // lanes past the record's last unit load nothing
+    constexpr int CPT = (REC + THREADS - 1) / THREADS;
     const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
     const unsigned lane_off = (unsigned)tid * 16u;
 #pragma unroll
     for (int c = 0; c < CPT; ++c)
-        __builtin_amdgcn_global_load_lds(
-            (const void *)(reinterpret_cast<const char *>(rec + c * THREADS) + lane_off),
-            (__attribute__((address_space(3))) void *)(dst + c * THREADS + wbase), 16, 0, 0);
+        if ((REC % THREADS) == 0 || c + 1 < CPT || c * THREADS + tid < REC)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(reinterpret_cast<const char *>(rec + c * THREADS) + lane_off),
+                (__attribute__((address_space(3))) void *)(dst + c * THREADS + wbase), 16, 0, 0);
 }
 
 __device__ __forceinline__ void wait_record_loads()

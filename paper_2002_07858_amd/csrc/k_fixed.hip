@@ -67,33 +67,55 @@ __global__ __launch_bounds__(256) void k_fixed_y(const double *__restrict__ W64,
     if (lane == 0) a[r] = s;
 }
 
-// t_q = W_m (S_q - o), b_q = ||t_q||^2 for grid points q of matrix slot ms:
-// one wave per (slot, q).
+// t_q = W_m (S_q - o), b_q = ||t_q||^2 for 64 grid points q of matrix slot ms
+// per block: W_m (transposed, zero above the diagonal) and the 64 signal
+// rows sit in LDS; each thread forms 4*NS*64/256 components with a uniform
+// loop over the N bins, then 64 threads sum the squares of their row (read
+// back from global memory, visible to the block after the barrier).
+template <int NS>
 __global__ __launch_bounds__(256) void k_fixed_t(const double *__restrict__ W64,
                                                  const double *__restrict__ S64,
                                                  const double *__restrict__ off,
                                                  const int64_t *__restrict__ m_of_slot, int N,
-                                                 int np, int64_t G, int64_t n_slots,
-                                                 int64_t b_stride, double *__restrict__ T,
-                                                 double *__restrict__ b)
+                                                 int64_t G, int64_t n_qtiles, int64_t b_stride,
+                                                 double *__restrict__ T, double *__restrict__ b)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (e >= n_slots * G) return;
-    const int64_t ms = e / G, q = e % G;
+    constexpr int NP = 4 * NS;
+    __shared__ double wt[NP * NP];        // wt[j][i] = W_m[i][j] (0 for j > i or past N)
+    __shared__ double xs[64 * NP];        // xs[r][j] = S_q[j] - o[j]
+    const int tid = threadIdx.x;
+    const int64_t ms = blockIdx.x / n_qtiles;
+    const int64_t q0 = (blockIdx.x % n_qtiles) * 64;
     const double *Wm = W64 + m_of_slot[ms] * ((int64_t)N * (N + 1) / 2);
-    const double x = (lane < N) ? S64[q * N + lane] - off[lane] : 0.0;
-    double t = 0.0;
-    const int row = lane < N ? lane : 0;
-    for (int j = 0; j < N; ++j) {
-        const double xj = __shfl(x, j);
-        if (j <= row) t = fma(Wm[(int64_t)row * (row + 1) / 2 + j], xj, t);
+    for (int e = tid; e < NP * NP; e += 256) {
+        const int j = e / NP, i = e % NP;
+        wt[e] = (i < N && j <= i) ? Wm[(int64_t)i * (i + 1) / 2 + j] : 0.0;
     }
-    if (lane >= N) t = 0.0;
-    if (lane < np) T[e * np + lane] = t;
-    double s = t * t;
-    for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w);
-    if (lane == 0) b[ms * b_stride + q] = s;
+    for (int e = tid; e < 64 * NP; e += 256) {
+        const int r = e / NP, j = e % NP;
+        const int64_t q = q0 + r;
+        xs[e] = (q < G && j < N) ? S64[q * N + j] - off[j] : 0.0;
+    }
+    __syncthreads();
+    double *Tm = T + ms * G * NP;
+#pragma unroll 1
+    for (int e = tid; e < 64 * NP; e += 256) {
+        const int r = e / NP, i = e % NP;
+        double t = 0.0;
+        for (int j = 0; j < N; ++j) t = fma(wt[j * NP + i], xs[r * NP + j], t);
+        const int64_t q = q0 + r;
+        if (q < G) Tm[q * NP + i] = t;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int64_t q = q0 + tid;
+        double sq = 0.0;
+        if (q < G) {
+            const double *tr = Tm + q * NP;
+            for (int i = 0; i < NP; ++i) sq = fma(tr[i], tr[i], sq);
+            b[ms * b_stride + q] = sq;
+        }
+    }
 }
 
 struct FxTileDesc {
@@ -343,6 +365,30 @@ hipError_t launch_fixed_min(int ns, const FxTileDesc *tiles, int64_t n_tiles, co
     }
 }
 
+template <int NS>
+hipError_t launch_fixed_t_ns(const fc_grid *g, const int64_t *m_of_slot, int64_t n_slots,
+                             int64_t b_stride, double *T, double *b, hipStream_t st)
+{
+    const int64_t n_qtiles = (g->G + 63) / 64;
+    hipLaunchKernelGGL((k_fixed_t<NS>), dim3((unsigned)(n_slots * n_qtiles)), dim3(256), 0, st,
+                       g->W64, g->S64, g->off, m_of_slot, g->N, g->G, n_qtiles, b_stride, T, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fixed_t(int ns, const fc_grid *g, const int64_t *m_of_slot, int64_t n_slots,
+                          int64_t b_stride, double *T, double *b, hipStream_t st)
+{
+    switch (ns) {
+#define FC_CASE(n) \
+    case n: return launch_fixed_t_ns<n>(g, m_of_slot, n_slots, b_stride, T, b, st);
+        FC_CASE(1) FC_CASE(2) FC_CASE(3) FC_CASE(4) FC_CASE(5) FC_CASE(6) FC_CASE(7) FC_CASE(8)
+        FC_CASE(9) FC_CASE(10) FC_CASE(11) FC_CASE(12) FC_CASE(13) FC_CASE(14) FC_CASE(15)
+        FC_CASE(16)
+#undef FC_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 // One round over the rows listed in order[0..R) (universe k = order[r], all
@@ -427,10 +473,9 @@ static hipError_t fixed_round(const fc_grid *g, int64_t R, const std::vector<int
                            g->off, dOrder.as<int64_t>(), dM.as<int64_t>(), N, np, nr,
                            dY.as<double>(), dA.as<double>());
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_fixed_t, dim3((unsigned)((n_slots * G + 3) / 4)), dim3(256), 0, st,
-                           g->W64, g->S64, g->off, dSlotM.as<int64_t>(), N, np, G, n_slots,
-                           b_stride, dT.as<double>(), dB.as<double>());
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_fixed_t(ns, g, dSlotM.as<int64_t>(), n_slots, b_stride, dT.as<double>(),
+                                dB.as<double>(), st)) != hipSuccess)
+            return e;
         if ((e = launch_fixed_min(ns, dTiles.as<FxTileDesc>(), n_tiles, dY.as<double>(),
                                   dA.as<double>(), dP.as<int64_t>(), dT.as<double>(),
                                   dB.as<double>(), b_stride, G, qpc, n_chunks, dCv.as<double>(),

@@ -41,7 +41,7 @@ struct Fp32Geo {
     static constexpr int NB = n_rowblocks_from_ns(NS);
     static constexpr int NG = n_groups_from_ns(NS);
     static constexpr int NWU = rec_w_units(NS);  // 16-byte units of W per record
-    static constexpr int REC = rec_units(NS);    // W + 512 B of S + padding
+    static constexpr int REC = rec_units(NS);    // W + 512 B of S and C
 };
 
 // Per-universe state a wave carries through its range of grid points.
@@ -67,12 +67,11 @@ __device__ __forceinline__ void fp32_point(int64_t q, bool more, const uint4 *__
     constexpr int NWU = rec_w_units(NS);
     constexpr int REC = rec_units(NS);
     constexpr int THREADS = 64 * kWavesPerBlock;
-    constexpr int CPT = REC / THREADS;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int grp = lane >> 4;
 
-    if (more) record_to_lds<CPT, THREADS>(R32 + (q + 1) * REC, nxt, tid);
+    if (more) record_to_lds<REC, THREADS>(R32 + (q + 1) * REC, nxt, tid);
     __builtin_amdgcn_sched_barrier(0);  // issue the copy before the contraction
 
     const float4 *wl = reinterpret_cast<const float4 *>(cur);
@@ -179,11 +178,9 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4
     constexpr int NG = Fp32Geo<NS>::NG;
     constexpr int UW = 16 * NC;            // universes per wave
     constexpr int NWU = rec_w_units(NS);   // 16-byte units of W per record
-    constexpr int REC = rec_units(NS);     // W + 512 B of S + padding
+    constexpr int REC = rec_units(NS);     // W + 512 B of S and C
     constexpr int THREADS = 64 * kWavesPerBlock;
-    static_assert(REC % THREADS == 0, "records are whole 4 KB pieces");
-    constexpr int CPT = REC / THREADS;     // units copied per thread
-    static_assert(CPT >= 1 && CPT <= 3, "records of at most three 4 KB pieces");
+    static_assert(REC <= 3 * THREADS, "records of at most three 4 KB pieces");
     static_assert(NG * 64 == NWU, "W groups");
 
     const uint4 *__restrict__ R32 = it.R;
@@ -223,7 +220,7 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4
     L.cp = 0.0f;
     L.have_cp = false;
 
-    record_to_lds<CPT, THREADS>(R32 + qb * REC, buf0, tid);
+    record_to_lds<REC, THREADS>(R32 + qb * REC, buf0, tid);
     wait_record_loads();
     __syncthreads();
     // grid points in pairs so that each one's LDS buffer is fixed

@@ -79,12 +79,11 @@ __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *_
     constexpr int UU = split_u_unit(NK, NB);
     constexpr int SU = split_scale_unit(NK, NB);
     constexpr int THREADS = 64 * kWavesPerBlock;
-    constexpr int CPT = REC / THREADS;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int grp = lane >> 4;
 
-    if (more) record_to_lds<CPT, THREADS>(R16 + (q + 1) * REC, nxt, tid);
+    if (more) record_to_lds<REC, THREADS>(R16 + (q + 1) * REC, nxt, tid);
     __builtin_amdgcn_sched_barrier(0);  // issue the copy before the contraction
 
     // every accumulator starts at -2^(eq+ed) u_q for its rows
@@ -177,9 +176,7 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
     constexpr int UW = 16 * NC;
     constexpr int REC = split_rec_units(NK, NB);
     constexpr int THREADS = 64 * kWavesPerBlock;
-    static_assert(REC % THREADS == 0, "records are whole 4 KB pieces");
-    constexpr int CPT = REC / THREADS;
-    static_assert(CPT >= 1 && CPT <= 4, "records of at most four 4 KB pieces");
+    static_assert(REC <= 4 * THREADS, "records of at most four 4 KB pieces");
 
     const uint4 *__restrict__ R16 = it.R;
     const double *__restrict__ d = it.d;
@@ -222,7 +219,7 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
     L.cp = 0.0f;
     L.have_cp = false;
 
-    record_to_lds<CPT, THREADS>(R16 + qb * REC, buf0, tid);
+    record_to_lds<REC, THREADS>(R16 + qb * REC, buf0, tid);
     wait_record_loads();
     __syncthreads();
     int64_t q = qb;
