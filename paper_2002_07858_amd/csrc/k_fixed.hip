@@ -68,10 +68,10 @@ __global__ __launch_bounds__(256) void k_fixed_y(const double *__restrict__ W64,
 }
 
 // t_q = W_m (S_q - o), b_q = ||t_q||^2 for 64 grid points q of matrix slot ms
-// per block: W_m (transposed, zero above the diagonal) and the 64 signal
-// rows sit in LDS; each thread forms 4*NS*64/256 components with a uniform
-// loop over the N bins, then 64 threads sum the squares of their row (read
-// back from global memory, visible to the block after the barrier).
+// per block, on the FP64 matrix cores: wave w forms rows q0 + 16w .. +15 of
+// T = X W^T (X = signal rows minus the offset), four 16-column blocks of
+// components, k-steps of four bins; W^T comes from LDS (zero above the
+// diagonal and past N), X straight from the signal table.
 template <int NS>
 __global__ __launch_bounds__(256) void k_fixed_t(const double *__restrict__ W64,
                                                  const double *__restrict__ S64,
@@ -81,40 +81,48 @@ __global__ __launch_bounds__(256) void k_fixed_t(const double *__restrict__ W64,
                                                  double *__restrict__ T, double *__restrict__ b)
 {
     constexpr int NP = 4 * NS;
-    __shared__ double wt[NP * NP];        // wt[j][i] = W_m[i][j] (0 for j > i or past N)
-    __shared__ double xs[64 * NP];        // xs[r][j] = S_q[j] - o[j]
-    const int tid = threadIdx.x;
+    constexpr int NC = (NP + 15) / 16;     // 16-column blocks of components
+    __shared__ double wt[NP * 16 * NC];    // wt[j][i] = W_m[i][j]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = lane >> 4, col = lane & 15;
     const int64_t ms = blockIdx.x / n_qtiles;
     const int64_t q0 = (blockIdx.x % n_qtiles) * 64;
     const double *Wm = W64 + m_of_slot[ms] * ((int64_t)N * (N + 1) / 2);
-    for (int e = tid; e < NP * NP; e += 256) {
-        const int j = e / NP, i = e % NP;
+    for (int e = tid; e < NP * 16 * NC; e += 256) {
+        const int j = e / (16 * NC), i = e % (16 * NC);
         wt[e] = (i < N && j <= i) ? Wm[(int64_t)i * (i + 1) / 2 + j] : 0.0;
     }
-    for (int e = tid; e < 64 * NP; e += 256) {
-        const int r = e / NP, j = e % NP;
-        const int64_t q = q0 + r;
-        xs[e] = (q < G && j < N) ? S64[q * N + j] - off[j] : 0.0;
-    }
     __syncthreads();
+    // A operand: row q = q0 + 16 wave + col, bins 4s + grp
+    const int64_t qa = q0 + 16 * wave + col;
+    const bool qa_in = qa < G;
+    v4d acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int j = 4 * s + grp;
+        const double x = (qa_in && j < N) ? S64[qa * N + j] - off[j] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, wt[j * 16 * NC + 16 * c + col], acc[c],
+                                                          0, 0, 0);
+    }
+    // FP64 output layout: register r holds row grp + 4 r, column col of block c
     double *Tm = T + ms * G * NP;
-#pragma unroll 1
-    for (int e = tid; e < 64 * NP; e += 256) {
-        const int r = e / NP, i = e % NP;
-        double t = 0.0;
-        for (int j = 0; j < N; ++j) t = fma(wt[j * NP + i], xs[r * NP + j], t);
-        const int64_t q = q0 + r;
-        if (q < G) Tm[q * NP + i] = t;
-    }
-    __syncthreads();
-    if (tid < 64) {
-        const int64_t q = q0 + tid;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t q = q0 + 16 * wave + grp + 4 * r;
         double sq = 0.0;
-        if (q < G) {
-            const double *tr = Tm + q * NP;
-            for (int i = 0; i < NP; ++i) sq = fma(tr[i], tr[i], sq);
-            b[ms * b_stride + q] = sq;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int i = 16 * c + col;
+            const double t = acc[c][r];
+            if (q < G && i < NP) Tm[q * NP + i] = t;
+            sq = fma(t, t, sq);   // components past N are exactly zero
         }
+        for (int w = 1; w < 16; w <<= 1) sq += __shfl_xor(sq, w);
+        if (col == 0 && q < G) b[ms * b_stride + q] = sq;
     }
 }
 
