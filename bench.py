@@ -72,7 +72,12 @@ WORKLOADS = {
 # WRITE_SIZE passes scaled by the same counters over a copy of known size
 # (the profiles directory holds the summaries).  Valid only while the kernel
 # sources hash to the value the counters were taken with.
-TRAFFIC = {}
+TRAFFIC = {
+    ("c2", "fp32"): {"bytes_per_launch": 15398686126, "source_hash": "422a2270a4e9ba4e",
+                     "profile": "profiles/k_scan_fp32_c2_counters.md"},
+    ("c2", "split_fp16"): {"bytes_per_launch": 10704148730, "source_hash": "422a2270a4e9ba4e",
+                           "profile": "profiles/k_scan_split_fp16_c2.md"},
+}
 TRAFFIC_SOURCES = ("paper_2002_07858_amd/csrc/k_scan.hip",
                    "paper_2002_07858_amd/csrc/k_scan_split.hip",
                    "paper_2002_07858_amd/csrc/fc_internal.h")
