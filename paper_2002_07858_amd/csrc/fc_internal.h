@@ -37,10 +37,9 @@
 // (zero past N / outside the real rows; 256 B each).  With d = dh + dl split
 // the same way, W_q (d - S_q) = W_q ((dh - Sh) + dl) + C up to rounding, so the
 // residual costs two FP32 instructions, its error is relative to the residual
-// itself, and C is the accumulators' initial value.  Zero padding follows up
-// to a whole number of 4 KB (256 x 16 B) pieces: one grid point's record is
-// rec_units(ns) 16-byte units, which the scan's 256 threads copy with the same
-// number of unpredicated loads each.
+// itself, and C is the accumulators' initial value.  One grid point's record
+// is rec_units(ns) 16-byte units, unpadded; the scan's 256 threads copy it
+// with direct global -> LDS loads, the last piece predicated.
 // ---------------------------------------------------------------------------
 namespace fcx {
 

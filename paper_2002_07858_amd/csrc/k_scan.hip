@@ -7,16 +7,17 @@
 // done on the matrix cores with v_mfma_f32_16x16x4_f32 over the lower-
 // triangular block pattern of W_q only, followed by a column-wise sum of
 // squares, a reduction across the four 16-lane groups and a strict-"<"
-// running minimum per universe.  The FP32 MFMA shares issue with the vector
-// ALU on this chip, so the vector work around it (residuals, squares) is
-// kept to FP32 instructions: FP64 ones cost twice as much.
+// running minimum per universe.  Vector instructions do not overlap the FP32
+// MFMAs on this chip, so the vector work around them (residuals, squares) is
+// kept to few FP32 instructions: FP64 ones cost twice as much.
 //
 // Work decomposition: a 256-thread block owns a tile of 4 waves x 32
 // universes and walks a contiguous range of grid points in list order.  Each
 // wave keeps its universes' residual operands in registers; the block
-// double-buffers one record per grid point in LDS (W_q fragments and S_q),
-// copying the next record while the waves contract the current one, with one
-// barrier per grid point.  Ranges of the same universes are merged with a
+// double-buffers one record per grid point in LDS (W_q fragments, S_q and the
+// correction C_q), bringing the next record in with direct global -> LDS
+// loads while the waves contract the current one, with one barrier per grid
+// point.  Ranges of the same universes are merged with a
 // 64-bit atomicMin on keys (FP32 chi2 bits above q), which reproduces
 // Algorithm 1's rule that the lowest q wins exact ties whatever the split.
 #include "fc_internal.h"
