@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
     __shared__ uint4 t0[TC * kFxThreads], t1[TC * kFxThreads];
     __shared__ uint4 b0[kFxTile / 2], b1[kFxTile / 2];
     __shared__ double red_v[4][kFxTile];
-    __shared__ int64_t red_q[4][kFxTile];
+    __shared__ int32_t red_q[4][kFxTile];
 
     const int64_t tile = blockIdx.x % n_tiles;
     const int chunk = (int)(blockIdx.x / n_tiles);
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
     // tile read as zero and are never reported)
     double yf[4][NS];
     double av[4];
-    int64_t pv[4];
+    int32_t pv[4];   // grid indices fit 31 bits (checked on the host)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int u = 16 * c + col;
@@ -174,14 +174,14 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
         for (int s = 0; s < NS; ++s) yf[c][s] = in ? Y[r * NP + 4 * s + grp] : 0.0;
         av[c] = in ? a[r] : 0.0;
-        pv[c] = in ? p_of_row[r] : -1;
+        pv[c] = in ? (int32_t)p_of_row[r] : -1;
     }
     double best[4];
-    int64_t bq[4];
+    int32_t bq[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         best[c] = __builtin_inf();
-        bq[c] = INT64_MAX;
+        bq[c] = INT32_MAX;
     }
 
     // the t tile of grid points q0 .. q0+63 (and their b) into LDS with
@@ -233,13 +233,14 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
                 acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(t, yf[c][s], acc[c], 0, 0, 0);
         }
         // FP64 output layout: lane l, register j holds row grp + 4 j of the
-        // wave's 16 grid points, universe column col of block c
+        // wave's 16 grid points, universe column col of block c (increasing q
+        // in j, so a strict "<" keeps the lowest q among equal values)
+        const int32_t qrow = (int32_t)q0 + 16 * wave + grp;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int qr = 16 * wave + grp + 4 * j;
-            const int64_t q = q0 + qr;
+            const int32_t q = qrow + 4 * j;
             if (q < qe) {
-                const double bqv = bl[qr];
+                const double bqv = bl[16 * wave + grp + 4 * j];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const double v = (av[c] + bqv) - 2.0 * acc[c][j];
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
         for (int sh = 16; sh <= 32; sh <<= 1) {
             const double ov = __shfl_xor(best[c], sh);
-            const int64_t oq = __shfl_xor(bq[c], sh);
+            const int32_t oq = __shfl_xor(bq[c], sh);
             if (ov < best[c] || (ov == best[c] && oq < bq[c])) {
                 best[c] = ov;
                 bq[c] = oq;
@@ -276,10 +277,10 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
     __syncthreads();
     if (tid < kFxTile && tid < td.n) {
         double v = red_v[0][tid];
-        int64_t q = red_q[0][tid];
+        int32_t q = red_q[0][tid];
         for (int w = 1; w < 4; ++w) {
             const double ov = red_v[w][tid];
-            const int64_t oq = red_q[w][tid];
+            const int32_t oq = red_q[w][tid];
             if (ov < v || (ov == v && oq < q)) {
                 v = ov;
                 q = oq;
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(256) void k_fixed_finish(
         }
     }
     const int64_t k = order[r];
-    if (q == INT64_MAX) q = p_of_row[r];  // no chi2 below +inf: Algorithm 1 keeps p
+    if (!(v < __builtin_inf())) q = p_of_row[r];  // no chi2 below +inf: Algorithm 1 keeps p
     dchi2[k] = cp[r] - v;
     chi2_min[k] = v;
     argmin[k] = q;

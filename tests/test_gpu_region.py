@@ -102,3 +102,24 @@ def test_region_errors(fc):
         fc.fc_region(g, fc.FC_FORM_SPLIT_BF16, dd, crit, acc, K0=16, K_max=64)
     assert ei.value.code == fc.FC_ERR_STATE
     g.destroy()
+
+
+def test_region_split_fp16_matches_oracle_up_to_near_ties(fc):
+    """The region in the split-FP16 form: counts, critical values and
+    acceptance agree with the oracle except where the data value lies within
+    the form's error of an order statistic."""
+    pr, g, dd = setup(fc, "c1", (10, 10), fc.FC_FORM_SPLIT_FP16, 33, 40003)
+    crit, acc, info = run_region(fc, g, fc.FC_FORM_SPLIT_FP16, dd, pr.G, None, 32, 256, 2.0, 13)
+    dd_h = dd.cpu().numpy()
+    g.destroy()
+    ref = oracle.region(pr.S, pr.F, np.arange(pr.G), 32, 256, 2.0, 13, ALPHA, dd_h)
+    same = info["K_used"] == ref["K_used"]
+    near = np.any(np.abs(dd_h[:, None] - ref["crit"]) <= 1e-2 * np.maximum(1.0, ref["crit"]),
+                  axis=1)
+    assert np.all(same | near)
+    assert same.mean() >= 0.9
+    np.testing.assert_array_equal(acc, (dd_h[:, None] <= crit).astype(np.uint8))
+    ok = same[:, None] & (np.abs(dd_h[:, None] - ref["crit"]) > 1e-2)
+    assert np.all((acc == ref["accepted"]) | ~ok)
+    scale = np.maximum(1.0, np.abs(ref["crit"]))
+    assert np.all((np.abs(crit - ref["crit"]) <= 1e-3 * scale) | ~same[:, None])
