@@ -612,3 +612,16 @@ def test_p14_fixed_matrix_reduces_to_per_point_scan():
         for key in ("dchi2", "chi2_min", "argmin", "chi2_p"):
             np.testing.assert_array_equal(r[key], ref[key])
         assert np.all(r["iters"] <= 1)
+
+
+def test_range_split_scan_equals_one_pass():
+    """Algorithm 1's running minimum over the grid walked in consecutive q
+    ranges (the oracle's memory-bounded path for large grids) is exactly the
+    single pass: same values, same minimiser, same second-best."""
+    pr = fcgen.make_problem("c1", K=40, true_subset=[0], n_axis=(12, 12))
+    one = oracle.scan(pr.S, pr.F, pr.d, pr.p_idx)
+    N = pr.N
+    for pts_per_range in (1, 7, 50):
+        many = oracle.scan(pr.S, pr.F, pr.d, pr.p_idx, block_bytes=8 * N * N * pts_per_range)
+        for key in ("dchi2", "chi2_min", "argmin", "chi2_p", "chi2_2nd"):
+            np.testing.assert_array_equal(many[key], one[key])
