@@ -40,7 +40,8 @@ def grids(fc):
     for name, n_axis in (("c1", None), ("c2", None), ("c3", (20, 20, 20))):
         pr = fcgen.make_problem(name, K=1, true_subset=[0], n_axis=n_axis)
         g = fc.fc_build_grid(pr.axes, pr.S)
-        fc.fc_build_covariance(g, pr.F, forms=fc.FC_FORM_FP32 | fc.FC_FORM_SPLIT_FP16)
+        fc.fc_build_covariance(g, pr.F, forms=fc.FC_FORM_FP32 | fc.FC_FORM_SPLIT_FP16 |
+                               fc.FC_FORM_SPLIT_BF16)
         out.append((pr, g))
     yield out
     for _, g in out:
@@ -96,9 +97,10 @@ def wait_all(server, ids, timeout=180.0):
 
 
 @pytest.mark.parametrize("form_name,policy", [("fp32", 0), ("split_fp16", 0), ("fp32", 1),
-                                             ("split_fp16", 1)])
+                                             ("split_fp16", 1), ("split_bf16", 1)])
 def test_mix_equals_alone(fc, grids, form_name, policy):
-    form = {"fp32": fc.FC_FORM_FP32, "split_fp16": fc.FC_FORM_SPLIT_FP16}[form_name]
+    form = {"fp32": fc.FC_FORM_FP32, "split_fp16": fc.FC_FORM_SPLIT_FP16,
+            "split_bf16": fc.FC_FORM_SPLIT_BF16}[form_name]
     server = fc.Server([g for _, g in grids], form=form, hbm_budget=512 << 20,
                        host_budget=512 << 20, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI,
                        launch_evals=2e7, policy=policy)
