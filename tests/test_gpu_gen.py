@@ -153,3 +153,39 @@ def test_generated_universes_scan_matches_oracle(fc):
     rep = parity.report(dev, ref, parity.TOL["fp32"])
     assert rep["e_rel"] <= parity.TOL["fp32"], rep
     assert rep["argmin_agree"] == 1.0, rep
+
+
+def test_large_universe_count_indexing(fc):
+    """2^26 universes drawn on the device and scanned: the universe array has
+    2.5e9 elements, past 32-bit indexing; sampled rows (the last ones
+    included) against the oracle, invariants on every row on the device."""
+    pr = fcgen.make_problem("c1", K=1, true_subset=[0], n_axis=(3, 3))
+    K = 1 << 26
+    p = np.array([1, 4, 8])
+    seg = np.array([0, K // 3, 2 * (K // 3), K])
+    g = fc.fc_build_grid(pr.axes, pr.S)
+    fc.fc_build_covariance(g, pr.F, forms=fc.FC_FORM_FP32)
+    d = torch.empty((K, pr.N), dtype=torch.float64, device="cuda")
+    pi = torch.empty(K, dtype=torch.int64, device="cuda")
+    fc.fc_generate_universes(g, to_dev(p, torch.int64), to_dev(seg, torch.int64), 31, d, pi)
+    o = {k: torch.empty(K, dtype=torch.float64, device="cuda") for k in ("dchi2", "chi2_min",
+                                                                       "chi2_p")}
+    o["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
+    fc.fc_scan(g, fc.FC_FORM_FP32, d, pi, o["dchi2"], o["chi2_min"], o["argmin"], o["chi2_p"])
+    torch.cuda.synchronize()
+    assert bool((o["dchi2"] >= 0).all()) and bool((o["argmin"] >= 0).all())
+    assert bool((o["argmin"] < pr.G).all())
+    rows = np.concatenate([np.arange(5), [K // 3 - 1, K // 3, K // 2], K - 1 - np.arange(5)])
+    k_of = np.searchsorted(seg, rows, side="right") - 1
+    d_host = d[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    dev = {k: v[torch.as_tensor(rows, device="cuda")].cpu().numpy() for k, v in o.items()}
+    g.destroy()
+    del d
+    # the oracle's rows: universe index j = row - seg[k] of point p[k]
+    ref_d = np.concatenate([oracle.universes(pr.S, pr.F, [p[k]], [0, 1], 31,
+                                             u_first=[r - seg[k]])[0]
+                            for r, k in zip(rows, k_of)])
+    assert close(d_host, ref_d)
+    ref = oracle.scan(pr.S, pr.F, ref_d, p[k_of])
+    rep = parity.report(dev, ref, parity.TOL["fp32"])
+    assert rep["e_rel"] <= parity.TOL["fp32"], rep
