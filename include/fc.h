@@ -368,13 +368,26 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
 /*
  * fc_server_submit -- queue one request (returns at once).
  *   grid   index into the server's grids;  p   true point, 0 <= p < G
- *   K      1..2^24 universes;  d   host [K][N] FP64, copied during the call
+ *   K      1..2^20 universes;  d   host [K][N] FP64, copied during the call
  *   req    host out: request id
  * FC_ERR_NOMEM if the request alone exceeds hbm_budget or the host staging
  * memory is exhausted.
  */
 int fc_server_submit(fc_server *s, int32_t grid, int64_t p, int64_t K, const double *d,
                      int64_t *req);
+
+/*
+ * fc_server_submit_drawn -- queue one request whose K universes are drawn on
+ * the device at admission (Section 2, steps 1 and 2 of the per-universe
+ * procedure): universes u_first .. u_first+K-1 of true point p with `seed`,
+ * the stream of fc_generate_universes.  Results are bitwise those of
+ * fc_server_submit with the same universes uploaded; only the outputs cross
+ * PCIe.
+ *   u_first >= 0;  other arguments as fc_server_submit.
+ * FC_ERR_NOT_PD if the grid's fractional matrix has no Cholesky factor.
+ */
+int fc_server_submit_drawn(fc_server *s, int32_t grid, int64_t p, int64_t K, uint64_t seed,
+                           int64_t u_first, int64_t *req);
 
 /*
  * fc_server_poll -- state of a request; when FC_REQ_DONE, copies its results

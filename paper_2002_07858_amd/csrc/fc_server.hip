@@ -121,6 +121,11 @@ struct Req {
     int64_t q_next = 0;
     bool finishing = false;
     hipEvent_t ev_done = nullptr;
+    // universes drawn on the device instead of uploaded
+    bool drawn = false;
+    uint64_t seed = 0;
+    int64_t u_first = 0;
+    int64_t *pu = nullptr, *h_pu = nullptr;  // {p, u_first}
 };
 
 struct Cls {
@@ -178,17 +183,23 @@ struct fc_server {
 
 namespace {
 
-// Both blocks hold the same eight pieces, each rounded to 256 B by carve():
-// universes, segment offsets, dchi2, chi2_min (keys), chi2_p, argmin, crit, hist.
-size_t block_bytes(const fc_server *s, int64_t K, int N)
+// Both blocks hold the same pieces, each rounded to 256 B by carve():
+// universes, segment offsets, {p, u_first}, dchi2, chi2_min (keys), chi2_p,
+// argmin, crit, hist.  A request whose universes are drawn on the device has
+// no universes in its host block.
+size_t block_bytes(const fc_server *s, int64_t K, int N, bool with_universes)
 {
     const size_t k = (size_t)K;
-    return Arena::round(sizeof(double) * k * N) + Arena::round(sizeof(int64_t) * 2) +
-           4 * Arena::round(sizeof(double) * k) + Arena::round(sizeof(double) * s->n_alpha) +
+    return (with_universes ? Arena::round(sizeof(double) * k * N) : 0) +
+           2 * Arena::round(sizeof(int64_t) * 2) + 4 * Arena::round(sizeof(double) * k) +
+           Arena::round(sizeof(double) * s->n_alpha) +
            Arena::round(sizeof(int64_t) * (s->n_bins + 1));
 }
-size_t host_block_bytes(const fc_server *s, int64_t K, int N) { return block_bytes(s, K, N); }
-size_t dev_block_bytes(const fc_server *s, int64_t K, int N) { return block_bytes(s, K, N); }
+size_t host_block_bytes(const fc_server *s, int64_t K, int N, bool drawn)
+{
+    return block_bytes(s, K, N, !drawn);
+}
+size_t dev_block_bytes(const fc_server *s, int64_t K, int N) { return block_bytes(s, K, N, true); }
 
 template <typename T>
 T *carve(char *&cur, size_t count)
@@ -204,8 +215,9 @@ void fc_server::request_pointers(Req &r)
 {
     const int N = grids[r.grid]->N;
     char *h = static_cast<char *>(host_base) + r.host_off;
-    r.h_d = carve<double>(h, (size_t)r.K * N);
+    r.h_d = r.drawn ? nullptr : carve<double>(h, (size_t)r.K * N);
     r.h_seg = carve<int64_t>(h, 2);
+    r.h_pu = carve<int64_t>(h, 2);
     r.h_dchi2 = carve<double>(h, r.K);
     r.h_cmin = carve<double>(h, r.K);
     r.h_chi2p = carve<double>(h, r.K);
@@ -232,12 +244,17 @@ bool fc_server::admit()
         r.crit = carve<double>(dv, n_alpha);
         r.hist = carve<int64_t>(dv, n_bins + 1);
         r.seg = carve<int64_t>(dv, 2);
+        r.pu = carve<int64_t>(dv, 2);
         Cls &c = classes[r.cls];
         hipError_t e;
-        if ((e = hipMemcpyAsync(r.d, r.h_d, sizeof(double) * (size_t)r.K * N,
-                                hipMemcpyHostToDevice, c.stream)) != hipSuccess ||
-            (e = hipMemcpyAsync(r.seg, r.h_seg, sizeof(int64_t) * 2, hipMemcpyHostToDevice,
+        if ((e = hipMemcpyAsync(r.seg, r.h_seg, sizeof(int64_t) * 2, hipMemcpyHostToDevice,
                                 c.stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(r.pu, r.h_pu, sizeof(int64_t) * 2, hipMemcpyHostToDevice,
+                                c.stream)) != hipSuccess ||
+            (e = r.drawn ? fcx::launch_gen_universes(grids[r.grid], 1, r.pu, r.seg, r.pu + 1,
+                                                     r.seed, r.K, r.d, nullptr, nullptr, c.stream)
+                         : hipMemcpyAsync(r.d, r.h_d, sizeof(double) * (size_t)r.K * N,
+                                          hipMemcpyHostToDevice, c.stream)) != hipSuccess ||
             (e = fcx::launch_init_keys(r.K, r.keys, r.chi2p, c.stream)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&r.ev_done, hipEventDisableTiming)) != hipSuccess) {
             device_error = true;
@@ -578,39 +595,49 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
     return FC_OK;
 }
 
-int fc_server_submit(fc_server *s, int32_t grid, int64_t p, int64_t K, const double *d,
-                     int64_t *req)
+namespace {
+
+int submit_common(fc_server *s, int32_t grid, int64_t p, int64_t K, const double *d, bool drawn,
+                  uint64_t seed, int64_t u_first, int64_t *req, const char *who)
 {
-    if (!s || !req) return fail(FC_ERR_INVALID_ARG, "fc_server_submit: NULL argument");
+    if (!s || !req) return fail(FC_ERR_INVALID_ARG, "%s: NULL argument", who);
     if (grid < 0 || grid >= (int32_t)s->grids.size())
-        return fail(FC_ERR_INVALID_ARG, "fc_server_submit: grid %d out of range", grid);
+        return fail(FC_ERR_INVALID_ARG, "%s: grid %d out of range", who, grid);
     const fc_grid *g = s->grids[grid];
     if (p < 0 || p >= g->G)
-        return fail(FC_ERR_INVALID_ARG, "fc_server_submit: p=%lld out of range", (long long)p);
+        return fail(FC_ERR_INVALID_ARG, "%s: p=%lld out of range", who, (long long)p);
     if (K < 1 || K > kMaxK)
-        return fail(FC_ERR_INVALID_ARG, "fc_server_submit: K=%lld not in 1..2^20", (long long)K);
-    if (!d) return fail(FC_ERR_INVALID_ARG, "fc_server_submit: d is NULL");
+        return fail(FC_ERR_INVALID_ARG, "%s: K=%lld not in 1..2^20", who, (long long)K);
+    if (!drawn && !d) return fail(FC_ERR_INVALID_ARG, "%s: d is NULL", who);
+    if (drawn && u_first < 0) return fail(FC_ERR_INVALID_ARG, "%s: u_first < 0", who);
+    if (drawn && !g->lf_ok)
+        return fail(FC_ERR_NOT_PD, "%s: the grid's fractional covariance has no factor", who);
     const size_t dev = Arena::round(dev_block_bytes(s, K, g->N));
     if (dev > s->dev_arena.size())
-        return fail(FC_ERR_NOMEM, "fc_server_submit: request needs %zu B > device budget %zu B", dev,
+        return fail(FC_ERR_NOMEM, "%s: request needs %zu B > device budget %zu B", who, dev,
                     s->dev_arena.size());
     std::unique_ptr<Req> r(new (std::nothrow) Req());
-    if (!r) return fail(FC_ERR_NOMEM, "fc_server_submit: host allocation");
+    if (!r) return fail(FC_ERR_NOMEM, "%s: host allocation", who);
     r->grid = grid;
     r->cls = s->grid_cls[grid];
     r->p = p;
     r->K = K;
-    r->host_bytes = host_block_bytes(s, K, g->N);
+    r->drawn = drawn;
+    r->seed = seed;
+    r->u_first = u_first;
+    r->host_bytes = host_block_bytes(s, K, g->N, drawn);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->device_error) return fail(FC_ERR_DEVICE, "%s", s->error_msg.c_str());
         if (!s->host_arena.alloc(r->host_bytes, &r->host_off))
-            return fail(FC_ERR_NOMEM, "fc_server_submit: host staging memory exhausted");
+            return fail(FC_ERR_NOMEM, "%s: host staging memory exhausted", who);
     }
     s->request_pointers(*r);
-    std::memcpy(r->h_d, d, sizeof(double) * (size_t)K * g->N);
+    if (!drawn) std::memcpy(r->h_d, d, sizeof(double) * (size_t)K * g->N);
     r->h_seg[0] = 0;
     r->h_seg[1] = K;
+    r->h_pu[0] = p;
+    r->h_pu[1] = u_first;
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(s->mu);
     r->id = s->next_id++;
@@ -619,6 +646,21 @@ int fc_server_submit(fc_server *s, int32_t grid, int64_t p, int64_t K, const dou
     s->reqs.emplace(r->id, std::move(r));
     s->cv.notify_all();
     return FC_OK;
+}
+
+}  // namespace
+
+int fc_server_submit(fc_server *s, int32_t grid, int64_t p, int64_t K, const double *d,
+                     int64_t *req)
+{
+    return submit_common(s, grid, p, K, d, false, 0, 0, req, "fc_server_submit");
+}
+
+int fc_server_submit_drawn(fc_server *s, int32_t grid, int64_t p, int64_t K, uint64_t seed,
+                           int64_t u_first, int64_t *req)
+{
+    return submit_common(s, grid, p, K, nullptr, true, seed, u_first, req,
+                         "fc_server_submit_drawn");
 }
 
 int fc_server_poll(fc_server *s, int64_t req, int32_t *state, double *dchi2, double *chi2_min,

@@ -45,7 +45,8 @@ EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_valu
             "fc_scan_fixed_m", "fc_generate_universes", "fc_region", "fc_data_scan",
             "fc_acceptance",
             "fc_grid_inverse_cov", "fc_grid_info",
-            "fc_grid_device_bytes", "fc_grid_destroy", "fc_last_error", "fc_server_create", "fc_server_submit", "fc_server_poll",
+            "fc_grid_device_bytes", "fc_grid_destroy", "fc_last_error", "fc_server_create", "fc_server_submit",
+            "fc_server_submit_drawn", "fc_server_poll",
             "fc_server_stats", "fc_server_destroy")
 
 
@@ -92,11 +93,13 @@ def lib():
         L.fc_server_create.argtypes = [ctypes.POINTER(_p), _p, _i32, _i32, ctypes.c_size_t,
                                        ctypes.c_size_t, _i32, _p, _i32, _dbl, _dbl, _i32]
         L.fc_server_submit.argtypes = [_p, _i32, _i64, _i64, _p, _p]
+        L.fc_server_submit_drawn.argtypes = [_p, _i32, _i64, _i64, ctypes.c_uint64, _i64, _p]
         L.fc_server_poll.argtypes = [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _i32]
         L.fc_server_stats.argtypes = [_p, _p, _p, _p, _p]
         L.fc_server_destroy.argtypes = [_p]
         L.fc_server_destroy.restype = None
-        for name in ("fc_server_create", "fc_server_submit", "fc_server_poll", "fc_server_stats"):
+        for name in ("fc_server_create", "fc_server_submit", "fc_server_submit_drawn",
+                     "fc_server_poll", "fc_server_stats"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
                      "fc_scan_fixed_m", "fc_generate_universes", "fc_region", "fc_data_scan",
@@ -357,6 +360,16 @@ class Server:
         _check(lib().fc_server_submit(_p(self.handle), int(grid), int(p), int(d.shape[0]),
                                       _hp(d), ctypes.byref(req)))
         self.K[req.value] = int(d.shape[0])
+        return req.value
+
+    def submit_drawn(self, grid: int, p: int, K: int, seed: int, u_first: int = 0) -> int:
+        """Queue a request whose K universes (u_first .. u_first+K-1 of point p,
+        stream `seed`) are drawn on the device.  Returns the request id."""
+        req = ctypes.c_int64()
+        _check(lib().fc_server_submit_drawn(_p(self.handle), int(grid), int(p), int(K),
+                                            int(seed) & (2**64 - 1), int(u_first),
+                                            ctypes.byref(req)))
+        self.K[req.value] = int(K)
         return req.value
 
     def poll(self, req: int, release: bool = True):

@@ -161,3 +161,84 @@ def test_admission_waits_for_memory_and_refuses_oversized(fc, grids):
     for i, (gi, p, d) in zip(ids, reqs):
         ref = alone(fc, grids[gi][1], fc.FC_FORM_FP32, p, d)
         np.testing.assert_array_equal(res[i]["dchi2"], ref["dchi2"])
+
+
+def drawn_universes(fc, grid, N, p, K, seed, u_first):
+    d = torch.empty((K, N), dtype=torch.float64, device="cuda")
+    fc.fc_generate_universes(grid, torch.tensor([p], dtype=torch.int64, device="cuda"),
+                             torch.tensor([0, K], dtype=torch.int64, device="cuda"), seed, d,
+                             u_first=torch.tensor([u_first], dtype=torch.int64, device="cuda"))
+    torch.cuda.synchronize()
+    return d.cpu().numpy()
+
+
+@pytest.mark.parametrize("form_name", ["fp32", "split_fp16"])
+def test_drawn_requests_equal_uploaded(fc, grids, form_name):
+    """Requests whose universes are drawn on the device at admission, mixed
+    with uploaded ones: each equals, bit for bit, the same universes drawn by
+    fc_generate_universes and scanned alone."""
+    form = {"fp32": fc.FC_FORM_FP32, "split_fp16": fc.FC_FORM_SPLIT_FP16}[form_name]
+    server = fc.Server([g for _, g in grids], form=form, hbm_budget=256 << 20,
+                       host_budget=256 << 20, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI,
+                       launch_evals=2e7, policy=fc.FC_SCHED_FAIR)
+    rng = np.random.default_rng(7)
+    drawn, uploaded = [], []
+    for j in range(12):
+        gi = int(rng.integers(0, len(grids)))
+        pr, _ = grids[gi]
+        p = int(rng.integers(0, pr.G))
+        K = int(rng.integers(100, 2500))
+        if j % 3 == 2:
+            d = fcgen.universes(4, 3000 + j, pr.S[p], pr.F, K)
+            uploaded.append((server.submit(gi, p, d), gi, p, d))
+        else:
+            seed, uf = int(rng.integers(0, 2**63)), int(rng.integers(0, 10**7))
+            drawn.append((server.submit_drawn(gi, p, K, seed, uf), gi, p, K, seed, uf))
+    res = wait_all(server, [r[0] for r in drawn + uploaded])
+    server.destroy()
+    for i, gi, p, K, seed, uf in drawn:
+        pr, g = grids[gi]
+        ref = alone(fc, g, form, p, drawn_universes(fc, g, pr.N, p, K, seed, uf))
+        for key in ("dchi2", "chi2_min", "argmin", "chi2_p", "crit", "hist"):
+            np.testing.assert_array_equal(res[i][key], ref[key], err_msg=key)
+    for i, gi, p, d in uploaded:
+        ref = alone(fc, grids[gi][1], form, p, d)
+        np.testing.assert_array_equal(res[i]["dchi2"], ref["dchi2"])
+
+
+def test_drawn_request_matches_oracle(fc, grids):
+    """A drawn request against the oracle's own universes (same stream) and
+    scan."""
+    pr, _ = grids[0]
+    server = fc.Server([g for _, g in grids], form=fc.FC_FORM_FP32, hbm_budget=64 << 20,
+                       host_budget=64 << 20, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI)
+    p, K, seed, uf = 137, 500, 2002_07858, 12345
+    i = server.submit_drawn(0, p, K, seed, uf)
+    r = wait_all(server, [i])[i]
+    with pytest.raises(fc.FCError):
+        server.submit_drawn(0, p, K, seed, -1)        # negative first universe
+    server.destroy()
+    d_o, _ = oracle.universes(pr.S, pr.F, [p], [0, K], seed, u_first=[uf])
+    ref = oracle.scan(pr.S, pr.F, d_o, np.full(K, p))
+    rep = parity.report(r, ref, parity.TOL["fp32"])
+    assert rep["e_rel"] <= parity.TOL["fp32"], rep
+    assert rep["argmin_agree"] == 1.0, rep
+
+
+def test_drawn_request_needs_a_factor(fc):
+    """A grid whose fractional matrix is only positive semidefinite can be
+    served with uploaded universes but not drawn ones."""
+    pr = fcgen.make_problem("c1", K=1, true_subset=[0])
+    g = fc.fc_build_grid(pr.axes, pr.S)
+    v = np.linspace(0.05, 0.2, pr.N)
+    fc.fc_build_covariance(g, np.outer(v, v), forms=fc.FC_FORM_FP32)
+    server = fc.Server([g], form=fc.FC_FORM_FP32, hbm_budget=16 << 20, host_budget=16 << 20,
+                       alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI)
+    with pytest.raises(fc.FCError) as ei:
+        server.submit_drawn(0, 3, 100, 1)
+    assert ei.value.code == fc.FC_ERR_NOT_PD
+    d = fcgen.universes(4, 1, pr.S[3], 0.01 * np.eye(pr.N), 100)
+    i = server.submit(0, 3, d)
+    assert wait_all(server, [i])[i]["dchi2"].shape == (100,)
+    server.destroy()
+    g.destroy()
