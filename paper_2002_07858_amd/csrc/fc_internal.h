@@ -13,29 +13,30 @@
 // ---------------------------------------------------------------------------
 // FP32 factor layout for the MFMA scan.
 //
-// The scan computes z = W_q r for a tile of universes with
-// v_mfma_f32_16x16x4_f32: A = a 16x4 block of W_q (rows = z index, cols =
-// bins), B = a 4x16 block of R (bins x universes).  Bins are taken four at a
-// time ("k-steps", ns = ceil(N/4)); z rows sixteen at a time ("row blocks",
-// nb = ceil(ns/4)).  The 16*nb padded rows hold the N real rows shifted down
-// by r0 = 16*nb - 4*ns (a multiple of 4 below 16), so that the padding sits
-// above the first real row and the last row block ends on the last real row.
-// W_q is lower triangular, so row block b only needs the first
-//     cnt(b) = ns - 4*(nb-1-b)
-// k-steps (N = 57: 3+7+11+15 = 36 blocks instead of the full 4*15 = 60).
-// The (s, b) pairs actually needed are enumerated with s outer and b inner;
-// pair t holds, for lane l, the A-operand value
-//     W_q[16b + l%16 - r0][4s + l/16]        (zero outside the triangle)
-// Per grid point the pairs are stored lane-major in groups of four,
-//     W[t/4][lane][t%4]                (ng = ceil(npair/4) groups of 1 KB)
-// so that every lane fetches its next four A values with one 16-byte access
-// and a wave reads 1 KB contiguously.  They are followed by the signal's FP32
-// part in the lane order of the B operand and by the W-image of its rounding
-// error in the lane order of the accumulators,
-//     Sh[g][s] = float(S_q[4s+g])                (g = 0..3, s = 0..15)
-//     C[e]     = float(-sum_k W_q[e-r0][k] (S_q[k] - Sh[k]))   (e = 0..63)
-// (zero past N / outside the real rows; 256 B each).  With d = dh + dl split
-// the same way, W_q (d - S_q) = W_q ((dh - Sh) + dl) + C up to rounding, so the
+// The scan computes z = W_q r with v_mfma_f32_4x4x1_16b_f32, one universe per
+// lane: B is the lane's own residual at one bin, so lane l of output
+// register j accumulates row 4b + j of W_q r for universe l, and chi^2 is the
+// lane's own sum of squares (no cross-lane reduction).  The A operand of each
+// instruction is one 4-row, 1-bin slice of W_q, broadcast from one of the 16
+// four-lane blocks of an A register (CBSZ = 4, ABID = slot), so one register
+// carries 16 slices.  Rows and bins are padded at the top/left by
+// P = 4 ns - N (ns = ceil(N/4)): padded index x' = x + P, so that the short
+// row block is the narrowest one.  Row block b (padded rows 4b .. 4b+3) needs
+// padded bins k' <= 4b + 3.  The (k', b) pairs are enumerated k' outer
+// (0 .. 4ns-1), b inner (k'/4 .. ns-1): npair = 2 ns (ns+1); the P ns pairs
+// with k' < P are zero and skipped by the scan (N = 57: 435 of 480).  Pair t
+// lives in A register t/16, slot t%16; lane 4 (t%16) + m holds
+//     W_q[4b + m - P][k' - P]                    (zero outside the triangle)
+// Per grid point the A registers are stored lane-major in groups of four,
+//     A[v/4][lane][v%4]               (ng = ceil(npair/64) groups of 1 KB)
+// so that a lane fetches four registers with one 16-byte access and a wave
+// reads 1 KB contiguously.  They are followed by the signal's FP32 part (real
+// bin order, read through the scalar cache) and by the W-image of its rounding
+// error (padded row order, the accumulators' start),
+//     Sh[k]  = float(S_q[k])                                      (k < 64)
+//     C[r']  = float(-sum_k W_q[r' - P][k] (S_q[k] - float(S_q[k])))  (r' < 64)
+// (zero outside the real bins / rows; 256 B each).  With d = dh + dl split the
+// same way, W_q (d - S_q) = W_q ((dh - Sh) + dl) + C up to rounding, so the
 // residual costs two FP32 instructions, its error is relative to the residual
 // itself, and C is the accumulators' initial value.  One grid point's record
 // is rec_units(ns) 16-byte units, unpadded; the scan's 256 threads copy it
@@ -45,38 +46,36 @@ namespace fcx {
 
 constexpr int kMaxBins = FC_MAX_BINS;
 constexpr int kWavesPerBlock = 4;
-constexpr int kScanColBlocks = 2;  // 16-universe column blocks per wave (32 universes)
+constexpr int kFp32UnivPerBlock = 64 * kWavesPerBlock;  // one universe per lane
 
 __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int n_ksteps(int N) { return ceil_div(N, 4); }
-__host__ __device__ constexpr int n_rowblocks_from_ns(int ns) { return ceil_div(ns, 4); }
-__host__ __device__ constexpr int row_shift(int ns) { return 16 * n_rowblocks_from_ns(ns) - 4 * ns; }
-__host__ __device__ constexpr int ksteps_of_block(int ns, int b)
-{
-    return ns - 4 * (n_rowblocks_from_ns(ns) - 1 - b);
-}
-__host__ __device__ constexpr int first_block_of_kstep(int ns, int s)
-{
-    int b = 0;
-    while (ksteps_of_block(ns, b) <= s) ++b;
-    return b;
-}
-__host__ __device__ constexpr int n_pairs_from_ns(int ns)
-{
-    int t = 0;
-    for (int b = 0; b < n_rowblocks_from_ns(ns); ++b) t += ksteps_of_block(ns, b);
-    return t;
-}
-__host__ __device__ constexpr int n_groups_from_ns(int ns) { return ceil_div(n_pairs_from_ns(ns), 4); }
+__host__ __device__ constexpr int fp32_pad(int ns, int N) { return 4 * ns - N; }
+__host__ __device__ constexpr int fp32_npairs(int ns) { return 2 * ns * (ns + 1); }
+__host__ __device__ constexpr int n_groups_from_ns(int ns) { return ceil_div(fp32_npairs(ns), 64); }
 __host__ __device__ constexpr int rec_w_units(int ns) { return n_groups_from_ns(ns) * 64; }
 __host__ __device__ constexpr int rec_units(int ns) { return rec_w_units(ns) + 32; }
-// Index of pair (s, b) in the fragment order (s outer, b inner).
-__host__ __device__ constexpr int pair_index(int ns, int s, int b)
+// Index of pair (k', b) in the enumeration order (k' outer, b inner).
+__host__ __device__ constexpr int fp32_pair_index(int ns, int kp, int b)
 {
-    const int nb = n_rowblocks_from_ns(ns);
     int t = 0;
-    for (int s2 = 0; s2 < s; ++s2) t += nb - first_block_of_kstep(ns, s2);
-    return t + (b - first_block_of_kstep(ns, s));
+    for (int c = 0; c < kp; ++c) t += ns - c / 4;
+    return t + (b - kp / 4);
+}
+// Padded bin k' and row block b of pair t (t < npair).
+__host__ __device__ constexpr int fp32_pair_kp(int ns, int t)
+{
+    int kp = 0;
+    while (t >= ns - kp / 4) {
+        t -= ns - kp / 4;
+        ++kp;
+    }
+    return kp;
+}
+__host__ __device__ constexpr int fp32_pair_b(int ns, int t)
+{
+    const int kp = fp32_pair_kp(ns, t);
+    return kp / 4 + (t - fp32_pair_index(ns, kp, kp / 4));
 }
 
 // ---------------------------------------------------------------------------
@@ -228,13 +227,13 @@ struct ScanItem {
     int32_t ed;                   // split FP16: scale exponent of (d - o)
 };
 
-hipError_t launch_serve_fp32(int ns, const ScanItem *items, int n_items, int *counter, int blocks,
+hipError_t launch_serve_fp32(int N, const ScanItem *items, int n_items, int *counter, int blocks,
                              hipStream_t st);
 hipError_t launch_serve_split(int nk, int nb, bool fp16, const ScanItem *items, int n_items,
                               int *counter, int blocks, hipStream_t st);
 int serve_fp32_univ_per_item();
 int serve_split_univ_per_item();
-int serve_slots_fp32(int ns);
+int serve_slots_fp32(int N);
 int serve_slots_split(int nk, int nb, bool fp16);
 
 hipError_t launch_crit_gapped(int64_t n_seg, const int64_t *seg_lo, const int64_t *seg_hi,

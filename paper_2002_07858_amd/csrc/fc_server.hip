@@ -346,7 +346,7 @@ bool fc_server::launch(Cls &c)
                             hipMemcpyHostToDevice, c.stream)) != hipSuccess ||
         (e = hipMemsetAsync(c.d_counter[slot], 0, sizeof(int), c.stream)) != hipSuccess ||
         (e = (form == FC_FORM_FP32)
-                 ? fcx::launch_serve_fp32(c.ns, c.d_items[slot], n, c.d_counter[slot], blocks,
+                 ? fcx::launch_serve_fp32(c.N, c.d_items[slot], n, c.d_counter[slot], blocks,
                                           c.stream)
                  : fcx::launch_serve_split(c.nk, c.nb, form == FC_FORM_SPLIT_FP16,
                                            c.d_items[slot], n, c.d_counter[slot], blocks,
@@ -532,7 +532,7 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
         for (size_t c = 0; c < s->classes.size(); ++c) {
             const Cls &cl = s->classes[c];
             const bool same = (form == FC_FORM_FP32)
-                                  ? cl.ns == fcx::n_ksteps(N)
+                                  ? cl.N == N
                                   : (cl.nk == fcx::split_nk(N) && cl.nb == fcx::split_nb(N));
             if (same) found = (int)c;
         }
@@ -582,7 +582,7 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
                 return cleanup_fail("fc_server_create: launch tables");
         }
         if (s->form == FC_FORM_FP32) {
-            c.slots = fcx::serve_slots_fp32(c.ns);
+            c.slots = fcx::serve_slots_fp32(c.N);
             c.upi = fcx::serve_fp32_univ_per_item();
         } else {
             c.slots = fcx::serve_slots_split(c.nk, c.nb, s->form == FC_FORM_SPLIT_FP16);

@@ -99,7 +99,6 @@ __global__ __launch_bounds__(64) void k_cov_build(
     __shared__ double A[kMaxBins * kLdsStride];
     __shared__ double Wc[kMaxBins * kLdsStride];
     const int i = threadIdx.x;
-    const int nb = n_rowblocks_from_ns(ns);
 
     for (int64_t q = blockIdx.x; q < G; q += gridDim.x) {
         const double *Sq = S64 + q * N;
@@ -157,45 +156,35 @@ __global__ __launch_bounds__(64) void k_cov_build(
                 for (int r = c; r < N; ++r) Wq[tri_index(r, c)] = Wc[r * kLdsStride + c];
         }
         if (forms & FC_FORM_FP32) {
-            // pair t = (s, b) in the scan's order; lane i holds W[16b + i%16 - r0][4s + i/16]
+            // A register v, lane i = 4 X + m: pair t = 16 v + X, i.e. padded
+            // row 4b + m and padded bin k' of that pair
             const int ru = rec_units(ns), wu = rec_w_units(ns);
+            const int P = fp32_pad(ns, N), np = fp32_npairs(ns);
             uint4 *rq = R32 + q * (int64_t)ru;
-            float4 *Wq = reinterpret_cast<float4 *>(rq);
-            const int row_in = i & 15, col_in = i >> 4;
-            const int r0 = row_shift(ns);
-            float vals[4];
-            int slot = 0, gi = 0;
-            for (int s = 0; s < ns; ++s) {
-                for (int b = first_block_of_kstep(ns, s); b < nb; ++b) {
-                    const int rr = 16 * b + row_in - r0, cc = 4 * s + col_in;
-                    vals[slot] = (rr >= 0 && rr < N && cc <= rr) ? (float)Wc[rr * kLdsStride + cc]
-                                                                  : 0.0f;
-                    if (++slot == 4) {
-                        Wq[gi * 64 + i] = make_float4(vals[0], vals[1], vals[2], vals[3]);
-                        slot = 0;
-                        ++gi;
-                    }
+            float *Wq = reinterpret_cast<float *>(rq);
+            const int X = i >> 2, m = i & 3;
+            for (int v = 0; v < 4 * n_groups_from_ns(ns); ++v) {
+                const int t = 16 * v + X;
+                float val = 0.0f;
+                if (t < np) {
+                    const int kp = fp32_pair_kp(ns, t), b = fp32_pair_b(ns, t);
+                    const int rr = 4 * b + m - P, cc = kp - P;
+                    if (rr >= 0 && rr < N && cc >= 0 && cc <= rr) val = (float)Wc[rr * kLdsStride + cc];
                 }
+                Wq[((v >> 2) * 64 + i) * 4 + (v & 3)] = val;
             }
-            if (slot) {
-                for (int z = slot; z < 4; ++z) vals[z] = 0.0f;
-                Wq[gi * 64 + i] = make_float4(vals[0], vals[1], vals[2], vals[3]);
-            }
-            // FP32 part of the signal in B-operand lane order (element g*16 + s
-            // holds S_q[4s + g]); then, in accumulator order (element e is
-            // row e - r0), minus W_q times the signal's FP32 rounding error
+            // FP32 part of the signal (real bin order), then minus W_q times
+            // its rounding error (padded row order)
             float *Sp = reinterpret_cast<float *>(rq + wu);
             {
-                const int g4 = i >> 4, s16 = i & 15, k = 4 * s16 + g4;
-                Sp[i] = (k < N) ? (float)Sq[k] : 0.0f;
-                const int rr = i - r0;
+                Sp[i] = (i < N) ? (float)Sq[i] : 0.0f;
+                const int rr = i - P;
                 double cv = 0.0;
                 if (rr >= 0 && rr < N)
                     for (int kk = 0; kk <= rr; ++kk)
                         cv -= Wc[rr * kLdsStride + kk] * (Sq[kk] - (double)(float)Sq[kk]);
                 Sp[64 + i] = (float)cv;
             }
-            for (int u = wu + 32 + i; u < ru; u += 64) rq[u] = make_uint4(0u, 0u, 0u, 0u);
         }
         if (forms & (FC_FORM_SPLIT_BF16 | FC_FORM_SPLIT_FP16)) {
             const int64_t sru = split_rec_units(split_nk(N), split_nb(N));

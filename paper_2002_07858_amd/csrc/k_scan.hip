@@ -4,23 +4,27 @@
 //     chi2(d, q) = ||W_q (d - S_q)||^2,   W_q = L_q^{-1} (lower triangular),
 // which equals (d-S_q)^T Sigma_q^{-1} (d-S_q).  For a fixed q and a tile of
 // universes this is a dense contraction Z = W_q R (R = bins x universes),
-// done on the matrix cores with v_mfma_f32_16x16x4_f32 over the lower-
-// triangular block pattern of W_q only, followed by a column-wise sum of
-// squares, a reduction across the four 16-lane groups and a strict-"<"
-// running minimum per universe.  Vector instructions do not overlap the FP32
-// MFMAs on this chip, so the vector work around them (residuals, squares) is
-// kept to few FP32 instructions: FP64 ones cost twice as much.
+// done on the matrix cores with v_mfma_f32_4x4x1_16b_f32: one universe per
+// lane, one bin per instruction, the 4-row slice of W_q broadcast to all 16
+// lane blocks.  The 4-row granularity covers the lower triangle with little
+// waste (N = 57: 1740 issued multiply-adds per evaluation for 1653 needed),
+// and each lane ends with its own universe's rows, so chi2 is a lane-local
+// sum of squares followed by a strict-"<" running minimum.  Vector
+// instructions do not overlap the FP32 MFMAs on this chip, so the vector work
+// around them (residuals, squares) is kept to few FP32 instructions.
 //
-// Work decomposition: a 256-thread block owns a tile of 4 waves x 32
-// universes and walks a contiguous range of grid points in list order.  Each
-// wave keeps its universes' residual operands in registers; the block
-// double-buffers one record per grid point in LDS (W_q fragments, S_q and the
+// Work decomposition: a 256-thread block owns 256 universes (one per lane)
+// and walks a contiguous range of grid points in list order.  Each lane
+// keeps its universe's residual sources in registers; the block
+// double-buffers one record per grid point in LDS (W_q slices, S_q and the
 // correction C_q), bringing the next record in with direct global -> LDS
 // loads while the waves contract the current one, with one barrier per grid
 // point.  Ranges of the same universes are merged with a
 // 64-bit atomicMin on keys (FP32 chi2 bits above q), which reproduces
 // Algorithm 1's rule that the lowest q wins exact ties whatever the split.
 #include "fc_internal.h"
+
+#include <utility>
 
 namespace fcx {
 
@@ -31,133 +35,158 @@ __device__ __forceinline__ float pick(const float4 &v, int c)
     return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
 }
 
-// Per grid point the block stages one record in LDS: the W_q fragments (NG
-// groups of 1 KB), the FP32 part of S_q in B-operand order (256 B) and the
-// correction C_q = -W_q (S_q - float(S_q)) in accumulator order (256 B).  Records are
-// double-buffered: while the waves contract grid point q from one buffer, the
-// block's 256 threads copy record q+1 into the other with coalesced 16-byte
-// loads, and one barrier per grid point hands the buffers over.
-template <int NS>
-struct Fp32Geo {
-    static constexpr int NB = n_rowblocks_from_ns(NS);
-    static constexpr int NG = n_groups_from_ns(NS);
-    static constexpr int NWU = rec_w_units(NS);  // 16-byte units of W per record
-    static constexpr int REC = rec_units(NS);    // W + 512 B of S and C
+// Sixteen signal values, read through the scalar cache (uniform per wave).
+struct Sig16 {
+    float v[16];
 };
+typedef const __attribute__((address_space(4))) Sig16 *sig_ptr;
+__device__ __forceinline__ Sig16 load_sig(sig_ptr p, int i)
+{
+    Sig16 r;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) r.v[k] = p[i].v[k];
+    return r;
+}
 
-// Per-universe state a wave carries through its range of grid points.
-template <int NS, int NC>
+// Per-universe state a lane carries through its range of grid points.  The
+// universe is held as d = dh + dl: dh = float(d) and dl, the rest, as FP16
+// scaled by a per-universe power of two 2^e (so that the largest |dl| 2^e
+// lies in [2^14, 2^15)); dl 2^e keeps 11 bits, so d is carried to 35 bits,
+// and the residual costs one subtraction and one mixed FP16/FP32 FMA.
+template <int N>
 struct Fp32Lane {
-    float dh[NC][NS], dl[NC][NS];  // B-operand sources d = dh + dl
-    int64_t p_own;                 // true point of the universe this lane reports
-    float best;                    // running minimum and its grid point
+    float dh[N];
+    uint32_t dl[(N + 1) / 2];  // dl 2^e as FP16, bins 2i (low half) and 2i+1 (high half)
+    float dl_scale;            // 2^-e
+    Sig16 s0;                  // the next grid point's first 16 signal values
+    int64_t p_own;       // the universe's true point (-1: no universe)
+    float best;          // running minimum and its grid point
     uint32_t qbest;
-    float cp;                      // chi2 at the true point, once seen
+    float cp;            // chi2 at the true point, once seen
     bool have_cp;
 };
+
+// r = dl 2^-e + t with dl taken from one FP16 half of a packed register: the
+// compiler folds the half selection and the conversion into one
+// mixed-precision FMA (v_fma_mix_f32).
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+template <int HI>
+__device__ __forceinline__ float fma_mix_dl(uint32_t dl2, float scale, float t)
+{
+    const half2_t h = __builtin_bit_cast(half2_t, dl2);
+    return __builtin_fmaf((float)h[HI], scale, t);
+}
+
+// Per-grid-point operands: the A-register group being consumed and the next
+// one (prefetched from LDS), the current and next 16 signal values (scalar
+// registers) and the residual of the current bin.
+struct Fp32Ops {
+    float4 a_cur, a_nxt;
+    Sig16 s_cur, s_nxt;
+    float r;
+};
+
+// Pair T of the enumeration: rotate the A groups at a group boundary, form
+// the residual at the first pair of its bin, and issue one 4x4x1 MFMA whose
+// A slice is broadcast from slot T % 16 of register T / 16.  Padded bins
+// left of the shift (k' < P) are zero and generate no code.
+template <int N, int T>
+__device__ __forceinline__ void fp32_pair(v4f (&acc)[n_ksteps(N)], Fp32Ops &o, Fp32Lane<N> &L,
+                                          const float4 *__restrict__ wl, sig_ptr sg,
+                                          sig_ptr sg_next, bool more, int lane)
+{
+    constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N);
+    constexpr int KP = fp32_pair_kp(NS, T), B = fp32_pair_b(NS, T);
+    constexpr int V = T / 16, NG = n_groups_from_ns(NS);
+    constexpr int NCH = (N + 15) / 16;  // 16-value signal chunks
+    if constexpr (T % 64 == 0 && T > 0) {
+        o.a_cur = o.a_nxt;
+        if constexpr (T / 64 + 1 < NG) o.a_nxt = wl[(T / 64 + 1) * 64 + lane];
+    }
+    if constexpr (KP >= P) {
+        if constexpr (B == KP / 4) {
+            if constexpr ((KP - P) % 16 == 0) {
+                if constexpr (KP > P) o.s_cur = o.s_nxt;
+                if constexpr ((KP - P) / 16 + 1 < NCH) o.s_nxt = load_sig(sg, (KP - P) / 16 + 1);
+                // with the last chunk in use, fetch the next point's first one
+                if constexpr ((KP - P) / 16 + 1 == NCH)
+                    if (more) L.s0 = load_sig(sg_next, 0);
+            }
+            const float t = L.dh[KP - P] - o.s_cur.v[(KP - P) % 16];
+            o.r = fma_mix_dl<(KP - P) & 1>(L.dl[(KP - P) / 2], L.dl_scale, t);
+        }
+        acc[B] = __builtin_amdgcn_mfma_f32_4x4x1f32(pick(o.a_cur, V % 4), o.r, acc[B], 4, T % 16,
+                                                    0);
+        // one bin at a time: keeps the scheduler from hoisting operands of
+        // later bins (register pressure)
+        if constexpr (B == NS - 1) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int N, int... Ts>
+__device__ __forceinline__ void fp32_pairs(v4f (&acc)[n_ksteps(N)], Fp32Ops &o, Fp32Lane<N> &L,
+                                           const float4 *__restrict__ wl, sig_ptr sg,
+                                           sig_ptr sg_next, bool more, int lane,
+                                           std::integer_sequence<int, Ts...>)
+{
+    (fp32_pair<N, Ts>(acc, o, L, wl, sg, sg_next, more, lane), ...);
+}
 
 // One grid point: contract the record in `cur`, fold chi2 into the running
 // minimum, and (if more) bring the next record into `nxt`.  The two LDS
 // buffers are separate objects so that the compiler can tell the copy into
-// one from the reads of the other.
-template <int NS, int NC>
+// one from the reads of the other.  The signal values come from the record in
+// global memory through scalar loads (read-only data, uniform addresses).
+template <int N>
 __device__ __forceinline__ void fp32_point(int64_t q, bool more, const uint4 *__restrict__ R32,
-                                           const uint4 *cur, uint4 *nxt, Fp32Lane<NS, NC> &L)
+                                           const uint4 *cur, uint4 *nxt, Fp32Lane<N> &L)
 {
-    constexpr int NB = Fp32Geo<NS>::NB;
+    constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N);
     constexpr int NWU = rec_w_units(NS);
     constexpr int REC = rec_units(NS);
     constexpr int THREADS = 64 * kWavesPerBlock;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int grp = lane >> 4;
 
+    // signal values through the scalar cache (the first 16 were fetched during
+    // the previous grid point); then the next record's copy, before the
+    // contraction
+    // the packed FP16 parts are re-presented to the compiler at every grid
+    // point, so that their FP32 conversions stay inside the mixed FMAs
+    // instead of being hoisted out of the grid loop into extra registers
+#pragma unroll
+    for (int i = 0; i < (N + 1) / 2; ++i) asm volatile("" : "+v"(L.dl[i]));
+    Fp32Ops o;
+    sig_ptr sg = (sig_ptr)(R32 + q * REC + NWU);  // Sh, real bins
+    sig_ptr sg_next = (sig_ptr)(R32 + (q + 1) * REC + NWU);
+    o.s_cur = L.s0;
     if (more) record_to_lds<REC, THREADS>(R32 + (q + 1) * REC, nxt, tid);
-    __builtin_amdgcn_sched_barrier(0);  // issue the copy before the contraction
+    __builtin_amdgcn_sched_barrier(0);
 
     const float4 *wl = reinterpret_cast<const float4 *>(cur);
-    const float *shl = reinterpret_cast<const float *>(cur + NWU) + grp * 16;
-    // accumulators start at C_q: rows 4 grp .. 4 grp + 3 of each row block
-    const float4 *cl = reinterpret_cast<const float4 *>(cur + NWU) + 16 + grp;
-    v4f acc[NC][NB];
+    const float4 *cl = reinterpret_cast<const float4 *>(cur + NWU) + 16;  // C, 16 x float4
+    // accumulators start at C_q (the same four rows in every lane)
+    v4f acc[NS];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const float4 cv = cl[4 * b];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c][b] = v4f{cv.x, cv.y, cv.z, cv.w};
+    for (int b = 0; b < NS; ++b) {
+        const float4 cv = cl[b];
+        acc[b] = v4f{cv.x, cv.y, cv.z, cv.w};
     }
+    o.a_cur = wl[lane];
+    if constexpr (n_groups_from_ns(NS) > 1) o.a_nxt = wl[64 + lane];
+    fp32_pairs<N>(acc, o, L, wl, sg, sg_next, more, lane,
+                  std::make_integer_sequence<int, fp32_npairs(NS)>{});
 
-    float4 wv = wl[lane];
-    int wg_loaded = 0;
+    // chi2 = the lane's sum of squares: four FP32 chains over the row blocks
+    // (the P padding rows of block 0 are zero and skipped)
+    float part[4];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const float sh = shl[s];
-        float r[NC];
+    for (int j = 0; j < 4; ++j) {
+        part[j] = (j >= P) ? acc[0][j] * acc[0][j] : 0.0f;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) r[c] = (L.dh[c][s] - sh) + L.dl[c][s];
-#pragma unroll
-        for (int b = first_block_of_kstep(NS, s); b < NB; ++b) {
-            const int t = pair_index(NS, s, b);
-            if ((t >> 2) != wg_loaded) {
-                wg_loaded = t >> 2;
-                wv = wl[wg_loaded * 64 + lane];
-            }
-            const float w = pick(wv, t & 3);
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-                acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, r[c], acc[c][b], 0, 0, 0);
-        }
+        for (int b = 1; b < NS; ++b) part[j] = fmaf(acc[b][j], acc[b][j], part[j]);
     }
-
-    // sum of squares per universe column: FP32 chains of the 4 rows a lane
-    // holds per row block, a pairwise tree over the blocks, then the four
-    // lane groups (FP32 instructions only)
-    float part[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        float blk[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            float a = acc[c][b][0] * acc[c][b][0];
-#pragma unroll
-            for (int j = 1; j < 4; ++j) a = fmaf(acc[c][b][j], acc[c][b][j], a);
-            blk[b] = a;
-        }
-        if constexpr (NB == 4)
-            part[c] = (blk[0] + blk[1]) + (blk[2] + blk[3]);
-        else if constexpr (NB == 3)
-            part[c] = (blk[0] + blk[1]) + blk[2];
-        else if constexpr (NB == 2)
-            part[c] = blk[0] + blk[1];
-        else
-            part[c] = blk[0];
-    }
-    float kk;
-    if constexpr (NC == 4) {
-        // reduce-scatter: lane l ends with column block l/16
-        const bool hi = lane >= 32;
-        float k0 = hi ? part[2] : part[0];
-        float k1 = hi ? part[3] : part[1];
-        const float s0 = hi ? part[0] : part[2];
-        const float s1 = hi ? part[1] : part[3];
-        k0 += __shfl_xor(s0, 32);
-        k1 += __shfl_xor(s1, 32);
-        const bool odd = grp & 1;
-        kk = odd ? k1 : k0;
-        const float ss = odd ? k0 : k1;
-        kk += __shfl_xor(ss, 16);
-    } else {
-        // lanes < 32 end with block 0, lanes >= 32 with block 1: swapping the
-        // upper half of part[0] with the lower half of part[1] leaves lane l
-        // both halves of its block; then rows of 16 lanes are paired
-        const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[0]),
-                                                        __float_as_uint(part[1]), false, false);
-        kk = __uint_as_float(h[0]) + __uint_as_float(h[1]);
-        const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(kk),
-                                                          __float_as_uint(kk), false, false);
-        kk = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
-    }
-    const float chi2 = kk;
+    const float chi2 = (part[0] + part[1]) + (part[2] + part[3]);
 
     if (q == L.p_own) {
         L.cp = chi2;
@@ -172,83 +201,81 @@ __device__ __forceinline__ void fp32_point(int64_t q, bool more, const uint4 *__
     __syncthreads();
 }
 
-template <int NS, int NC>
+template <int N>
 __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4 *buf1)
 {
-    static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
-    constexpr int NG = Fp32Geo<NS>::NG;
-    constexpr int UW = 16 * NC;            // universes per wave
-    constexpr int NWU = rec_w_units(NS);   // 16-byte units of W per record
-    constexpr int REC = rec_units(NS);     // W + 512 B of S and C
+    constexpr int REC = rec_units(n_ksteps(N));  // A groups + 512 B of S and C
     constexpr int THREADS = 64 * kWavesPerBlock;
     static_assert(REC <= 3 * THREADS, "records of at most three 4 KB pieces");
-    static_assert(NG * 64 == NWU, "W groups");
 
     const uint4 *__restrict__ R32 = it.R;
     const double *__restrict__ d = it.d;
     const int64_t K = it.K;
-    const int N = it.N;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int64_t u0 = it.u0 + wave * UW;
+    const int64_t u = it.u0 + tid;  // this lane's universe
     const int64_t qb = it.qb, qe = it.qe;
     if (qb >= qe) return;  // uniform per block
-    const int grp = lane >> 4, col = lane & 15;
 
-    Fp32Lane<NS, NC> L;
-    // B-operand sources as FP32 pairs d = dh + dl: universe u0+16c+col, bin
-    // 4s+grp (zero past N and past K; waves past K still take part in the
-    // copies and barriers)
+    Fp32Lane<N> L;
+    // residual sources d = dh + dl 2^-e (zero past K; lanes past K still take
+    // part in the copies and barriers).  The rest d - dh is exact in FP64.
+    double rest[N];
+    double big = 0.0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const int64_t u = u0 + 16 * c + col;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int k = 4 * s + grp;
-            const double v = (u < K && k < N) ? d[u * N + k] : 0.0;
-            L.dh[c][s] = (float)v;
-            L.dl[c][s] = (float)(v - (double)L.dh[c][s]);
-        }
+    for (int k = 0; k < N; ++k) {
+        const double v = (u < K) ? d[u * N + k] : 0.0;
+        L.dh[k] = (float)v;
+        rest[k] = v - (double)L.dh[k];
+        big = fmax(big, fabs(rest[k]));
     }
-    // after the reduction, lane l holds column block cl of universe column col
-    const int cl = (NC == 4) ? grp : (grp >> 1);
-    const bool owner = (NC == 4) ? true : ((grp & 1) == 0);
-    const int64_t u_own = u0 + 16 * cl + col;
-    L.p_own = (u_own < K) ? (it.p_idx ? it.p_idx[u_own] : it.p) : -1;
+    // largest |rest| 2^e in [2^14, 2^15); e clamped so that 2^-e stays a
+    // normal FP32 number (rests that small are below FP16's reach and vanish)
+    int e = (big > 0.0) ? 14 - ilogb(big) : 0;
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    L.dl_scale = ldexpf(1.0f, -e);
+#pragma unroll
+    for (int i = 0; i < (N + 1) / 2; ++i) {
+        const _Float16 lo = (_Float16)(float)ldexp(rest[2 * i], e);
+        const _Float16 hi = (2 * i + 1 < N) ? (_Float16)(float)ldexp(rest[2 * i + 1], e)
+                                            : (_Float16)0.0f;
+        L.dl[i] = (uint32_t)__builtin_bit_cast(uint16_t, lo) |
+                  ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+    }
+    L.p_own = (u < K) ? (it.p_idx ? it.p_idx[u] : it.p) : -1;
     L.best = __builtin_inff();
     L.qbest = 0xffffffffu;
     L.cp = 0.0f;
     L.have_cp = false;
 
+    L.s0 = load_sig((sig_ptr)(R32 + qb * REC + rec_w_units(n_ksteps(N))), 0);
     record_to_lds<REC, THREADS>(R32 + qb * REC, buf0, tid);
     wait_record_loads();
     __syncthreads();
     // grid points in pairs so that each one's LDS buffer is fixed
     int64_t q = qb;
     for (; q + 1 < qe; q += 2) {
-        fp32_point<NS, NC>(q, true, R32, buf0, buf1, L);
-        fp32_point<NS, NC>(q + 1, q + 2 < qe, R32, buf1, buf0, L);
+        fp32_point<N>(q, true, R32, buf0, buf1, L);
+        fp32_point<N>(q + 1, q + 2 < qe, R32, buf1, buf0, L);
     }
-    if (q < qe) fp32_point<NS, NC>(q, false, R32, buf0, buf1, L);
+    if (q < qe) fp32_point<N>(q, false, R32, buf0, buf1, L);
 
-    if (owner && u_own < K) {
-        if (L.have_cp) it.chi2_p[u_own] = (double)L.cp;
+    if (u < K) {
+        if (L.have_cp) it.chi2_p[u] = (double)L.cp;
         if (L.best < __builtin_inff()) {
             const unsigned long long key =
                 ((unsigned long long)__float_as_uint(L.best) << 32) | (unsigned long long)L.qbest;
-            atomicMin(&it.keys[u_own], key);
+            atomicMin(&it.keys[u], key);
         }
     }
 }
 
-template <int NS, int NC>
+template <int N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32(
     const uint4 *__restrict__ R32, const double *__restrict__ d,
-    const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
+    const int64_t *__restrict__ p_idx, int64_t K, int64_t G, int64_t n_utiles,
     int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
 {
-    __shared__ uint4 buf0[Fp32Geo<NS>::REC], buf1[Fp32Geo<NS>::REC];
+    __shared__ uint4 buf0[rec_units(n_ksteps(N))], buf1[rec_units(n_ksteps(N))];
     ScanItem it;
     it.R = R32;
     it.d = d;
@@ -262,21 +289,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     it.ed = 0;
     const int64_t utile = blockIdx.x % n_utiles;
     const int64_t qchunk = blockIdx.x / n_utiles;
-    it.u0 = utile * (int64_t)(16 * NC * kWavesPerBlock);
+    it.u0 = utile * (int64_t)kFp32UnivPerBlock;
     it.qb = qchunk * q_per_chunk;
     it.qe = (it.qb + q_per_chunk < G) ? it.qb + q_per_chunk : G;
-    fp32_item<NS, NC>(it, buf0, buf1);
+    fp32_item<N>(it, buf0, buf1);
 }
 
 // Serving: a persistent-style launch over a table of items (any mix of
 // requests and grids with this bin count).  Resident blocks take items in
 // turn from an atomic counter until the table is exhausted; the table is
 // finite and fixed at launch, so every block reaches the exit.
-template <int NS, int NC>
+template <int N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_serve_fp32(
     const ScanItem *__restrict__ items, int n_items, int *__restrict__ counter)
 {
-    __shared__ uint4 buf0[Fp32Geo<NS>::REC], buf1[Fp32Geo<NS>::REC];
+    __shared__ uint4 buf0[rec_units(n_ksteps(N))], buf1[rec_units(n_ksteps(N))];
     __shared__ int cur;
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
@@ -284,7 +311,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int i = cur;
         __syncthreads();
         if (i >= n_items) break;
-        fp32_item<NS, NC>(items[i], buf0, buf1);
+        fp32_item<N>(items[i], buf0, buf1);
         __syncthreads();
     }
 }
@@ -417,65 +444,68 @@ ScanGeometry scan_geometry(int64_t K, int64_t G, int slots, int univ_per_block)
     return sg;
 }
 
-template <int NS>
-static hipError_t launch_fp32_ns(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                                 unsigned long long *keys, double *chi2_p, hipStream_t st)
+template <int N>
+static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
+                                unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
-    constexpr int NC = kScanColBlocks;
     static int slots = 0;  // per instantiation; same device model for the process
     if (slots == 0)
-        slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32<NS, NC>),
+        slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32<N>),
                                64 * kWavesPerBlock);
-    const ScanGeometry sg = scan_geometry(K, g->G, slots, 16 * NC * kWavesPerBlock);
+    const ScanGeometry sg = scan_geometry(K, g->G, slots, kFp32UnivPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
-    hipLaunchKernelGGL((k_scan_fp32<NS, NC>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
-                       st, g->R32, d, p_idx, K, g->N, g->G, sg.n_utiles, sg.q_per_chunk, keys,
-                       chi2_p);
+    hipLaunchKernelGGL((k_scan_fp32<N>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, st,
+                       g->R32, d, p_idx, K, g->G, sg.n_utiles, sg.q_per_chunk, keys, chi2_p);
     return hipGetLastError();
 }
 
-template <int NS>
-static hipError_t launch_serve_fp32_ns(const ScanItem *items, int n_items, int *counter, int blocks,
-                                       hipStream_t st)
+template <int N>
+static hipError_t launch_serve_fp32_n(const ScanItem *items, int n_items, int *counter, int blocks,
+                                      hipStream_t st)
 {
-    hipLaunchKernelGGL((k_serve_fp32<NS, kScanColBlocks>), dim3((unsigned)blocks), dim3(256), 0, st,
-                       items, n_items, counter);
+    hipLaunchKernelGGL((k_serve_fp32<N>), dim3((unsigned)blocks), dim3(256), 0, st, items, n_items,
+                       counter);
     return hipGetLastError();
 }
 
-template <int NS>
-static int serve_slots_fp32_ns()
+template <int N>
+static int serve_slots_fp32_n()
 {
     static int slots = 0;
     if (slots == 0)
-        slots = resident_slots(reinterpret_cast<const void *>(&k_serve_fp32<NS, kScanColBlocks>), 256);
+        slots = resident_slots(reinterpret_cast<const void *>(&k_serve_fp32<N>), 256);
     return slots;
 }
 
-int serve_fp32_univ_per_item() { return 16 * kScanColBlocks * kWavesPerBlock; }
+int serve_fp32_univ_per_item() { return kFp32UnivPerBlock; }
 
-hipError_t launch_serve_fp32(int ns, const ScanItem *items, int n_items, int *counter, int blocks,
+// One instantiation per bin count: the padding shift and the skipped pairs
+// are compile-time constants of the kernel.
+#define FC_EACH_N(X)                                                                            \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)       \
+    X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) \
+    X(32) X(33) X(34) X(35) X(36) X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46) \
+    X(47) X(48) X(49) X(50) X(51) X(52) X(53) X(54) X(55) X(56) X(57) X(58) X(59) X(60) X(61) \
+    X(62) X(63) X(64)
+
+hipError_t launch_serve_fp32(int N, const ScanItem *items, int n_items, int *counter, int blocks,
                              hipStream_t st)
 {
-    switch (ns) {
+    switch (N) {
 #define FC_CASE(n) \
-    case n: return launch_serve_fp32_ns<n>(items, n_items, counter, blocks, st);
-        FC_CASE(1) FC_CASE(2) FC_CASE(3) FC_CASE(4) FC_CASE(5) FC_CASE(6) FC_CASE(7) FC_CASE(8)
-        FC_CASE(9) FC_CASE(10) FC_CASE(11) FC_CASE(12) FC_CASE(13) FC_CASE(14) FC_CASE(15)
-        FC_CASE(16)
+    case n: return launch_serve_fp32_n<n>(items, n_items, counter, blocks, st);
+        FC_EACH_N(FC_CASE)
 #undef FC_CASE
     default: return hipErrorInvalidValue;
     }
 }
 
-int serve_slots_fp32(int ns)
+int serve_slots_fp32(int N)
 {
-    switch (ns) {
+    switch (N) {
 #define FC_CASE(n) \
-    case n: return serve_slots_fp32_ns<n>();
-        FC_CASE(1) FC_CASE(2) FC_CASE(3) FC_CASE(4) FC_CASE(5) FC_CASE(6) FC_CASE(7) FC_CASE(8)
-        FC_CASE(9) FC_CASE(10) FC_CASE(11) FC_CASE(12) FC_CASE(13) FC_CASE(14) FC_CASE(15)
-        FC_CASE(16)
+    case n: return serve_slots_fp32_n<n>();
+        FC_EACH_N(FC_CASE)
 #undef FC_CASE
     default: return 512;
     }
@@ -484,16 +514,15 @@ int serve_slots_fp32(int ns)
 hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
                             unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
-    switch (g->ns) {
+    switch (g->N) {
 #define FC_CASE(n) \
-    case n: return launch_fp32_ns<n>(g, K, d, p_idx, keys, chi2_p, st);
-        FC_CASE(1) FC_CASE(2) FC_CASE(3) FC_CASE(4) FC_CASE(5) FC_CASE(6) FC_CASE(7) FC_CASE(8)
-        FC_CASE(9) FC_CASE(10) FC_CASE(11) FC_CASE(12) FC_CASE(13) FC_CASE(14) FC_CASE(15)
-        FC_CASE(16)
+    case n: return launch_fp32_n<n>(g, K, d, p_idx, keys, chi2_p, st);
+        FC_EACH_N(FC_CASE)
 #undef FC_CASE
     default: return hipErrorInvalidValue;
     }
 }
+#undef FC_EACH_N
 
 template <int NP>
 static hipError_t launch_fp64_np(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,

@@ -1,8 +1,10 @@
 // Host-only check of the FP32 fragment layout of the library (fc_internal.h):
-// for every bin count N = 1..64 the (k-step, row-block) pairs enumerated by
-// pair_index cover every entry of the lower triangle of an N x N factor
-// exactly once, never reach outside the padded tile, and are numbered
-// 0..npair-1 in enumeration order.  Prints "ok" or the first failure.
+// for every bin count N = 1..64 the (padded bin, row block) pairs enumerated
+// by fp32_pair_index cover every entry of the lower triangle of an N x N
+// factor exactly once (rows 4b + m - P, bins k' - P, pairs with k' < P
+// skipped), never reach outside the padded tile, are numbered 0..npair-1 in
+// enumeration order, and fp32_pair_kp / fp32_pair_b invert the numbering.
+// Prints "ok" or the first failure.
 #include <cstdio>
 #include <vector>
 
@@ -13,27 +15,35 @@ using namespace fcx;
 int main()
 {
     for (int N = 1; N <= 64; ++N) {
-        const int ns = n_ksteps(N), nb = n_rowblocks_from_ns(ns), r0 = row_shift(ns);
-        if (r0 < 0 || r0 >= 16 || r0 % 4) { printf("N=%d bad shift %d\n", N, r0); return 1; }
+        const int ns = n_ksteps(N), P = fp32_pad(ns, N);
+        if (P < 0 || P > 3) { printf("N=%d bad shift %d\n", N, P); return 1; }
         std::vector<int> hits(N * N, 0);
-        int t_expect = 0;
-        for (int s = 0; s < ns; ++s) {
-            for (int b = first_block_of_kstep(ns, s); b < nb; ++b) {
-                if (pair_index(ns, s, b) != t_expect) { printf("N=%d pair order\n", N); return 1; }
+        int t_expect = 0, issued = 0;
+        for (int kp = 0; kp < 4 * ns; ++kp) {
+            for (int b = kp / 4; b < ns; ++b) {
+                const int t = fp32_pair_index(ns, kp, b);
+                if (t != t_expect) { printf("N=%d pair order\n", N); return 1; }
+                if (fp32_pair_kp(ns, t) != kp || fp32_pair_b(ns, t) != b) {
+                    printf("N=%d pair %d decodes wrongly\n", N, t);
+                    return 1;
+                }
                 ++t_expect;
-                if (s >= ksteps_of_block(ns, b)) { printf("N=%d s beyond block\n", N); return 1; }
-                for (int lane = 0; lane < 64; ++lane) {
-                    const int rr = 16 * b + (lane & 15) - r0, cc = 4 * s + (lane >> 4);
+                if (kp < P) continue;  // zero columns, not issued
+                ++issued;
+                for (int m = 0; m < 4; ++m) {
+                    const int rr = 4 * b + m - P, cc = kp - P;
                     if (rr >= 0 && rr < N && cc <= rr) hits[rr * N + cc] += 1;
                 }
             }
-            // blocks before the first one must not need this k-step
-            for (int b = 0; b < first_block_of_kstep(ns, s); ++b) {
-                const int last_row = 16 * b + 15 - r0;
-                if (4 * s <= last_row) { printf("N=%d skipped needed block\n", N); return 1; }
+            // blocks before the first one must not need this bin
+            for (int b = 0; b < kp / 4; ++b) {
+                const int last_row = 4 * b + 3 - P;
+                if (kp - P <= last_row) { printf("N=%d skipped needed block\n", N); return 1; }
             }
         }
-        if (t_expect != n_pairs_from_ns(ns)) { printf("N=%d npair\n", N); return 1; }
+        if (t_expect != fp32_npairs(ns)) { printf("N=%d npair\n", N); return 1; }
+        if (n_groups_from_ns(ns) * 64 < fp32_npairs(ns)) { printf("N=%d groups\n", N); return 1; }
+        if (issued != fp32_npairs(ns) - P * ns) { printf("N=%d issued\n", N); return 1; }
         for (int r = 0; r < N; ++r)
             for (int c = 0; c < N; ++c)
                 if (hits[r * N + c] != (c <= r ? 1 : 0)) {
@@ -41,8 +51,10 @@ int main()
                     return 1;
                 }
     }
-    printf("pairs N=57: %d, N=38: %d, N=64: %d\n", n_pairs_from_ns(n_ksteps(57)),
-           n_pairs_from_ns(n_ksteps(38)), n_pairs_from_ns(n_ksteps(64)));
+    printf("issued pairs N=57: %d, N=38: %d, N=64: %d\n",
+           fp32_npairs(n_ksteps(57)) - fp32_pad(n_ksteps(57), 57) * n_ksteps(57),
+           fp32_npairs(n_ksteps(38)) - fp32_pad(n_ksteps(38), 38) * n_ksteps(38),
+           fp32_npairs(n_ksteps(64)));
     printf("ok\n");
     return 0;
 }

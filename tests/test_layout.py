@@ -1,4 +1,4 @@
-"""CPU check of the MFMA fragment layout shared by the covariance build and
+"""CPU check of the MFMA slice layout shared by the covariance build and
 the FP32 scan (compiled host-only from the library's own header)."""
 import os
 import subprocess
@@ -20,4 +20,5 @@ def test_fragment_pairs_cover_the_triangle_once(tmp_path):
     subprocess.check_call(cmd)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
     assert out.strip().endswith("ok"), out
-    assert "N=57: 36" in out and "N=38: 18" in out and "N=64: 40" in out
+    # 4-row slices issued per 64 universes: 2 ns (ns+1) - P ns
+    assert "N=57: 435" in out and "N=38: 200" in out and "N=64: 544" in out
