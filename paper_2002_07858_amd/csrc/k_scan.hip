@@ -80,16 +80,41 @@ __device__ __forceinline__ float fma_mix_dl(uint32_t dl2, float scale, float t)
 // Per-grid-point operands: the A-register group being consumed and the next
 // one (prefetched from LDS), the current and next 16 signal values (scalar
 // registers) and the residual of the current bin.
+constexpr int kResGroup = 4;  // residuals formed together (bins)
+
 struct Fp32Ops {
     float4 a_cur, a_nxt;
     Sig16 s_cur, s_nxt;
-    float r;
+    float r[kResGroup];  // residuals of the current group of bins
 };
 
+// Residual of real bin K into o.r[K % kResGroup], rotating the signal chunks
+// when K starts a new one; with the last chunk in use, the next grid point's
+// first chunk is fetched.
+template <int N, int K>
+__device__ __forceinline__ void fp32_residual(Fp32Ops &o, Fp32Lane<N> &L, sig_ptr sg,
+                                              sig_ptr sg_next, bool more)
+{
+    constexpr int NCH = (N + 15) / 16;  // 16-value signal chunks
+    if constexpr (K < N) {
+        if constexpr (K % 16 == 0) {
+            if constexpr (K > 0) o.s_cur = o.s_nxt;
+            if constexpr (K / 16 + 1 < NCH) o.s_nxt = load_sig(sg, K / 16 + 1);
+            if constexpr (K / 16 + 1 == NCH)
+                if (more) L.s0 = load_sig(sg_next, 0);
+        }
+        const float t = L.dh[K] - o.s_cur.v[K % 16];
+        o.r[K % kResGroup] = fma_mix_dl<K & 1>(L.dl[K / 2], L.dl_scale, t);
+    }
+}
+
 // Pair T of the enumeration: rotate the A groups at a group boundary, form
-// the residual at the first pair of its bin, and issue one 4x4x1 MFMA whose
-// A slice is broadcast from slot T % 16 of register T / 16.  Padded bins
-// left of the shift (k' < P) are zero and generate no code.
+// the residuals of a group of kResGroup bins at the first pair of the
+// group's first bin, and issue one 4x4x1 MFMA whose A slice is broadcast
+// from slot T % 16 of register T / 16.  Vector instructions do not overlap
+// the FP32 MFMAs, and each switch from MFMAs to vector work costs about one
+// MFMA's latency, so the residuals are formed in groups rather than one per
+// bin.  Padded bins left of the shift (k' < P) are zero and generate no code.
 template <int N, int T>
 __device__ __forceinline__ void fp32_pair(v4f (&acc)[n_ksteps(N)], Fp32Ops &o, Fp32Lane<N> &L,
                                           const float4 *__restrict__ wl, sig_ptr sg,
@@ -98,28 +123,27 @@ __device__ __forceinline__ void fp32_pair(v4f (&acc)[n_ksteps(N)], Fp32Ops &o, F
     constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N);
     constexpr int KP = fp32_pair_kp(NS, T), B = fp32_pair_b(NS, T);
     constexpr int V = T / 16, NG = n_groups_from_ns(NS);
-    constexpr int NCH = (N + 15) / 16;  // 16-value signal chunks
     if constexpr (T % 64 == 0 && T > 0) {
         o.a_cur = o.a_nxt;
         if constexpr (T / 64 + 1 < NG) o.a_nxt = wl[(T / 64 + 1) * 64 + lane];
     }
     if constexpr (KP >= P) {
-        if constexpr (B == KP / 4) {
-            if constexpr ((KP - P) % 16 == 0) {
-                if constexpr (KP > P) o.s_cur = o.s_nxt;
-                if constexpr ((KP - P) / 16 + 1 < NCH) o.s_nxt = load_sig(sg, (KP - P) / 16 + 1);
-                // with the last chunk in use, fetch the next point's first one
-                if constexpr ((KP - P) / 16 + 1 == NCH)
-                    if (more) L.s0 = load_sig(sg_next, 0);
-            }
-            const float t = L.dh[KP - P] - o.s_cur.v[(KP - P) % 16];
-            o.r = fma_mix_dl<(KP - P) & 1>(L.dl[(KP - P) / 2], L.dl_scale, t);
+        constexpr int K = KP - P;
+        if constexpr (B == KP / 4 && K % kResGroup == 0) {
+            static_assert(kResGroup == 4, "four residuals per group");
+            fp32_residual<N, K>(o, L, sg, sg_next, more);
+            fp32_residual<N, K + 1>(o, L, sg, sg_next, more);
+            fp32_residual<N, K + 2>(o, L, sg, sg_next, more);
+            fp32_residual<N, K + 3>(o, L, sg, sg_next, more);
+            // keep the group's vector work together, ahead of its MFMAs
+            __builtin_amdgcn_sched_barrier(0);
         }
-        acc[B] = __builtin_amdgcn_mfma_f32_4x4x1f32(pick(o.a_cur, V % 4), o.r, acc[B], 4, T % 16,
-                                                    0);
-        // one bin at a time: keeps the scheduler from hoisting operands of
-        // later bins (register pressure)
-        if constexpr (B == NS - 1) __builtin_amdgcn_sched_barrier(0);
+        acc[B] = __builtin_amdgcn_mfma_f32_4x4x1f32(pick(o.a_cur, V % 4), o.r[K % kResGroup],
+                                                    acc[B], 4, T % 16, 0);
+        // one group of bins at a time: keeps the scheduler from hoisting
+        // operands of later bins (register pressure)
+        if constexpr (B == NS - 1 && K % kResGroup == kResGroup - 1)
+            __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -219,25 +243,24 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4
     Fp32Lane<N> L;
     // residual sources d = dh + dl 2^-e (zero past K; lanes past K still take
     // part in the copies and barriers).  The rest d - dh is exact in FP64.
-    double rest[N];
-    double big = 0.0;
+    float rest[N];
+    float big = 0.0f;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const double v = (u < K) ? d[u * N + k] : 0.0;
         L.dh[k] = (float)v;
-        rest[k] = v - (double)L.dh[k];
-        big = fmax(big, fabs(rest[k]));
+        rest[k] = (float)(v - (double)L.dh[k]);
+        big = fmaxf(big, fabsf(rest[k]));
     }
     // largest |rest| 2^e in [2^14, 2^15); e clamped so that 2^-e stays a
     // normal FP32 number (rests that small are below FP16's reach and vanish)
-    int e = (big > 0.0) ? 14 - ilogb(big) : 0;
+    int e = (big > 0.0f) ? 14 - ilogbf(big) : 0;
     e = e < -100 ? -100 : (e > 100 ? 100 : e);
     L.dl_scale = ldexpf(1.0f, -e);
 #pragma unroll
     for (int i = 0; i < (N + 1) / 2; ++i) {
-        const _Float16 lo = (_Float16)(float)ldexp(rest[2 * i], e);
-        const _Float16 hi = (2 * i + 1 < N) ? (_Float16)(float)ldexp(rest[2 * i + 1], e)
-                                            : (_Float16)0.0f;
+        const _Float16 lo = (_Float16)ldexpf(rest[2 * i], e);
+        const _Float16 hi = (2 * i + 1 < N) ? (_Float16)ldexpf(rest[2 * i + 1], e) : (_Float16)0.0f;
         L.dl[i] = (uint32_t)__builtin_bit_cast(uint16_t, lo) |
                   ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
     }
