@@ -80,7 +80,7 @@ __device__ __forceinline__ float fma_mix_dl(uint32_t dl2, float scale, float t)
 // Per-grid-point operands: the A-register group being consumed and the next
 // one (prefetched from LDS), the current and next 16 signal values (scalar
 // registers) and the residual of the current bin.
-constexpr int kResGroup = 4;  // residuals formed together (bins)
+constexpr int kResGroup = 8;  // residuals formed together (bins)
 
 struct Fp32Ops {
     float4 a_cur, a_nxt;
@@ -130,11 +130,15 @@ __device__ __forceinline__ void fp32_pair(v4f (&acc)[n_ksteps(N)], Fp32Ops &o, F
     if constexpr (KP >= P) {
         constexpr int K = KP - P;
         if constexpr (B == KP / 4 && K % kResGroup == 0) {
-            static_assert(kResGroup == 4, "four residuals per group");
+            static_assert(kResGroup == 8, "eight residuals per group");
             fp32_residual<N, K>(o, L, sg, sg_next, more);
             fp32_residual<N, K + 1>(o, L, sg, sg_next, more);
             fp32_residual<N, K + 2>(o, L, sg, sg_next, more);
             fp32_residual<N, K + 3>(o, L, sg, sg_next, more);
+            fp32_residual<N, K + 4>(o, L, sg, sg_next, more);
+            fp32_residual<N, K + 5>(o, L, sg, sg_next, more);
+            fp32_residual<N, K + 6>(o, L, sg, sg_next, more);
+            fp32_residual<N, K + 7>(o, L, sg, sg_next, more);
             // keep the group's vector work together, ahead of its MFMAs
             __builtin_amdgcn_sched_barrier(0);
         }
