@@ -70,26 +70,26 @@ WORKLOADS = {
 
 # HBM traffic of the scan kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by the same counters over a copy of known size
-# (the profiles directory holds the summaries).  Valid only while the kernel
+# (the profiles directory holds the summaries).  Valid only while the kernel's
 # sources hash to the value the counters were taken with.
+FP32_SOURCES = ("paper_2002_07858_amd/csrc/k_scan.hip", "paper_2002_07858_amd/csrc/fc_internal.h")
+SPLIT_SOURCES = ("paper_2002_07858_amd/csrc/k_scan_split.hip",
+                 "paper_2002_07858_amd/csrc/fc_internal.h")
 TRAFFIC = {
-    ("c2", "fp32"): {"bytes_per_launch": 15398686126, "source_hash": "7a2aa53b4679788d",
-                     "profile": "profiles/k_scan_fp32_c2_counters.md"},
-    ("c2", "split_fp16"): {"bytes_per_launch": 10704148730, "source_hash": "7a2aa53b4679788d",
-                           "profile": "profiles/k_scan_split_fp16_c2.md"},
+    ("c2", "fp32"): {"bytes_per_launch": 10770685185, "source_hash": "4fa35b95b2811a7e",
+                     "sources": FP32_SOURCES, "profile": "profiles/k_scan_fp32_c2_counters.md"},
+    ("c2", "split_fp16"): {"bytes_per_launch": None, "source_hash": None,
+                           "sources": SPLIT_SOURCES, "profile": "profiles/k_scan_split_fp16_c2.md"},
 }
-TRAFFIC_SOURCES = ("paper_2002_07858_amd/csrc/k_scan.hip",
-                   "paper_2002_07858_amd/csrc/k_scan_split.hip",
-                   "paper_2002_07858_amd/csrc/fc_internal.h")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the scan sources with // comments and blank lines removed (a
+def kernel_source_hash(sources) -> str:
+    """Hash of a kernel's sources with // comments and blank lines removed (a
     comment edit does not invalidate the counters; any code edit does)."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel)) as f:
             for line in f:
                 code = re.sub(r"//.*", "", line).rstrip()
@@ -480,7 +480,7 @@ def main():
                 "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None}
     tr = TRAFFIC.get((args.workload, args.form))
-    if tr is not None and tr["source_hash"] == kernel_source_hash():
+    if tr is not None and tr["source_hash"] == kernel_source_hash(tr["sources"]):
         roofline["traffic"] = tr["bytes_per_launch"]
         roofline["traffic_GBps"] = tr["bytes_per_launch"] / (scan_ms * 1e-3) / 1e9
         roofline["traffic_source"] = tr["profile"]
