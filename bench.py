@@ -78,7 +78,7 @@ SPLIT_SOURCES = ("paper_2002_07858_amd/csrc/k_scan_split.hip",
 TRAFFIC = {
     ("c2", "fp32"): {"bytes_per_launch": 10770685185, "source_hash": "4fa35b95b2811a7e",
                      "sources": FP32_SOURCES, "profile": "profiles/k_scan_fp32_c2_counters.md"},
-    ("c2", "split_fp16"): {"bytes_per_launch": None, "source_hash": None,
+    ("c2", "split_fp16"): {"bytes_per_launch": 10706519139, "source_hash": "6983b2e8921d48ea",
                            "sources": SPLIT_SOURCES, "profile": "profiles/k_scan_split_fp16_c2.md"},
 }
 

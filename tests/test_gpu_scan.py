@@ -151,6 +151,32 @@ def test_scan_parity_bin_counts(fc, N):
         assert rep["argmin_agree"] == 1.0, (form, rep)
 
 
+@pytest.mark.parametrize("N", list(range(1, 65)))
+def test_fp32_every_bin_count(fc, N):
+    """The FP32 kernel is compiled once per bin count (the padding shift, the
+    skipped slices and the signal-chunk boundaries are constants of each
+    instantiation): every N against the oracle, with an odd grid (a grid point
+    left over after the pairs), two universe tiles and a ragged second one."""
+    rng = np.random.default_rng(1000 + N)
+    G, K = 23, 300
+    S = rng.uniform(20, 800, size=(G, N))
+    A = rng.normal(size=(N, 2 * N))
+    W = A @ A.T
+    dw = np.sqrt(np.diag(W))
+    F = 0.5 * ((W / np.outer(dw, dw)) + (W / np.outer(dw, dw)).T) * 0.02
+    p = rng.integers(0, G, size=K)
+    d = S[p] + rng.normal(0, 1, size=(K, N)) * np.sqrt(S[p])
+    ref = oracle.scan(S, F, d, p)
+    g = fc.fc_build_grid([np.arange(float(G))], S)
+    fc.fc_build_covariance(g, F, forms=FORM["fp32"])
+    dev = run_scan(fc, g, FORM["fp32"], d, p)
+    g.destroy()
+    parity.check_invariants(dev, G)
+    rep = parity.report(dev, ref, parity.TOL["fp32"])
+    assert rep["e_rel"] <= parity.TOL["fp32"], rep
+    assert rep["argmin_agree"] == 1.0, rep
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
