@@ -177,6 +177,41 @@ int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2
                       double hist_hi, int64_t *hist, hipStream_t stream);
 
 /*
+ * fc_scan_points -- the scan of fc_scan for universes grouped by true point,
+ * the shape of Algorithm 1 (one true point p, N_univ universes fluctuated
+ * around S(p)).  Segment pt = [seg_off[pt], seg_off[pt+1]) holds universes of
+ * true point p[pt]; results are those of fc_scan with p_idx[u] = p[pt] (to
+ * the FP32 tolerance in the FP32 form, identical in the others).  In the FP32
+ * form a wave of 64 universes of one segment uses
+ *     W_q (d - S_q) = W_q (d - S_p) + W_q (S_p - S_q),
+ * with d - S_p rounded to FP32 once and the second term taken from an offset
+ * table built for the call, so its grid loop does no per-bin vector work;
+ * waves that straddle segments take fc_scan's residual form.
+ *   n_pts, p       n_pts >= 1 (when K > 0); device int64 [n_pts] true points
+ *                  (outside [0, G): those universes get NaN as in fc_scan)
+ *   seg_off        device int64 [n_pts+1], non-decreasing, seg_off[0] = 0,
+ *                  seg_off[n_pts] = K (rows are assigned by it)
+ *   K, d           host K; device [K][N] FP64 universes
+ *   workspace      device scratch of at least fc_scan_points_workspace()
+ *                  bytes, 256-byte aligned, owned by the caller; calls that
+ *                  overlap in time need separate workspaces
+ *   dchi2, chi2_min, argmin, chi2_p   as fc_scan
+ * Asynchronous; FC_ERR_INVALID_ARG for a short or misaligned workspace.
+ */
+int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t *p,
+                   const int64_t *seg_off, int64_t K, const double *d, void *workspace,
+                   size_t workspace_bytes, double *dchi2, double *chi2_min, int64_t *argmin,
+                   double *chi2_p, hipStream_t stream);
+
+/*
+ * fc_scan_points_workspace -- bytes of workspace fc_scan_points needs for
+ * (form, n_pts, K) on this grid: 12 K (+ alignment) and, for the FP32 form,
+ * 16 ns n_pts G for the offset table (C2: 256 points: 614 MB).
+ */
+int fc_scan_points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K,
+                             size_t *bytes);
+
+/*
  * fc_scan_fixed_m -- Algorithm 1 as printed: one matrix M for the whole grid
  * scan of a universe, and its iteration (Section 2, step 5: update M at the
  * minimiser and scan again until the minimiser repeats).  Per universe k,

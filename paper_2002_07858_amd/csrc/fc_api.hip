@@ -317,6 +317,78 @@ int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d, const in
     return fail(FC_ERR_UNSUPPORTED, "fc_scan: form %d not implemented", form);
 }
 
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Workspace of fc_scan_points: p_idx [K] int64, pt_idx [K] int32 and, for the
+// FP32 form, the offset table [n_pts][G][4 ns] FP32.
+size_t points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K)
+{
+    size_t b = align256(sizeof(int64_t) * (size_t)K) + align256(sizeof(int32_t) * (size_t)K);
+    if (form == FC_FORM_FP32) b += sizeof(float) * (size_t)n_pts * (size_t)g->G * 4 * (size_t)g->ns;
+    return b;
+}
+
+}  // namespace
+
+int fc_scan_points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K,
+                             size_t *bytes)
+{
+    g_last_error.clear();
+    if (!g || !bytes) return fail(FC_ERR_INVALID_ARG, "fc_scan_points_workspace: NULL argument");
+    if (n_pts < 0 || K < 0 || n_pts > 0x7fffffff)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_workspace: bad n_pts or K");
+    *bytes = points_workspace(g, form, n_pts, K);
+    return FC_OK;
+}
+
+int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t *p,
+                   const int64_t *seg_off, int64_t K, const double *d, void *workspace,
+                   size_t workspace_bytes, double *dchi2, double *chi2_min, int64_t *argmin,
+                   double *chi2_p, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_scan_points: grid is NULL");
+    if (form != FC_FORM_FP64 && form != FC_FORM_FP32 && form != FC_FORM_SPLIT_BF16 &&
+        form != FC_FORM_SPLIT_FP16)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points: bad form %d", form);
+    if (!(g->forms & (uint32_t)form))
+        return fail(FC_ERR_STATE, "fc_scan_points: form %d was not built for this grid", form);
+    if (K < 0 || n_pts < 0 || n_pts > 0x7fffffff)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points: bad n_pts or K");
+    if (K == 0) return FC_OK;
+    if (n_pts == 0) return fail(FC_ERR_INVALID_ARG, "fc_scan_points: K > 0 universes, no points");
+    if (K > (int64_t(1) << 30))
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points: K=%lld > 2^30", (long long)K);
+    if (!p || !seg_off || !d || !workspace || !dchi2 || !chi2_min || !argmin || !chi2_p)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points: NULL device pointer");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points: workspace not 256-byte aligned");
+    const size_t need = points_workspace(g, form, n_pts, K);
+    if (workspace_bytes < need)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points: workspace %zu B < %zu B", workspace_bytes,
+                    need);
+    char *ws = static_cast<char *>(workspace);
+    int64_t *p_idx = reinterpret_cast<int64_t *>(ws);
+    int32_t *pt_idx = reinterpret_cast<int32_t *>(ws + align256(sizeof(int64_t) * (size_t)K));
+    float *T = reinterpret_cast<float *>(ws + align256(sizeof(int64_t) * (size_t)K) +
+                                         align256(sizeof(int32_t) * (size_t)K));
+    hipError_t e;
+    if ((e = fcx::launch_expand_segments(K, n_pts, seg_off, p, p_idx, pt_idx, stream)) != hipSuccess)
+        return hip_fail(e, "fc_scan_points: segment expansion");
+    if (form != FC_FORM_FP32)
+        return fc_scan(g, form, K, d, p_idx, dchi2, chi2_min, argmin, chi2_p, stream);
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
+    if ((e = fcx::launch_offset_table(g, n_pts, p, T, stream)) != hipSuccess ||
+        (e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
+        (e = fcx::launch_scan_fp32(g, K, d, p_idx, keys, chi2_p, stream, T, pt_idx)) !=
+            hipSuccess ||
+        (e = fcx::launch_finalize(K, p_idx, keys, argmin, chi2_p, dchi2, stream)) != hipSuccess)
+        return hip_fail(e, "fc_scan_points: fp32 launch");
+    return FC_OK;
+}
+
 int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2, int32_t n_alpha,
                       const double *alpha, double *crit, int32_t n_bins, double hist_hi,
                       int64_t *hist, hipStream_t stream)

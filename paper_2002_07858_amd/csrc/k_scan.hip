@@ -160,6 +160,31 @@ __device__ __forceinline__ void fp32_pairs(v4f (&acc)[n_ksteps(N)], Fp32Ops &o, 
     (fp32_pair<N, Ts>(acc, o, L, wl, sg, sg_next, more, lane), ...);
 }
 
+// chi2 = the lane's sum of squares (four FP32 chains over the row blocks; the
+// P padding rows of block 0 are zero and skipped), folded into the running
+// minimum with Algorithm 1's strict "<", and kept when q is the true point.
+template <int NS, int P>
+__device__ __forceinline__ void fp32_fold(const v4f (&acc)[NS], int64_t q, int64_t p_own,
+                                          float &best, uint32_t &qbest, float &cp, bool &have_cp)
+{
+    float part[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        part[j] = (j >= P) ? acc[0][j] * acc[0][j] : 0.0f;
+#pragma unroll
+        for (int b = 1; b < NS; ++b) part[j] = fmaf(acc[b][j], acc[b][j], part[j]);
+    }
+    const float chi2 = (part[0] + part[1]) + (part[2] + part[3]);
+    if (q == p_own) {
+        cp = chi2;
+        have_cp = true;
+    }
+    if (chi2 < best) {
+        best = chi2;
+        qbest = (uint32_t)q;
+    }
+}
+
 // One grid point: contract the record in `cur`, fold chi2 into the running
 // minimum, and (if more) bring the next record into `nxt`.  The two LDS
 // buffers are separate objects so that the compiler can tell the copy into
@@ -205,32 +230,16 @@ __device__ __forceinline__ void fp32_point(int64_t q, bool more, const uint4 *__
     fp32_pairs<N>(acc, o, L, wl, sg, sg_next, more, lane,
                   std::make_integer_sequence<int, fp32_npairs(NS)>{});
 
-    // chi2 = the lane's sum of squares: four FP32 chains over the row blocks
-    // (the P padding rows of block 0 are zero and skipped)
-    float part[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        part[j] = (j >= P) ? acc[0][j] * acc[0][j] : 0.0f;
-#pragma unroll
-        for (int b = 1; b < NS; ++b) part[j] = fmaf(acc[b][j], acc[b][j], part[j]);
-    }
-    const float chi2 = (part[0] + part[1]) + (part[2] + part[3]);
-
-    if (q == L.p_own) {
-        L.cp = chi2;
-        L.have_cp = true;
-    }
-    if (chi2 < L.best) {
-        L.best = chi2;
-        L.qbest = (uint32_t)q;
-    }
+    fp32_fold<NS, P>(acc, q, L.p_own, L.best, L.qbest, L.cp, L.have_cp);
 
     if (more) wait_record_loads();
     __syncthreads();
 }
 
+// Residual form for a wave whose universes do not share one true point (or
+// when no offset table is given): d - S_q is formed per bin and grid point.
 template <int N>
-__device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4 *buf1)
+__device__ __forceinline__ void fp32_run_slow(const ScanItem &it, uint4 *buf0, uint4 *buf1)
 {
     constexpr int REC = rec_units(n_ksteps(N));  // A groups + 512 B of S and C
     constexpr int THREADS = 64 * kWavesPerBlock;
@@ -242,7 +251,6 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4
     const int tid = threadIdx.x;
     const int64_t u = it.u0 + tid;  // this lane's universe
     const int64_t qb = it.qb, qe = it.qe;
-    if (qb >= qe) return;  // uniform per block
 
     Fp32Lane<N> L;
     // residual sources d = dh + dl 2^-e (zero past K; lanes past K still take
@@ -296,13 +304,183 @@ __device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4
     }
 }
 
+// Offset form for a wave whose universes all belong to one true point p
+// (Algorithm 1 runs per true point): with e = d - S_p rounded to FP32 once,
+//     W_q (d - S_q) = W_q e + T_pq,    T_pq = W_q (S_p - S_q),
+// and T_pq (FP64 arithmetic on the FP32 factor, rounded once) is the
+// accumulators' start, read from a table built before the scan.  The MFMAs
+// take e straight from registers, so the grid loop has no vector work besides
+// the squares and the minimum.
+template <int N>
+struct Fp32Fast {
+    float e[N];       // d - S_p
+    int64_t p_own;    // -1: no universe
+    float best;
+    uint32_t qbest;
+    float cp;
+    bool have_cp;
+};
+
+// Copy one offset-table row (4 ns floats, 16-byte aligned) into the wave's
+// LDS slot with direct global -> LDS loads, one 16-byte piece per lane.
+template <int NS>
+__device__ __forceinline__ void trow_to_lds(const float *__restrict__ row, float4 *dst_wave, int lane)
+{
+    if (lane < NS)
+        __builtin_amdgcn_global_load_lds((const void *)(row + 4 * lane),
+                                         (__attribute__((address_space(3))) void *)dst_wave, 16, 0,
+                                         0);
+}
+
+template <int N, int T>
+__device__ __forceinline__ void fp32_fast_pair(v4f (&acc)[n_ksteps(N)], float4 &a_cur, float4 &a_nxt,
+                                               const Fp32Fast<N> &L, const float4 *__restrict__ wl,
+                                               int lane)
+{
+    constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N);
+    constexpr int KP = fp32_pair_kp(NS, T), B = fp32_pair_b(NS, T);
+    constexpr int V = T / 16, NG = n_groups_from_ns(NS);
+    if constexpr (T % 64 == 0 && T > 0) {
+        a_cur = a_nxt;
+        if constexpr (T / 64 + 1 < NG) a_nxt = wl[(T / 64 + 1) * 64 + lane];
+    }
+    if constexpr (KP >= P) {
+        acc[B] = __builtin_amdgcn_mfma_f32_4x4x1f32(pick(a_cur, V % 4), L.e[KP - P], acc[B], 4,
+                                                    T % 16, 0);
+        if constexpr (B == NS - 1 && (KP - P) % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int N, int... Ts>
+__device__ __forceinline__ void fp32_fast_pairs(v4f (&acc)[n_ksteps(N)], float4 &a_cur,
+                                                float4 &a_nxt, const Fp32Fast<N> &L,
+                                                const float4 *__restrict__ wl, int lane,
+                                                std::integer_sequence<int, Ts...>)
+{
+    (fp32_fast_pair<N, Ts>(acc, a_cur, a_nxt, L, wl, lane), ...);
+}
+
+template <int N>
+__device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint4 *__restrict__ R32,
+                                                const float *__restrict__ trow, const uint4 *cur,
+                                                uint4 *nxt, const float4 *tcur, float4 *tnxt, int wv,
+                                                Fp32Fast<N> &L)
+{
+    constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N);
+    constexpr int REC = rec_units(NS);
+    constexpr int NR = 4 * NS;
+    constexpr int THREADS = 64 * kWavesPerBlock;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+
+    if (more) {
+        record_to_lds<REC, THREADS>(R32 + (q + 1) * REC, nxt, tid);
+        trow_to_lds<NS>(trow + (q + 1) * NR, tnxt + 16 * wv, lane);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    const float4 *wl = reinterpret_cast<const float4 *>(cur);
+    v4f acc[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) {
+        const float4 tv = tcur[16 * wv + b];
+        acc[b] = v4f{tv.x, tv.y, tv.z, tv.w};
+    }
+    float4 a_cur = wl[lane], a_nxt = a_cur;
+    if constexpr (n_groups_from_ns(NS) > 1) a_nxt = wl[64 + lane];
+    fp32_fast_pairs<N>(acc, a_cur, a_nxt, L, wl, lane,
+                       std::make_integer_sequence<int, fp32_npairs(NS)>{});
+    fp32_fold<NS, P>(acc, q, L.p_own, L.best, L.qbest, L.cp, L.have_cp);
+
+    if (more) wait_record_loads();
+    __syncthreads();
+}
+
+template <int N>
+__device__ __forceinline__ void fp32_run_fast(const ScanItem &it, uint4 *buf0, uint4 *buf1,
+                                              float4 *tb0, float4 *tb1, int32_t pt, int64_t p)
+{
+    constexpr int NS = n_ksteps(N);
+    constexpr int REC = rec_units(NS);
+    constexpr int NR = 4 * NS;
+    constexpr int THREADS = 64 * kWavesPerBlock;
+    const uint4 *__restrict__ R32 = it.R;
+    const int64_t K = it.K;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t u = it.u0 + tid;
+    const int64_t qb = it.qb, qe = it.qe;
+    const bool act = u < K;
+
+    Fp32Fast<N> L;
+    const double *__restrict__ sp = it.S64 + p * N;  // uniform: scalar loads
+#pragma unroll
+    for (int k = 0; k < N; ++k) L.e[k] = act ? (float)(it.d[u * N + k] - sp[k]) : 0.0f;
+    L.p_own = act ? p : -1;
+    L.best = __builtin_inff();
+    L.qbest = 0xffffffffu;
+    L.cp = 0.0f;
+    L.have_cp = false;
+    const float *__restrict__ trow = it.T + (int64_t)pt * it.G * NR;
+
+    record_to_lds<REC, THREADS>(R32 + qb * REC, buf0, tid);
+    trow_to_lds<NS>(trow + qb * NR, tb0 + 16 * wv, lane);
+    wait_record_loads();
+    __syncthreads();
+    int64_t q = qb;
+    for (; q + 1 < qe; q += 2) {
+        fp32_fast_point<N>(q, true, R32, trow, buf0, buf1, tb0, tb1, wv, L);
+        fp32_fast_point<N>(q + 1, q + 2 < qe, R32, trow, buf1, buf0, tb1, tb0, wv, L);
+    }
+    if (q < qe) fp32_fast_point<N>(q, false, R32, trow, buf0, buf1, tb0, tb1, wv, L);
+
+    if (act) {
+        if (L.have_cp) it.chi2_p[u] = (double)L.cp;
+        if (L.best < __builtin_inff()) {
+            const unsigned long long key =
+                ((unsigned long long)__float_as_uint(L.best) << 32) | (unsigned long long)L.qbest;
+            atomicMin(&it.keys[u], key);
+        }
+    }
+}
+
+// One work item (a tile of 256 universes x a range of grid points).  With an
+// offset table, a wave whose active universes share one segment (and a valid
+// true point) takes the offset form, any other wave the residual form; both
+// walk the same grid points with the same copies and barriers.
+template <int N>
+__device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4 *buf1, float4 *tb0,
+                                          float4 *tb1)
+{
+    if (it.qb >= it.qe) return;  // uniform per block
+    if (it.T != nullptr) {
+        const int64_t u = it.u0 + threadIdx.x;
+        const bool act = u < it.K;
+        const int32_t pt = act ? it.pt_idx[u] : -1;
+        const int64_t p = act ? it.p_idx[u] : -1;
+        const int32_t pt0 = __builtin_amdgcn_readfirstlane(pt);
+        const int64_t p0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(p >> 32)) << 32) |
+                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)p));
+        const bool mixed = act && (pt != pt0 || p != p0);
+        if (pt0 >= 0 && p0 >= 0 && p0 < it.G && __ballot(mixed) == 0) {
+            fp32_run_fast<N>(it, buf0, buf1, tb0, tb1, pt0, p0);
+            return;
+        }
+    }
+    fp32_run_slow<N>(it, buf0, buf1);
+}
+
 template <int N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32(
     const uint4 *__restrict__ R32, const double *__restrict__ d,
     const int64_t *__restrict__ p_idx, int64_t K, int64_t G, int64_t n_utiles,
-    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
+    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p,
+    const float *__restrict__ T, const int32_t *__restrict__ pt_idx,
+    const double *__restrict__ S64)
 {
     __shared__ uint4 buf0[rec_units(n_ksteps(N))], buf1[rec_units(n_ksteps(N))];
+    __shared__ float4 tb0[16 * kWavesPerBlock], tb1[16 * kWavesPerBlock];
     ScanItem it;
     it.R = R32;
     it.d = d;
@@ -314,12 +492,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     it.K = K;
     it.N = N;
     it.ed = 0;
+    it.T = T;
+    it.pt_idx = pt_idx;
+    it.S64 = S64;
+    it.G = G;
     const int64_t utile = blockIdx.x % n_utiles;
     const int64_t qchunk = blockIdx.x / n_utiles;
     it.u0 = utile * (int64_t)kFp32UnivPerBlock;
     it.qb = qchunk * q_per_chunk;
     it.qe = (it.qb + q_per_chunk < G) ? it.qb + q_per_chunk : G;
-    fp32_item<N>(it, buf0, buf1);
+    fp32_item<N>(it, buf0, buf1, tb0, tb1);
 }
 
 // Serving: a persistent-style launch over a table of items (any mix of
@@ -331,6 +513,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const ScanItem *__restrict__ items, int n_items, int *__restrict__ counter)
 {
     __shared__ uint4 buf0[rec_units(n_ksteps(N))], buf1[rec_units(n_ksteps(N))];
+    __shared__ float4 tb0[16 * kWavesPerBlock], tb1[16 * kWavesPerBlock];
     __shared__ int cur;
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
@@ -338,7 +521,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int i = cur;
         __syncthreads();
         if (i >= n_items) break;
-        fp32_item<N>(items[i], buf0, buf1);
+        fp32_item<N>(items[i], buf0, buf1, tb0, tb1);
         __syncthreads();
     }
 }
@@ -473,7 +656,8 @@ ScanGeometry scan_geometry(int64_t K, int64_t G, int slots, int univ_per_block)
 
 template <int N>
 static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                                unsigned long long *keys, double *chi2_p, hipStream_t st)
+                                unsigned long long *keys, double *chi2_p, const float *T,
+                                const int32_t *pt_idx, hipStream_t st)
 {
     static int slots = 0;  // per instantiation; same device model for the process
     if (slots == 0)
@@ -482,7 +666,106 @@ static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, co
     const ScanGeometry sg = scan_geometry(K, g->G, slots, kFp32UnivPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     hipLaunchKernelGGL((k_scan_fp32<N>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, st,
-                       g->R32, d, p_idx, K, g->G, sg.n_utiles, sg.q_per_chunk, keys, chi2_p);
+                       g->R32, d, p_idx, K, g->G, sg.n_utiles, sg.q_per_chunk, keys, chi2_p, T,
+                       pt_idx, g->S64);
+    return hipGetLastError();
+}
+
+// Offset table of the FP32 offset form: T[pt][q][r'] = sum_k' W'_q[r'][k']
+// (S_p - S_q)[k' - P] for the true point p = p[pt] of every segment, in FP64
+// arithmetic on the FP32 factor as the scan uses it (padded rows r' < 4 ns),
+// rounded once to FP32; rows of an out-of-range p are zero (such segments take
+// the residual form).  One block per grid point (grid-stride): the record's A
+// slices are expanded into a dense padded W' in LDS, and each thread computes
+// the 4 ns rows of one segment.
+template <int N>
+__global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ R32,
+                                                      const double *__restrict__ S64, int64_t G,
+                                                      int64_t n_pts, const int64_t *__restrict__ p,
+                                                      float *__restrict__ T)
+{
+    constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N), NR = 4 * NS;
+    constexpr int REC = rec_units(NS), NP = fp32_npairs(NS), NG = n_groups_from_ns(NS);
+    constexpr int WS = NR + 1;  // LDS row stride (floats)
+    __shared__ float W[NR * WS];
+    __shared__ double Sq[NR];
+    __shared__ unsigned char pk[NP], pb[NP];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int t = 0;
+        for (int kp = 0; kp < NR; ++kp)
+            for (int b = kp / 4; b < NS; ++b, ++t) {
+                pk[t] = (unsigned char)kp;
+                pb[t] = (unsigned char)b;
+            }
+    }
+    __syncthreads();
+    for (int64_t q = blockIdx.x; q < G; q += gridDim.x) {
+        for (int i = tid; i < NR * WS; i += blockDim.x) W[i] = 0.0f;
+        for (int i = tid; i < NR; i += blockDim.x) Sq[i] = (i >= P) ? S64[q * N + (i - P)] : 0.0;
+        __syncthreads();
+        const float *rec = reinterpret_cast<const float *>(R32 + q * REC);
+        // float f of the A part: register v = 4 (f / 256) + f % 4, lane (f / 4) % 64
+        for (int f = tid; f < NG * 256; f += blockDim.x) {
+            const int v = 4 * (f / 256) + (f & 3), ln = (f >> 2) & 63;
+            const int t = 16 * v + (ln >> 2);
+            if (t < NP) W[(4 * pb[t] + (ln & 3)) * WS + pk[t]] = rec[f];
+        }
+        __syncthreads();
+        for (int64_t pt = tid; pt < n_pts; pt += blockDim.x) {
+            const int64_t pp = p[pt];
+            double acc[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+            if (pp >= 0 && pp < G) {
+                const double *sp = S64 + pp * N;
+#pragma unroll
+                for (int kp = P; kp < NR; ++kp) {
+                    const double dk = sp[kp - P] - Sq[kp];
+#pragma unroll
+                    for (int r = kp; r < NR; ++r) acc[r] = fma((double)W[r * WS + kp], dk, acc[r]);
+                }
+            }
+            float4 *dst = reinterpret_cast<float4 *>(T + (pt * G + q) * NR);
+#pragma unroll
+            for (int b = 0; b < NS; ++b)
+                dst[b] = make_float4((float)acc[4 * b], (float)acc[4 * b + 1], (float)acc[4 * b + 2],
+                                     (float)acc[4 * b + 3]);
+        }
+        __syncthreads();
+    }
+}
+
+// Segment expansion: universe u of segment pt = max{k : seg_off[k] <= u}
+// gets p_idx[u] = p[pt] and pt_idx[u] = pt.
+__global__ __launch_bounds__(256) void k_expand_segments(int64_t K, int64_t n_pts,
+                                                         const int64_t *__restrict__ seg_off,
+                                                         const int64_t *__restrict__ p,
+                                                         int64_t *__restrict__ p_idx,
+                                                         int32_t *__restrict__ pt_idx)
+{
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < K;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = n_pts - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (seg_off[mid] <= u)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        p_idx[u] = p[lo];
+        pt_idx[u] = (int32_t)lo;
+    }
+}
+
+template <int N>
+static hipError_t launch_offset_table_n(const fc_grid *g, int64_t n_pts, const int64_t *p, float *T,
+                                        hipStream_t st)
+{
+    const int64_t blocks = g->G < 65536 ? g->G : 65536;
+    hipLaunchKernelGGL((k_offset_table<N>), dim3((unsigned)blocks), dim3(256), 0, st, g->R32, g->S64,
+                       g->G, n_pts, p, T);
     return hipGetLastError();
 }
 
@@ -539,15 +822,38 @@ int serve_slots_fp32(int N)
 }
 
 hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                            unsigned long long *keys, double *chi2_p, hipStream_t st)
+                            unsigned long long *keys, double *chi2_p, hipStream_t st,
+                            const float *T, const int32_t *pt_idx)
 {
     switch (g->N) {
 #define FC_CASE(n) \
-    case n: return launch_fp32_n<n>(g, K, d, p_idx, keys, chi2_p, st);
+    case n: return launch_fp32_n<n>(g, K, d, p_idx, keys, chi2_p, T, pt_idx, st);
         FC_EACH_N(FC_CASE)
 #undef FC_CASE
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_offset_table(const fc_grid *g, int64_t n_pts, const int64_t *p, float *T,
+                               hipStream_t st)
+{
+    switch (g->N) {
+#define FC_CASE(n) \
+    case n: return launch_offset_table_n<n>(g, n_pts, p, T, st);
+        FC_EACH_N(FC_CASE)
+#undef FC_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_expand_segments(int64_t K, int64_t n_pts, const int64_t *seg_off,
+                                  const int64_t *p, int64_t *p_idx, int32_t *pt_idx, hipStream_t st)
+{
+    int64_t blocks = (K + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_expand_segments, dim3((unsigned)blocks), dim3(256), 0, st, K, n_pts, seg_off,
+                       p, p_idx, pt_idx);
+    return hipGetLastError();
 }
 #undef FC_EACH_N
 

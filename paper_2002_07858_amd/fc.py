@@ -41,7 +41,8 @@ FC_REQ_RUNNING = 1
 FC_REQ_DONE = 2
 FC_REQ_FAILED = -1
 
-EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
+EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_scan_points",
+            "fc_scan_points_workspace", "fc_critical_value",
             "fc_scan_fixed_m", "fc_generate_universes", "fc_region", "fc_data_scan",
             "fc_acceptance",
             "fc_grid_inverse_cov", "fc_grid_info",
@@ -74,6 +75,9 @@ def lib():
         L.fc_build_grid.argtypes = [ctypes.POINTER(_p), _i32, _p, _p, _i32, _p, _p, _p]
         L.fc_build_covariance.argtypes = [_p, _p, _i32, _p, _u32, _p, _p]
         L.fc_scan.argtypes = [_p, _i32, _i64, _p, _p, _p, _p, _p, _p, _p]
+        L.fc_scan_points.argtypes = [_p, _i32, _i64, _p, _p, _i64, _p, _p, ctypes.c_size_t, _p,
+                                     _p, _p, _p, _p]
+        L.fc_scan_points_workspace.argtypes = [_p, _i32, _i64, _i64, _p]
         L.fc_critical_value.argtypes = [_i64, _p, _p, _i32, _p, _p, _i32, _dbl, _p, _p]
         L.fc_generate_universes.argtypes = [_p, _i64, _p, _p, _p, ctypes.c_uint64, _i64, _p, _p,
                                             _p, _p]
@@ -101,7 +105,8 @@ def lib():
         for name in ("fc_server_create", "fc_server_submit", "fc_server_submit_drawn",
                      "fc_server_poll", "fc_server_stats"):
             getattr(L, name).restype = ctypes.c_int
-        for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_critical_value",
+        for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_scan_points",
+                     "fc_scan_points_workspace", "fc_critical_value",
                      "fc_scan_fixed_m", "fc_generate_universes", "fc_region", "fc_data_scan",
             "fc_acceptance",
             "fc_grid_inverse_cov", "fc_grid_info"):
@@ -219,6 +224,34 @@ def fc_scan(grid: Grid, form: int, d, p_idx, dchi2, chi2_min, argmin, chi2_p, st
                          _dev(dchi2, "f64", "dchi2"), _dev(chi2_min, "f64", "chi2_min"),
                          _dev(argmin, "i64", "argmin"), _dev(chi2_p, "f64", "chi2_p"),
                          _stream(stream)))
+
+
+def fc_scan_points_workspace(grid: Grid, form: int, n_pts: int, K: int) -> int:
+    """Bytes of workspace fc_scan_points needs."""
+    b = ctypes.c_size_t()
+    _check(lib().fc_scan_points_workspace(grid._h, int(form), int(n_pts), int(K),
+                                          ctypes.byref(b)))
+    return b.value
+
+
+def fc_scan_points(grid: Grid, form: int, p, seg_off, d, dchi2, chi2_min, argmin, chi2_p,
+                   workspace=None, stream=None):
+    """Enqueue the scan of universes grouped by true point: segment i of
+    seg_off (n_pts + 1 offsets) holds universes of true point p[i].  The
+    workspace (a uint8 CUDA tensor) is allocated here when not given."""
+    import torch
+    K = int(d.shape[0])
+    n_pts = int(p.numel())
+    need = fc_scan_points_workspace(grid, form, n_pts, K)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=d.device)
+    _check(lib().fc_scan_points(grid._h, int(form), n_pts, _dev(p, "i64", "p"),
+                                _dev(seg_off, "i64", "seg_off"), K, _dev(d, "f64", "d"),
+                                _dev(workspace, "u8", "workspace"), int(workspace.numel()),
+                                _dev(dchi2, "f64", "dchi2"), _dev(chi2_min, "f64", "chi2_min"),
+                                _dev(argmin, "i64", "argmin"), _dev(chi2_p, "f64", "chi2_p"),
+                                _stream(stream)))
+    return workspace
 
 
 def fc_critical_value(seg_off, dchi2, alpha, crit, n_bins=200, hist_hi=50.0, hist=None,
