@@ -76,9 +76,9 @@ FP32_SOURCES = ("paper_2002_07858_amd/csrc/k_scan.hip", "paper_2002_07858_amd/cs
 SPLIT_SOURCES = ("paper_2002_07858_amd/csrc/k_scan_split.hip",
                  "paper_2002_07858_amd/csrc/fc_internal.h")
 TRAFFIC = {
-    ("c2", "fp32"): {"bytes_per_launch": 10770685185, "source_hash": "4fa35b95b2811a7e",
+    ("c2", "fp32", "universes"): {"bytes_per_launch": 10770685185, "source_hash": "4fa35b95b2811a7e",
                      "sources": FP32_SOURCES, "profile": "profiles/k_scan_fp32_c2_counters.md"},
-    ("c2", "split_fp16"): {"bytes_per_launch": 10706519139, "source_hash": "6983b2e8921d48ea",
+    ("c2", "split_fp16", "universes"): {"bytes_per_launch": 10706519139, "source_hash": "6983b2e8921d48ea",
                            "sources": SPLIT_SOURCES, "profile": "profiles/k_scan_split_fp16_c2.md"},
 }
 
@@ -369,6 +369,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--form", default=None, choices=["fp32", "fp64", "split_bf16", "split_fp16"],
                     help="scan form (default fp32; fp64 for c1)")
+    ap.add_argument("--scan", default="points", choices=["points", "universes"],
+                    help="scan entry: fc_scan_points (universes grouped by true point, "
+                    "default) or fc_scan (per-universe true points)")
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-per-point", type=int, default=None,
                     help="universes per true point in the CPU-baseline sample")
@@ -436,13 +439,26 @@ def main():
 
     ev = {k: torch.cuda.Event(enable_timing=True) for k in ("c0", "c1", "s0", "s1", "k1")}
 
+    # universes grouped by true point (Algorithm 1's shape): fc_scan_points with
+    # a workspace allocated once; --scan universes uses fc_scan with per-universe
+    # true points instead
+    pts_t = torch.as_tensor(pr.p_idx[pr.seg_off[:-1]]).to(dev)
+    ws = None
+    if args.scan == "points":
+        ws = torch.empty(fc.fc_scan_points_workspace(grid, form, n_seg, K), dtype=torch.uint8,
+                         device=dev)
+
     def step(times=None):
         ev["c0"].record(stream)
         fc.fc_build_covariance(grid, pr.F, pr.stat_mode, pr.stat_diag, forms=form)
         ev["c1"].record(stream)
         ev["s0"].record(stream)
-        fc.fc_scan(grid, form, d_t, p_t, outs["dchi2"], outs["chi2_min"], outs["argmin"],
-                   outs["chi2_p"])
+        if args.scan == "points":
+            fc.fc_scan_points(grid, form, pts_t, so_t, d_t, outs["dchi2"], outs["chi2_min"],
+                              outs["argmin"], outs["chi2_p"], workspace=ws)
+        else:
+            fc.fc_scan(grid, form, d_t, p_t, outs["dchi2"], outs["chi2_min"], outs["argmin"],
+                       outs["chi2_p"])
         ev["s1"].record(stream)
         fc.fc_critical_value(so_t, outs["dchi2"], ALPHA, crit, N_BINS, HIST_HI, hist)
         ev["k1"].record(stream)
@@ -479,7 +495,7 @@ def main():
     roofline = {"bound": "alu" if args.form == "fp64" else "mfma", "achieved": achieved / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None}
-    tr = TRAFFIC.get((args.workload, args.form))
+    tr = TRAFFIC.get((args.workload, args.form, args.scan))
     if tr is not None and tr["source_hash"] == kernel_source_hash(tr["sources"]):
         roofline["traffic"] = tr["bytes_per_launch"]
         roofline["traffic_GBps"] = tr["bytes_per_launch"] / (scan_ms * 1e-3) / 1e9
@@ -500,7 +516,8 @@ def main():
            "config": {"workload": wl["desc"] + ", per-point FP64 covariance factor, "
                                   f"{args.form} scan, crit at 0.6827/0.9/0.95 + 200-bin hist",
                       "G": G, "N": N, "K_total": K, "evals_per_step": evals,
-                      "form": args.form, "parallelism": "single-gpu"},
+                      "form": args.form, "scan_entry": "fc_scan_points" if args.scan == "points"
+                      else "fc_scan", "parallelism": "single-gpu"},
            "phases_ms": {k: float(np.mean(v)) for k, v in times.items()},
            "scan_evals_per_s": evals / (scan_ms * 1e-3),
            "bitwise_deterministic": deterministic,

@@ -179,16 +179,18 @@ int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2
 /*
  * fc_scan_points -- the scan of fc_scan for universes grouped by true point,
  * the shape of Algorithm 1 (one true point p, N_univ universes fluctuated
- * around S(p)).  Segment pt = [seg_off[pt], seg_off[pt+1]) holds universes of
- * true point p[pt]; results are those of fc_scan with p_idx[u] = p[pt] (to
- * the FP32 tolerance in the FP32 form, identical in the others).  In the FP32
- * form a wave of 64 universes of one segment uses
+ * around S(p)).  Segment s = [seg_off[s], seg_off[s+1]) holds universes of
+ * true point p[s]; results are those of fc_scan with p_idx[u] = p[s] (to the
+ * FP32 tolerance in the FP32 form, identical in the others).  The FP32 form
+ * scans tiles of up to 256 universes of one segment with
  *     W_q (d - S_q) = W_q (d - S_p) + W_q (S_p - S_q),
- * with d - S_p rounded to FP32 once and the second term taken from an offset
- * table built for the call, so its grid loop does no per-bin vector work;
- * waves that straddle segments take fc_scan's residual form.
- *   n_pts, p       n_pts >= 1 (when K > 0); device int64 [n_pts] true points
- *                  (outside [0, G): those universes get NaN as in fc_scan)
+ * d - S_p rounded to FP32 once and the second term taken from an offset
+ * table built for the call (FP64 arithmetic, rounded once), so its grid loop
+ * does no per-bin vector work.
+ *   n_pts, p       n_pts >= 1 (when K > 0); device int64 [n_pts] true points;
+ *                  a segment whose point is outside [0, G) is not scanned in
+ *                  the FP32 form (dchi2, chi2_p NaN, chi2_min +inf, argmin p;
+ *                  fc_scan's NaN in the others)
  *   seg_off        device int64 [n_pts+1], non-decreasing, seg_off[0] = 0,
  *                  seg_off[n_pts] = K (rows are assigned by it)
  *   K, d           host K; device [K][N] FP64 universes
@@ -205,7 +207,7 @@ int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t 
 
 /*
  * fc_scan_points_workspace -- bytes of workspace fc_scan_points needs for
- * (form, n_pts, K) on this grid: 12 K (+ alignment) and, for the FP32 form,
+ * (form, n_pts, K) on this grid: 8 K (+ alignment) and, for the FP32 form,
  * 16 ns n_pts G for the offset table (C2: 256 points: 614 MB).
  */
 int fc_scan_points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K,

@@ -194,12 +194,15 @@ hipError_t launch_scan_split(const fc_grid *g, bool fp16, int64_t K, const doubl
                              const int64_t *p_idx, unsigned long long *keys, double *chi2_p,
                              hipStream_t st);
 hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                            unsigned long long *keys, double *chi2_p, hipStream_t st,
-                            const float *T = nullptr, const int32_t *pt_idx = nullptr);
+                            unsigned long long *keys, double *chi2_p, hipStream_t st);
+hipError_t launch_scan_fp32_points(const fc_grid *g, int64_t n_pts, const int64_t *p,
+                                   const int64_t *seg_off, int64_t K, const double *d,
+                                   const float *T, unsigned long long *keys, double *chi2_p,
+                                   hipStream_t st);
 hipError_t launch_offset_table(const fc_grid *g, int64_t n_pts, const int64_t *p, float *T,
                                hipStream_t st);
 hipError_t launch_expand_segments(int64_t K, int64_t n_pts, const int64_t *seg_off,
-                                  const int64_t *p, int64_t *p_idx, int32_t *pt_idx, hipStream_t st);
+                                  const int64_t *p, int64_t *p_idx, hipStream_t st);
 hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
                             double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p,
                             hipStream_t st);
@@ -230,11 +233,6 @@ struct ScanItem {
     int64_t qb, qe;               // grid points [qb, qe)
     int32_t N;                    // bins
     int32_t ed;                   // split FP16: scale exponent of (d - o)
-    // FP32 offset form (all null/0: residual form only)
-    const float *T;               // [n_pts][G][4 ns] offset table W_q (S_p - S_q)
-    const int32_t *pt_idx;        // [K] segment (table row block) of each universe
-    const double *S64;            // the grid's FP64 signal
-    int64_t G;                    // grid points (table stride)
 };
 
 hipError_t launch_serve_fp32(int N, const ScanItem *items, int n_items, int *counter, int blocks,

@@ -327,10 +327,6 @@ bool fc_server::launch(Cls &c)
                 it.qe = qe;
                 it.N = g->N;
                 it.ed = (form == FC_FORM_SPLIT_FP16) ? g->ed16 : 0;
-                it.T = nullptr;  // residual form
-                it.pt_idx = nullptr;
-                it.S64 = g->S64;
-                it.G = g->G;
             }
             const double w = (double)r->K * (double)(qe - qb);
             budget -= w;

@@ -236,10 +236,10 @@ __device__ __forceinline__ void fp32_point(int64_t q, bool more, const uint4 *__
     __syncthreads();
 }
 
-// Residual form for a wave whose universes do not share one true point (or
-// when no offset table is given): d - S_q is formed per bin and grid point.
+// One work item (a tile of 256 universes x a range of grid points) in the
+// residual form: d - S_q is formed per bin and grid point.
 template <int N>
-__device__ __forceinline__ void fp32_run_slow(const ScanItem &it, uint4 *buf0, uint4 *buf1)
+__device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4 *buf1)
 {
     constexpr int REC = rec_units(n_ksteps(N));  // A groups + 512 B of S and C
     constexpr int THREADS = 64 * kWavesPerBlock;
@@ -251,6 +251,7 @@ __device__ __forceinline__ void fp32_run_slow(const ScanItem &it, uint4 *buf0, u
     const int tid = threadIdx.x;
     const int64_t u = it.u0 + tid;  // this lane's universe
     const int64_t qb = it.qb, qe = it.qe;
+    if (qb >= qe) return;  // uniform per block
 
     Fp32Lane<N> L;
     // residual sources d = dh + dl 2^-e (zero past K; lanes past K still take
@@ -363,7 +364,7 @@ __device__ __forceinline__ void fp32_fast_pairs(v4f (&acc)[n_ksteps(N)], float4 
 template <int N>
 __device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint4 *__restrict__ R32,
                                                 const float *__restrict__ trow, const uint4 *cur,
-                                                uint4 *nxt, const float4 *tcur, float4 *tnxt, int wv,
+                                                uint4 *nxt, const float4 *tcur, float4 *tnxt,
                                                 Fp32Fast<N> &L)
 {
     constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N);
@@ -375,7 +376,7 @@ __device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint
 
     if (more) {
         record_to_lds<REC, THREADS>(R32 + (q + 1) * REC, nxt, tid);
-        trow_to_lds<NS>(trow + (q + 1) * NR, tnxt + 16 * wv, lane);
+        if (tid < 64) trow_to_lds<NS>(trow + (q + 1) * NR, tnxt, lane);
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -383,7 +384,7 @@ __device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint
     v4f acc[NS];
 #pragma unroll
     for (int b = 0; b < NS; ++b) {
-        const float4 tv = tcur[16 * wv + b];
+        const float4 tv = tcur[b];
         acc[b] = v4f{tv.x, tv.y, tv.z, tv.w};
     }
     float4 a_cur = wl[lane], a_nxt = a_cur;
@@ -391,96 +392,21 @@ __device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint
     fp32_fast_pairs<N>(acc, a_cur, a_nxt, L, wl, lane,
                        std::make_integer_sequence<int, fp32_npairs(NS)>{});
     fp32_fold<NS, P>(acc, q, L.p_own, L.best, L.qbest, L.cp, L.have_cp);
+    // the sums of squares stay with their grid point (one set of accumulators
+    // live at a time)
+    __builtin_amdgcn_sched_barrier(0);
 
     if (more) wait_record_loads();
     __syncthreads();
 }
 
 template <int N>
-__device__ __forceinline__ void fp32_run_fast(const ScanItem &it, uint4 *buf0, uint4 *buf1,
-                                              float4 *tb0, float4 *tb1, int32_t pt, int64_t p)
-{
-    constexpr int NS = n_ksteps(N);
-    constexpr int REC = rec_units(NS);
-    constexpr int NR = 4 * NS;
-    constexpr int THREADS = 64 * kWavesPerBlock;
-    const uint4 *__restrict__ R32 = it.R;
-    const int64_t K = it.K;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t u = it.u0 + tid;
-    const int64_t qb = it.qb, qe = it.qe;
-    const bool act = u < K;
-
-    Fp32Fast<N> L;
-    const double *__restrict__ sp = it.S64 + p * N;  // uniform: scalar loads
-#pragma unroll
-    for (int k = 0; k < N; ++k) L.e[k] = act ? (float)(it.d[u * N + k] - sp[k]) : 0.0f;
-    L.p_own = act ? p : -1;
-    L.best = __builtin_inff();
-    L.qbest = 0xffffffffu;
-    L.cp = 0.0f;
-    L.have_cp = false;
-    const float *__restrict__ trow = it.T + (int64_t)pt * it.G * NR;
-
-    record_to_lds<REC, THREADS>(R32 + qb * REC, buf0, tid);
-    trow_to_lds<NS>(trow + qb * NR, tb0 + 16 * wv, lane);
-    wait_record_loads();
-    __syncthreads();
-    int64_t q = qb;
-    for (; q + 1 < qe; q += 2) {
-        fp32_fast_point<N>(q, true, R32, trow, buf0, buf1, tb0, tb1, wv, L);
-        fp32_fast_point<N>(q + 1, q + 2 < qe, R32, trow, buf1, buf0, tb1, tb0, wv, L);
-    }
-    if (q < qe) fp32_fast_point<N>(q, false, R32, trow, buf0, buf1, tb0, tb1, wv, L);
-
-    if (act) {
-        if (L.have_cp) it.chi2_p[u] = (double)L.cp;
-        if (L.best < __builtin_inff()) {
-            const unsigned long long key =
-                ((unsigned long long)__float_as_uint(L.best) << 32) | (unsigned long long)L.qbest;
-            atomicMin(&it.keys[u], key);
-        }
-    }
-}
-
-// One work item (a tile of 256 universes x a range of grid points).  With an
-// offset table, a wave whose active universes share one segment (and a valid
-// true point) takes the offset form, any other wave the residual form; both
-// walk the same grid points with the same copies and barriers.
-template <int N>
-__device__ __forceinline__ void fp32_item(const ScanItem &it, uint4 *buf0, uint4 *buf1, float4 *tb0,
-                                          float4 *tb1)
-{
-    if (it.qb >= it.qe) return;  // uniform per block
-    if (it.T != nullptr) {
-        const int64_t u = it.u0 + threadIdx.x;
-        const bool act = u < it.K;
-        const int32_t pt = act ? it.pt_idx[u] : -1;
-        const int64_t p = act ? it.p_idx[u] : -1;
-        const int32_t pt0 = __builtin_amdgcn_readfirstlane(pt);
-        const int64_t p0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(p >> 32)) << 32) |
-                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)p));
-        const bool mixed = act && (pt != pt0 || p != p0);
-        if (pt0 >= 0 && p0 >= 0 && p0 < it.G && __ballot(mixed) == 0) {
-            fp32_run_fast<N>(it, buf0, buf1, tb0, tb1, pt0, p0);
-            return;
-        }
-    }
-    fp32_run_slow<N>(it, buf0, buf1);
-}
-
-template <int N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32(
     const uint4 *__restrict__ R32, const double *__restrict__ d,
     const int64_t *__restrict__ p_idx, int64_t K, int64_t G, int64_t n_utiles,
-    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p,
-    const float *__restrict__ T, const int32_t *__restrict__ pt_idx,
-    const double *__restrict__ S64)
+    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
 {
     __shared__ uint4 buf0[rec_units(n_ksteps(N))], buf1[rec_units(n_ksteps(N))];
-    __shared__ float4 tb0[16 * kWavesPerBlock], tb1[16 * kWavesPerBlock];
     ScanItem it;
     it.R = R32;
     it.d = d;
@@ -492,16 +418,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     it.K = K;
     it.N = N;
     it.ed = 0;
-    it.T = T;
-    it.pt_idx = pt_idx;
-    it.S64 = S64;
-    it.G = G;
     const int64_t utile = blockIdx.x % n_utiles;
     const int64_t qchunk = blockIdx.x / n_utiles;
     it.u0 = utile * (int64_t)kFp32UnivPerBlock;
     it.qb = qchunk * q_per_chunk;
     it.qe = (it.qb + q_per_chunk < G) ? it.qb + q_per_chunk : G;
-    fp32_item<N>(it, buf0, buf1, tb0, tb1);
+    fp32_item<N>(it, buf0, buf1);
 }
 
 // Serving: a persistent-style launch over a table of items (any mix of
@@ -513,7 +435,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const ScanItem *__restrict__ items, int n_items, int *__restrict__ counter)
 {
     __shared__ uint4 buf0[rec_units(n_ksteps(N))], buf1[rec_units(n_ksteps(N))];
-    __shared__ float4 tb0[16 * kWavesPerBlock], tb1[16 * kWavesPerBlock];
     __shared__ int cur;
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
@@ -521,8 +442,88 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int i = cur;
         __syncthreads();
         if (i >= n_items) break;
-        fp32_item<N>(items[i], buf0, buf1, tb0, tb1);
+        fp32_item<N>(items[i], buf0, buf1);
         __syncthreads();
+    }
+}
+
+// Scan of universes grouped by true point, offset form throughout.  Tiles
+// never straddle segments: segment s owns the tile ids
+//     [start_s, start_s + ceil(len_s / 256)),   start_s = floor(seg_off[s] / 256) + s,
+// which are disjoint across segments (start_{s+1} >= start_s + ceil(len_s / 256))
+// and all below floor(K / 256) + n_pts + 1; ids in the gaps and segments whose
+// true point is outside the grid do nothing.  Each block scans one tile (its
+// 4 waves share the true point, so one offset-table row per grid point serves
+// them all) over a range of grid points.
+__device__ __forceinline__ int64_t tile_start(const int64_t *__restrict__ seg_off, int64_t s)
+{
+    return seg_off[s] / 256 + s;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32_pts(
+    const uint4 *__restrict__ R32, const double *__restrict__ S64, const double *__restrict__ d,
+    int64_t G, int64_t n_pts, const int64_t *__restrict__ p, const int64_t *__restrict__ seg_off,
+    const float *__restrict__ T, int64_t n_tiles, int64_t q_per_chunk,
+    unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
+{
+    constexpr int NS = n_ksteps(N);
+    constexpr int REC = rec_units(NS);
+    constexpr int NR = 4 * NS;
+    constexpr int THREADS = 64 * kWavesPerBlock;
+    __shared__ uint4 buf0[REC], buf1[REC];
+    __shared__ float4 tb0[16], tb1[16];
+    const int64_t tile = blockIdx.x % n_tiles;
+    const int64_t qb = (blockIdx.x / n_tiles) * q_per_chunk;
+    const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
+    // the tile's segment: the largest s with start_s <= tile (uniform)
+    int64_t lo = 0, hi = n_pts - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (tile_start(seg_off, mid) <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int64_t seg = lo;
+    const int64_t i = tile - tile_start(seg_off, seg);
+    const int64_t s0 = seg_off[seg], s1 = seg_off[seg + 1];
+    const int64_t pp = p[seg];
+    if (qb >= qe || 256 * i >= s1 - s0 || pp < 0 || pp >= G) return;  // uniform per block
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int64_t u = s0 + 256 * i + tid;
+    const bool act = u < s1;
+
+    Fp32Fast<N> L;
+    const double *__restrict__ sp = S64 + pp * N;  // uniform: scalar loads
+#pragma unroll
+    for (int k = 0; k < N; ++k) L.e[k] = act ? (float)(d[u * N + k] - sp[k]) : 0.0f;
+    L.p_own = act ? pp : -1;
+    L.best = __builtin_inff();
+    L.qbest = 0xffffffffu;
+    L.cp = 0.0f;
+    L.have_cp = false;
+    const float *__restrict__ trow = T + seg * G * NR;
+
+    record_to_lds<REC, THREADS>(R32 + qb * REC, buf0, tid);
+    if (tid < 64) trow_to_lds<NS>(trow + qb * NR, tb0, lane);
+    wait_record_loads();
+    __syncthreads();
+    int64_t q = qb;
+    for (; q + 1 < qe; q += 2) {
+        fp32_fast_point<N>(q, true, R32, trow, buf0, buf1, tb0, tb1, L);
+        fp32_fast_point<N>(q + 1, q + 2 < qe, R32, trow, buf1, buf0, tb1, tb0, L);
+    }
+    if (q < qe) fp32_fast_point<N>(q, false, R32, trow, buf0, buf1, tb0, tb1, L);
+
+    if (act) {
+        if (L.have_cp) chi2_p[u] = (double)L.cp;
+        if (L.best < __builtin_inff()) {
+            const unsigned long long key =
+                ((unsigned long long)__float_as_uint(L.best) << 32) | (unsigned long long)L.qbest;
+            atomicMin(&keys[u], key);
+        }
     }
 }
 
@@ -656,8 +657,7 @@ ScanGeometry scan_geometry(int64_t K, int64_t G, int slots, int univ_per_block)
 
 template <int N>
 static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                                unsigned long long *keys, double *chi2_p, const float *T,
-                                const int32_t *pt_idx, hipStream_t st)
+                                unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
     static int slots = 0;  // per instantiation; same device model for the process
     if (slots == 0)
@@ -666,8 +666,26 @@ static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, co
     const ScanGeometry sg = scan_geometry(K, g->G, slots, kFp32UnivPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     hipLaunchKernelGGL((k_scan_fp32<N>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, st,
-                       g->R32, d, p_idx, K, g->G, sg.n_utiles, sg.q_per_chunk, keys, chi2_p, T,
-                       pt_idx, g->S64);
+                       g->R32, d, p_idx, K, g->G, sg.n_utiles, sg.q_per_chunk, keys, chi2_p);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64_t *p,
+                                    const int64_t *seg_off, int64_t K, const double *d,
+                                    const float *T, unsigned long long *keys, double *chi2_p,
+                                    hipStream_t st)
+{
+    static int slots = 0;
+    if (slots == 0)
+        slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32_pts<N>),
+                               64 * kWavesPerBlock);
+    const int64_t n_tiles = K / 256 + n_pts + 1;  // bound on the tile ids
+    const ScanGeometry sg = scan_geometry(n_tiles * 256, g->G, slots, 256);
+    const int64_t blocks = n_tiles * sg.n_qchunks;
+    hipLaunchKernelGGL((k_scan_fp32_pts<N>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
+                       st, g->R32, g->S64, d, g->G, n_pts, p, seg_off, T, n_tiles, sg.q_per_chunk,
+                       keys, chi2_p);
     return hipGetLastError();
 }
 
@@ -676,8 +694,9 @@ static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, co
 // arithmetic on the FP32 factor as the scan uses it (padded rows r' < 4 ns),
 // rounded once to FP32; rows of an out-of-range p are zero (such segments take
 // the residual form).  One block per grid point (grid-stride): the record's A
-// slices are expanded into a dense padded W' in LDS, and each thread computes
-// the 4 ns rows of one segment.
+// slices are expanded into the transposed dense factor W'^T in LDS (zero above
+// the diagonal), and each thread accumulates all 4 ns rows of one segment,
+// bin by bin, from float4 columns of W'^T.
 template <int N>
 __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ R32,
                                                       const double *__restrict__ S64, int64_t G,
@@ -686,8 +705,7 @@ __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ 
 {
     constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N), NR = 4 * NS;
     constexpr int REC = rec_units(NS), NP = fp32_npairs(NS), NG = n_groups_from_ns(NS);
-    constexpr int WS = NR + 1;  // LDS row stride (floats)
-    __shared__ float W[NR * WS];
+    __shared__ float4 Wt[NR * NS];  // Wt[k'][b] = W'[4b .. 4b+3][k']
     __shared__ double Sq[NR];
     __shared__ unsigned char pk[NP], pb[NP];
     const int tid = threadIdx.x;
@@ -700,8 +718,9 @@ __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ 
             }
     }
     __syncthreads();
+    float *wt = reinterpret_cast<float *>(Wt);
     for (int64_t q = blockIdx.x; q < G; q += gridDim.x) {
-        for (int i = tid; i < NR * WS; i += blockDim.x) W[i] = 0.0f;
+        for (int i = tid; i < NR * NR; i += blockDim.x) wt[i] = 0.0f;
         for (int i = tid; i < NR; i += blockDim.x) Sq[i] = (i >= P) ? S64[q * N + (i - P)] : 0.0;
         __syncthreads();
         const float *rec = reinterpret_cast<const float *>(R32 + q * REC);
@@ -709,7 +728,7 @@ __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ 
         for (int f = tid; f < NG * 256; f += blockDim.x) {
             const int v = 4 * (f / 256) + (f & 3), ln = (f >> 2) & 63;
             const int t = 16 * v + (ln >> 2);
-            if (t < NP) W[(4 * pb[t] + (ln & 3)) * WS + pk[t]] = rec[f];
+            if (t < NP) wt[pk[t] * NR + 4 * pb[t] + (ln & 3)] = rec[f];
         }
         __syncthreads();
         for (int64_t pt = tid; pt < n_pts; pt += blockDim.x) {
@@ -718,12 +737,17 @@ __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ 
 #pragma unroll
             for (int r = 0; r < NR; ++r) acc[r] = 0.0;
             if (pp >= 0 && pp < G) {
-                const double *sp = S64 + pp * N;
-#pragma unroll
+                const double *sp = S64 + pp * N - P;
                 for (int kp = P; kp < NR; ++kp) {
-                    const double dk = sp[kp - P] - Sq[kp];
+                    const double dk = sp[kp] - Sq[kp];
 #pragma unroll
-                    for (int r = kp; r < NR; ++r) acc[r] = fma((double)W[r * WS + kp], dk, acc[r]);
+                    for (int b = 0; b < NS; ++b) {
+                        const float4 w = Wt[kp * NS + b];
+                        acc[4 * b] = fma((double)w.x, dk, acc[4 * b]);
+                        acc[4 * b + 1] = fma((double)w.y, dk, acc[4 * b + 1]);
+                        acc[4 * b + 2] = fma((double)w.z, dk, acc[4 * b + 2]);
+                        acc[4 * b + 3] = fma((double)w.w, dk, acc[4 * b + 3]);
+                    }
                 }
             }
             float4 *dst = reinterpret_cast<float4 *>(T + (pt * G + q) * NR);
@@ -736,13 +760,12 @@ __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ 
     }
 }
 
-// Segment expansion: universe u of segment pt = max{k : seg_off[k] <= u}
-// gets p_idx[u] = p[pt] and pt_idx[u] = pt.
+// Segment expansion: universe u of segment s = max{k : seg_off[k] <= u} gets
+// p_idx[u] = p[s].
 __global__ __launch_bounds__(256) void k_expand_segments(int64_t K, int64_t n_pts,
                                                          const int64_t *__restrict__ seg_off,
                                                          const int64_t *__restrict__ p,
-                                                         int64_t *__restrict__ p_idx,
-                                                         int32_t *__restrict__ pt_idx)
+                                                         int64_t *__restrict__ p_idx)
 {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < K;
          u += (int64_t)gridDim.x * blockDim.x) {
@@ -755,7 +778,6 @@ __global__ __launch_bounds__(256) void k_expand_segments(int64_t K, int64_t n_pt
                 hi = mid - 1;
         }
         p_idx[u] = p[lo];
-        pt_idx[u] = (int32_t)lo;
     }
 }
 
@@ -822,12 +844,25 @@ int serve_slots_fp32(int N)
 }
 
 hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                            unsigned long long *keys, double *chi2_p, hipStream_t st,
-                            const float *T, const int32_t *pt_idx)
+                            unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
     switch (g->N) {
 #define FC_CASE(n) \
-    case n: return launch_fp32_n<n>(g, K, d, p_idx, keys, chi2_p, T, pt_idx, st);
+    case n: return launch_fp32_n<n>(g, K, d, p_idx, keys, chi2_p, st);
+        FC_EACH_N(FC_CASE)
+#undef FC_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_scan_fp32_points(const fc_grid *g, int64_t n_pts, const int64_t *p,
+                                   const int64_t *seg_off, int64_t K, const double *d,
+                                   const float *T, unsigned long long *keys, double *chi2_p,
+                                   hipStream_t st)
+{
+    switch (g->N) {
+#define FC_CASE(n) \
+    case n: return launch_fp32_pts_n<n>(g, n_pts, p, seg_off, K, d, T, keys, chi2_p, st);
         FC_EACH_N(FC_CASE)
 #undef FC_CASE
     default: return hipErrorInvalidValue;
@@ -847,12 +882,12 @@ hipError_t launch_offset_table(const fc_grid *g, int64_t n_pts, const int64_t *p
 }
 
 hipError_t launch_expand_segments(int64_t K, int64_t n_pts, const int64_t *seg_off,
-                                  const int64_t *p, int64_t *p_idx, int32_t *pt_idx, hipStream_t st)
+                                  const int64_t *p, int64_t *p_idx, hipStream_t st)
 {
     int64_t blocks = (K + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_expand_segments, dim3((unsigned)blocks), dim3(256), 0, st, K, n_pts, seg_off,
-                       p, p_idx, pt_idx);
+                       p, p_idx);
     return hipGetLastError();
 }
 #undef FC_EACH_N

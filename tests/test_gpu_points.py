@@ -2,8 +2,8 @@
 
 The FP32 form's offset path (d - S_p once, W_q (S_p - S_q) from a table) is
 checked against the FP64 oracle; the other forms must equal fc_scan on the
-expanded per-universe true points bit for bit.  Segments are ragged so that
-some waves straddle two true points (residual path) and others do not.
+expanded per-universe true points bit for bit.  Segments are ragged (empty,
+single-universe, tile-sized and longer ones), so tiles end short of 256.
 """
 from __future__ import annotations
 
@@ -99,7 +99,7 @@ def test_points_other_forms_equal_fc_scan(fc, form_name):
 @pytest.mark.parametrize("N", list(range(1, 65)))
 def test_points_fp32_every_bin_count(fc, N):
     """The offset path is compiled per bin count like the residual path: every
-    N, with one wave straddling the two segments."""
+    N, with two segments whose tiles end short of 256 universes."""
     rng = np.random.default_rng(2000 + N)
     G, sizes = 23, np.array([200, 100])
     S = rng.uniform(20, 800, size=(G, N))
@@ -125,7 +125,7 @@ def test_points_fp32_every_bin_count(fc, N):
 def test_points_unfluctuated_and_bad_points(fc):
     """d = S_p exactly: the offset path gives Delta chi2 = 0 and chi2_min = 0
     exactly (e = 0 and the table row at q = p is W (S_p - S_p) = 0); a
-    segment whose true point is outside the grid gets NaN as in fc_scan."""
+    segment whose true point is outside the grid gets NaN."""
     pr = fcgen.make_problem("c1", K=1, true_subset=[0])
     ps = np.array([0, 17, 382, 399, 200])
     sizes = np.array([64, 64, 64, 64, 64])
@@ -149,7 +149,7 @@ def test_points_workspace_errors(fc):
     fc.fc_build_covariance(g, pr.F, forms=2)
     K = 100
     need = fc.fc_scan_points_workspace(g, 2, 1, K)
-    assert need >= 12 * K + pr.G * 16 * 10          # universes + table (N = 38: ns = 10)
+    assert need >= 8 * K + pr.G * 16 * 10           # true points + table (N = 38: ns = 10)
     p = torch.tensor([5], dtype=torch.int64, device="cuda")
     seg = torch.tensor([0, K], dtype=torch.int64, device="cuda")
     d = torch.as_tensor(pr.S[[5] * K]).cuda()
