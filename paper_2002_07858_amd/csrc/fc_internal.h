@@ -47,6 +47,8 @@ namespace fcx {
 constexpr int kMaxBins = FC_MAX_BINS;
 constexpr int kWavesPerBlock = 4;
 constexpr int kFp32UnivPerBlock = 64 * kWavesPerBlock;  // one universe per lane
+constexpr int kPtsWaves = 4;                 // waves per block of the points scan
+constexpr int kPtsTile = 64 * kPtsWaves;     // its universes per tile
 
 __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int n_ksteps(int N) { return ceil_div(N, 4); }

@@ -370,7 +370,7 @@ __device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint
     constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N);
     constexpr int REC = rec_units(NS);
     constexpr int NR = 4 * NS;
-    constexpr int THREADS = 64 * kWavesPerBlock;
+    constexpr int THREADS = kPtsTile;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
 
@@ -392,9 +392,6 @@ __device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint
     fp32_fast_pairs<N>(acc, a_cur, a_nxt, L, wl, lane,
                        std::make_integer_sequence<int, fp32_npairs(NS)>{});
     fp32_fold<NS, P>(acc, q, L.p_own, L.best, L.qbest, L.cp, L.have_cp);
-    // the sums of squares stay with their grid point (one set of accumulators
-    // live at a time)
-    __builtin_amdgcn_sched_barrier(0);
 
     if (more) wait_record_loads();
     __syncthreads();
@@ -447,21 +444,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 }
 
-// Scan of universes grouped by true point, offset form throughout.  Tiles
-// never straddle segments: segment s owns the tile ids
-//     [start_s, start_s + ceil(len_s / 256)),   start_s = floor(seg_off[s] / 256) + s,
-// which are disjoint across segments (start_{s+1} >= start_s + ceil(len_s / 256))
-// and all below floor(K / 256) + n_pts + 1; ids in the gaps and segments whose
+// Scan of universes grouped by true point, offset form throughout.  Tiles of
+// B = kPtsTile universes never straddle segments: segment s owns the tile ids
+//     [start_s, start_s + ceil(len_s / B)),   start_s = floor(seg_off[s] / B) + s,
+// which are disjoint across segments (start_{s+1} >= start_s + ceil(len_s / B))
+// and all below floor(K / B) + n_pts + 1; ids in the gaps and segments whose
 // true point is outside the grid do nothing.  Each block scans one tile (its
-// 4 waves share the true point, so one offset-table row per grid point serves
+// waves share the true point, so one offset-table row per grid point serves
 // them all) over a range of grid points.
 __device__ __forceinline__ int64_t tile_start(const int64_t *__restrict__ seg_off, int64_t s)
 {
-    return seg_off[s] / 256 + s;
+    return seg_off[s] / kPtsTile + s;
 }
 
 template <int N>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32_pts(
+__global__ __launch_bounds__(kPtsTile) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32_pts(
     const uint4 *__restrict__ R32, const double *__restrict__ S64, const double *__restrict__ d,
     int64_t G, int64_t n_pts, const int64_t *__restrict__ p, const int64_t *__restrict__ seg_off,
     const float *__restrict__ T, int64_t n_tiles, int64_t q_per_chunk,
@@ -470,7 +467,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     constexpr int NS = n_ksteps(N);
     constexpr int REC = rec_units(NS);
     constexpr int NR = 4 * NS;
-    constexpr int THREADS = 64 * kWavesPerBlock;
+    constexpr int THREADS = kPtsTile;
     __shared__ uint4 buf0[REC], buf1[REC];
     __shared__ float4 tb0[16], tb1[16];
     const int64_t tile = blockIdx.x % n_tiles;
@@ -489,10 +486,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int64_t i = tile - tile_start(seg_off, seg);
     const int64_t s0 = seg_off[seg], s1 = seg_off[seg + 1];
     const int64_t pp = p[seg];
-    if (qb >= qe || 256 * i >= s1 - s0 || pp < 0 || pp >= G) return;  // uniform per block
+    if (qb >= qe || kPtsTile * i >= s1 - s0 || pp < 0 || pp >= G) return;  // uniform per block
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int64_t u = s0 + 256 * i + tid;
+    const int64_t u = s0 + kPtsTile * i + tid;
     const bool act = u < s1;
 
     Fp32Fast<N> L;
@@ -678,12 +675,11 @@ static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64
 {
     static int slots = 0;
     if (slots == 0)
-        slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32_pts<N>),
-                               64 * kWavesPerBlock);
-    const int64_t n_tiles = K / 256 + n_pts + 1;  // bound on the tile ids
-    const ScanGeometry sg = scan_geometry(n_tiles * 256, g->G, slots, 256);
+        slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32_pts<N>), kPtsTile);
+    const int64_t n_tiles = K / kPtsTile + n_pts + 1;  // bound on the tile ids
+    const ScanGeometry sg = scan_geometry(n_tiles * kPtsTile, g->G, slots, kPtsTile);
     const int64_t blocks = n_tiles * sg.n_qchunks;
-    hipLaunchKernelGGL((k_scan_fp32_pts<N>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
+    hipLaunchKernelGGL((k_scan_fp32_pts<N>), dim3((unsigned)blocks), dim3(kPtsTile), 0,
                        st, g->R32, g->S64, d, g->G, n_pts, p, seg_off, T, n_tiles, sg.q_per_chunk,
                        keys, chi2_p);
     return hipGetLastError();
