@@ -322,11 +322,13 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Workspace of fc_scan_points: p_idx [K] int64 and, for the FP32 form, the
-// offset table [n_pts][G][4 ns] FP32.
+// tile prefix [n_pts+1] int64 and the offset table [n_pts][G][4 ns] FP32.
 size_t points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K)
 {
     size_t b = align256(sizeof(int64_t) * (size_t)K);
-    if (form == FC_FORM_FP32) b += sizeof(float) * (size_t)n_pts * (size_t)g->G * 4 * (size_t)g->ns;
+    if (form == FC_FORM_FP32)
+        b += align256(sizeof(int64_t) * (size_t)(n_pts + 1)) +
+             sizeof(float) * (size_t)n_pts * (size_t)g->G * 4 * (size_t)g->ns;
     return b;
 }
 
@@ -371,7 +373,9 @@ int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t 
                     need);
     char *ws = static_cast<char *>(workspace);
     int64_t *p_idx = reinterpret_cast<int64_t *>(ws);
-    float *T = reinterpret_cast<float *>(ws + align256(sizeof(int64_t) * (size_t)K));
+    int64_t *tile_start = reinterpret_cast<int64_t *>(ws + align256(sizeof(int64_t) * (size_t)K));
+    float *T = reinterpret_cast<float *>(ws + align256(sizeof(int64_t) * (size_t)K) +
+                                         align256(sizeof(int64_t) * (size_t)(n_pts + 1)));
     hipError_t e;
     if ((e = fcx::launch_expand_segments(K, n_pts, seg_off, p, p_idx, stream)) != hipSuccess)
         return hip_fail(e, "fc_scan_points: segment expansion");
@@ -380,8 +384,8 @@ int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t 
     unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
     if ((e = fcx::launch_offset_table(g, n_pts, p, T, stream)) != hipSuccess ||
         (e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
-        (e = fcx::launch_scan_fp32_points(g, n_pts, p, seg_off, K, d, T, keys, chi2_p,
-                                          stream)) != hipSuccess ||
+        (e = fcx::launch_scan_fp32_points(g, n_pts, p, seg_off, K, d, T, tile_start, keys,
+                                          chi2_p, stream)) != hipSuccess ||
         (e = fcx::launch_finalize(K, p_idx, keys, argmin, chi2_p, dchi2, stream)) != hipSuccess)
         return hip_fail(e, "fc_scan_points: fp32 launch");
     return FC_OK;

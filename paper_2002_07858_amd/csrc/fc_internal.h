@@ -199,8 +199,8 @@ hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const 
                             unsigned long long *keys, double *chi2_p, hipStream_t st);
 hipError_t launch_scan_fp32_points(const fc_grid *g, int64_t n_pts, const int64_t *p,
                                    const int64_t *seg_off, int64_t K, const double *d,
-                                   const float *T, unsigned long long *keys, double *chi2_p,
-                                   hipStream_t st);
+                                   const float *T, int64_t *tile_start, unsigned long long *keys,
+                                   double *chi2_p, hipStream_t st);
 hipError_t launch_offset_table(const fc_grid *g, int64_t n_pts, const int64_t *p, float *T,
                                hipStream_t st);
 hipError_t launch_expand_segments(int64_t K, int64_t n_pts, const int64_t *seg_off,

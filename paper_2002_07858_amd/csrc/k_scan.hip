@@ -445,23 +445,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // Scan of universes grouped by true point, offset form throughout.  Tiles of
-// B = kPtsTile universes never straddle segments: segment s owns the tile ids
-//     [start_s, start_s + ceil(len_s / B)),   start_s = floor(seg_off[s] / B) + s,
-// which are disjoint across segments (start_{s+1} >= start_s + ceil(len_s / B))
-// and all below floor(K / B) + n_pts + 1; ids in the gaps and segments whose
-// true point is outside the grid do nothing.  Each block scans one tile (its
-// waves share the true point, so one offset-table row per grid point serves
-// them all) over a range of grid points.
-__device__ __forceinline__ int64_t tile_start(const int64_t *__restrict__ seg_off, int64_t s)
-{
-    return seg_off[s] / kPtsTile + s;
-}
-
+// B = kPtsTile universes never straddle segments: segment s owns the dense
+// tile ids [tile_start[s], tile_start[s+1]), tile_start[s+1] - tile_start[s] =
+// ceil(len_s / B) (a prefix sum built before the launch), all below
+// floor(K / B) + n_pts.  Each block scans one tile (its waves share the true
+// point, so one offset-table row per grid point serves them all) over a range
+// of grid points.  Blocks are dispatched round-robin over the 8 XCDs (block b
+// runs on XCD b mod 8), so block b = xcd + 8 (m + 8 (j + J c)) is given tile
+// 8 (xcd + 8 j) + m of grid chunk c: eight consecutive tiles (a segment's,
+// mostly) run on one XCD at the same time and share its L2 for the offset
+// rows and the records, and the XCDs get equal shares of the tiles.
+// Segments whose true point is outside the grid do nothing.
 template <int N>
 __global__ __launch_bounds__(kPtsTile) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32_pts(
     const uint4 *__restrict__ R32, const double *__restrict__ S64, const double *__restrict__ d,
     int64_t G, int64_t n_pts, const int64_t *__restrict__ p, const int64_t *__restrict__ seg_off,
-    const float *__restrict__ T, int64_t n_tiles, int64_t q_per_chunk,
+    const int64_t *__restrict__ tile_start, const float *__restrict__ T, int64_t groups_per_xcd,
+    int64_t q_per_chunk,
     unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
 {
     constexpr int NS = n_ksteps(N);
@@ -470,23 +470,28 @@ __global__ __launch_bounds__(kPtsTile) __attribute__((amdgpu_waves_per_eu(2))) v
     constexpr int THREADS = kPtsTile;
     __shared__ uint4 buf0[REC], buf1[REC];
     __shared__ float4 tb0[16], tb1[16];
-    const int64_t tile = blockIdx.x % n_tiles;
-    const int64_t qb = (blockIdx.x / n_tiles) * q_per_chunk;
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b % 8, k = b / 8;
+    const int64_t member = k % 8, rest = k / 8;
+    const int64_t group = xcd + 8 * (rest % groups_per_xcd);
+    const int64_t tile = 8 * group + member;
+    const int64_t qb = (rest / groups_per_xcd) * q_per_chunk;
     const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
-    // the tile's segment: the largest s with start_s <= tile (uniform)
+    if (tile >= tile_start[n_pts]) return;  // uniform per block
+    // the tile's segment: the largest s with tile_start[s] <= tile (uniform)
     int64_t lo = 0, hi = n_pts - 1;
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
-        if (tile_start(seg_off, mid) <= tile)
+        if (tile_start[mid] <= tile)
             lo = mid;
         else
             hi = mid - 1;
     }
     const int64_t seg = lo;
-    const int64_t i = tile - tile_start(seg_off, seg);
+    const int64_t i = tile - tile_start[seg];
     const int64_t s0 = seg_off[seg], s1 = seg_off[seg + 1];
     const int64_t pp = p[seg];
-    if (qb >= qe || kPtsTile * i >= s1 - s0 || pp < 0 || pp >= G) return;  // uniform per block
+    if (qb >= qe || pp < 0 || pp >= G) return;  // uniform per block
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int64_t u = s0 + kPtsTile * i + tid;
@@ -667,21 +672,56 @@ static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, co
     return hipGetLastError();
 }
 
+// Dense tile ids of the points scan: tile_start[0] = 0, tile_start[s+1] =
+// tile_start[s] + ceil((seg_off[s+1] - seg_off[s]) / kPtsTile).  One block;
+// segments in chunks of 1024 with a running carry.
+__global__ __launch_bounds__(1024) void k_tile_prefix(int64_t n_pts,
+                                                      const int64_t *__restrict__ seg_off,
+                                                      int64_t *__restrict__ tile_start)
+{
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    int64_t carry = 0;
+    if (tid == 0) tile_start[0] = 0;
+    for (int64_t base = 0; base < n_pts; base += 1024) {
+        const int64_t s = base + tid;
+        int64_t v = 0;
+        if (s < n_pts) {
+            const int64_t len = seg_off[s + 1] - seg_off[s];
+            v = len > 0 ? (len + kPtsTile - 1) / kPtsTile : 0;
+        }
+        part[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan (Hillis-Steele)
+            const int64_t add = tid >= off ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += add;
+            __syncthreads();
+        }
+        if (s < n_pts) tile_start[s + 1] = carry + part[tid];
+        carry += part[1023];
+        __syncthreads();
+    }
+}
+
 template <int N>
 static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64_t *p,
                                     const int64_t *seg_off, int64_t K, const double *d,
-                                    const float *T, unsigned long long *keys, double *chi2_p,
-                                    hipStream_t st)
+                                    const float *T, int64_t *tile_start, unsigned long long *keys,
+                                    double *chi2_p, hipStream_t st)
 {
     static int slots = 0;
     if (slots == 0)
         slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32_pts<N>), kPtsTile);
-    const int64_t n_tiles = K / kPtsTile + n_pts + 1;  // bound on the tile ids
-    const ScanGeometry sg = scan_geometry(n_tiles * kPtsTile, g->G, slots, kPtsTile);
+    const int64_t max_tiles = K / kPtsTile + n_pts;  // bound on the dense tile count
+    const int64_t groups_per_xcd = (max_tiles + 63) / 64;
+    const int64_t n_tiles = 64 * groups_per_xcd;    // blocks per grid chunk
+    const ScanGeometry sg = scan_geometry(max_tiles * kPtsTile, g->G, slots, kPtsTile);
     const int64_t blocks = n_tiles * sg.n_qchunks;
+    hipLaunchKernelGGL(k_tile_prefix, dim3(1), dim3(1024), 0, st, n_pts, seg_off, tile_start);
     hipLaunchKernelGGL((k_scan_fp32_pts<N>), dim3((unsigned)blocks), dim3(kPtsTile), 0,
-                       st, g->R32, g->S64, d, g->G, n_pts, p, seg_off, T, n_tiles, sg.q_per_chunk,
-                       keys, chi2_p);
+                       st, g->R32, g->S64, d, g->G, n_pts, p, seg_off, tile_start, T, groups_per_xcd,
+                       sg.q_per_chunk, keys, chi2_p);
     return hipGetLastError();
 }
 
@@ -853,12 +893,12 @@ hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const 
 
 hipError_t launch_scan_fp32_points(const fc_grid *g, int64_t n_pts, const int64_t *p,
                                    const int64_t *seg_off, int64_t K, const double *d,
-                                   const float *T, unsigned long long *keys, double *chi2_p,
-                                   hipStream_t st)
+                                   const float *T, int64_t *tile_start, unsigned long long *keys,
+                                   double *chi2_p, hipStream_t st)
 {
     switch (g->N) {
 #define FC_CASE(n) \
-    case n: return launch_fp32_pts_n<n>(g, n_pts, p, seg_off, K, d, T, keys, chi2_p, st);
+    case n: return launch_fp32_pts_n<n>(g, n_pts, p, seg_off, K, d, T, tile_start, keys, chi2_p, st);
         FC_EACH_N(FC_CASE)
 #undef FC_CASE
     default: return hipErrorInvalidValue;
