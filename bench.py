@@ -76,11 +76,18 @@ FP32_SOURCES = ("paper_2002_07858_amd/csrc/k_scan.hip", "paper_2002_07858_amd/cs
 SPLIT_SOURCES = ("paper_2002_07858_amd/csrc/k_scan_split.hip",
                  "paper_2002_07858_amd/csrc/fc_internal.h")
 TRAFFIC = {
-    ("c2", "fp32", "universes"): {"bytes_per_launch": 10770685185, "source_hash": "4fa35b95b2811a7e",
-                     "sources": FP32_SOURCES, "profile": "profiles/k_scan_fp32_c2_counters.md"},
-    ("c2", "split_fp16", "universes"): {"bytes_per_launch": 10706519139, "source_hash": "6983b2e8921d48ea",
-                           "sources": SPLIT_SOURCES, "profile": "profiles/k_scan_split_fp16_c2.md"},
+    ("c2", "fp32", "points"): {"bytes_per_launch": 7870033510, "source_hash": "11364d079d0b019d",
+                               "sources": FP32_SOURCES,
+                               "profile": "profiles/k_scan_fp32_pts_c2_counters.md"},
+    ("c2", "fp32", "universes"): {"bytes_per_launch": 11047722114, "source_hash": "11364d079d0b019d",
+                                  "sources": FP32_SOURCES,
+                                  "profile": "profiles/k_scan_fp32_pts_c2_counters.md"},
+    ("c2", "split_fp16", "universes"): {"bytes_per_launch": 10706519139,
+                                        "source_hash": "6983b2e8921d48ea", "sources": SPLIT_SOURCES,
+                                        "profile": "profiles/k_scan_split_fp16_c2.md"},
 }
+# the split forms scan through the same kernel under either entry
+TRAFFIC[("c2", "split_fp16", "points")] = TRAFFIC[("c2", "split_fp16", "universes")]
 
 
 def kernel_source_hash(sources) -> str:
@@ -492,7 +499,10 @@ def main():
     split = args.form.startswith("split")
     achieved = evals * (split_flop_per_eval(N) if split else fpe) / (scan_ms * 1e-3)
     peak = PEAK[args.form]
-    roofline = {"bound": "alu" if args.form == "fp64" else "mfma", "achieved": achieved / 1e12,
+    kernel = {"fp64": "k_scan_fp64", "fp32": "k_scan_fp32_pts" if args.scan == "points"
+              else "k_scan_fp32"}.get(args.form, "k_scan_split")
+    roofline = {"kernel": kernel, "bound": "alu" if args.form == "fp64" else "mfma",
+                "achieved": achieved / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None}
     tr = TRAFFIC.get((args.workload, args.form, args.scan))
