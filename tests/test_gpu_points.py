@@ -186,3 +186,50 @@ def test_points_full_size_c2_sampled(fc):
     ref = oracle.scan(pr.S, pr.F, pr.d[rows], pr.p_idx[rows])
     rep = parity.report({k: v[rows] for k, v in dev.items()}, ref, parity.TOL["fp32"])
     assert rep["e_rel"] <= parity.TOL["fp32"], rep
+
+
+def test_points_many_segments_and_long_ones(fc):
+    """2500 segments (the tile prefix sum runs over three 1024-segment chunks),
+    most of them tiny, some empty, and two long ones of 20 and 9 tiles (more
+    than the eight tiles that share an XCD)."""
+    pr = fcgen.make_problem("c1", K=1, true_subset=[0], n_axis=(12, 12))
+    rng = np.random.default_rng(11)
+    sizes = rng.integers(0, 4, 2500)
+    sizes[100] = 5000
+    sizes[2400] = 2100
+    p = rng.integers(0, pr.G, sizes.size)
+    seg = np.concatenate([[0], np.cumsum(sizes)])
+    p_idx = np.repeat(p, sizes)
+    K = int(seg[-1])
+    d = pr.S[p_idx] + rng.normal(0, 1, size=(K, pr.N)) * np.sqrt(pr.S[p_idx])
+    g = fc.fc_build_grid(pr.axes, pr.S)
+    fc.fc_build_covariance(g, pr.F, forms=2)
+    dev = run_points(fc, g, 2, p, seg, d)
+    g.destroy()
+    parity.check_invariants(dev, pr.G)
+    ref = oracle.scan(pr.S, pr.F, d, p_idx)
+    rep = parity.report(dev, ref, parity.TOL["fp32"])
+    assert rep["e_rel"] <= parity.TOL["fp32"], rep
+    assert rep["argmin_agree"] == 1.0, rep
+
+
+def test_points_empty_inputs(fc):
+    """K = 0 enqueues nothing; all-empty segments likewise; n_pts = 0 with
+    universes is an argument error."""
+    pr = fcgen.make_problem("c1", K=1, true_subset=[0])
+    g = fc.fc_build_grid(pr.axes, pr.S)
+    fc.fc_build_covariance(g, pr.F, forms=2)
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    ei = torch.empty(0, dtype=torch.int64, device="cuda")
+    d0 = torch.empty((0, pr.N), dtype=torch.float64, device="cuda")
+    fc.fc_scan_points(g, 2, torch.tensor([3, 4], dtype=torch.int64, device="cuda"),
+                      torch.zeros(3, dtype=torch.int64, device="cuda"), d0, e, e, ei, e)
+    o = outputs(5)
+    with pytest.raises(fc.FCError) as ei_:
+        fc.fc_scan_points(g, 2, torch.empty(0, dtype=torch.int64, device="cuda"),
+                          torch.zeros(1, dtype=torch.int64, device="cuda"),
+                          torch.as_tensor(pr.S[[3] * 5]).cuda(), o["dchi2"], o["chi2_min"],
+                          o["argmin"], o["chi2_p"])
+    assert ei_.value.code == fc.FC_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    g.destroy()
