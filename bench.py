@@ -369,6 +369,55 @@ def region_bench(pr, form_name: str, K0=256, K_max=4096, z=2.0):
             "region_points": [int(x) for x in acc.sum(dim=0).cpu().tolist()]}
 
 
+# ---------------------------------------------------------------------------
+# Grid sharding on one device: the grid cut into equal slices, each scanned by
+# its own call (one device's share of a grid-sharded job, at its real shape),
+# merged through one shared (key, chi2_p) state, checked bit for bit against
+# the one-call scan's outputs.
+# ---------------------------------------------------------------------------
+def shard_bench(fc, grid, form, form_name, scan_entry, pr, d_t, p_t, pts_t, so_t, ref, n_shards):
+    import torch
+    K, G = pr.K, pr.G
+    edges = [G * i // n_shards for i in range(n_shards + 1)]
+    nq_max = max(b - a for a, b in zip(edges[:-1], edges[1:]))
+    ws = None
+    if scan_entry == "points":
+        ws = torch.empty(fc.fc_scan_points_slice_workspace(grid, form, int(so_t.numel()) - 1, K,
+                                                           nq_max),
+                         dtype=torch.uint8, device="cuda")
+    keys = torch.empty(K, dtype=torch.int64, device="cuda")
+    chi2_p = torch.empty(K, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_shards + 1)]
+    for _ in range(2):  # an untimed pass over the slices, then the timed one
+        fc.fc_scan_state_init(keys, chi2_p)
+        evs[0].record(stream)
+        for i, (a, b) in enumerate(zip(edges[:-1], edges[1:])):
+            if scan_entry == "points":
+                fc.fc_scan_points_slice(grid, form, pts_t, so_t, d_t, a, b - a, keys, chi2_p,
+                                        workspace=ws)
+            else:
+                fc.fc_scan_slice(grid, form, d_t, p_t, a, b - a, keys, chi2_p)
+            evs[i + 1].record(stream)
+    o = {k: torch.empty(K, dtype=torch.float64, device="cuda") for k in ("dchi2", "chi2_min")}
+    o["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
+    fc.fc_scan_state_finalize(grid, p_t, keys, chi2_p, o["dchi2"], o["chi2_min"], o["argmin"])
+    torch.cuda.synchronize()
+    ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(n_shards)]
+    mid = float(np.median(ms))
+    equal = all(bool(torch.equal(o[k], ref[k])) for k in o) and bool(torch.equal(chi2_p,
+                                                                                  ref["chi2_p"]))
+    slice_evals = [float(K) * (b - a) for a, b in zip(edges[:-1], edges[1:])]
+    flops = slice_evals[0] * (split_flop_per_eval(pr.N) if form_name.startswith("split")
+                              else flop_per_eval(pr.N))
+    return {"shards": n_shards, "grid_points_per_shard": edges[1] - edges[0],
+            "universes": K, "scan_entry": scan_entry, "slice_ms": ms,
+            "slice_evals_per_s": slice_evals[0] / (mid * 1e-3),
+            "slice_roofline_frac": flops / (mid * 1e-3) / PEAK[form_name],
+            "sum_ms": float(sum(ms)),
+            "merged_equals_one_call": equal}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -389,6 +438,9 @@ def main():
                     help="1: also run the one-matrix scan leg (default on for c2)")
     ap.add_argument("--region", type=int, default=None,
                     help="1: also run the full-surface region leg (default on for c2)")
+    ap.add_argument("--shards", type=int, default=8,
+                    help="grid-sharding leg: slices of the grid scanned by separate calls "
+                         "(0: off; not for the fp64 form)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (counter calibration)")
     ap.add_argument("--serving-loads", default="0.5,0.8",
@@ -537,6 +589,10 @@ def main():
         base, rep = cpu_baseline(pr, args.cpu_per_point, dev_out, TOL[args.form])
         res["cpu_baseline"] = base
         res["err_vs_fp64"] = rep
+    if args.shards > 0 and args.form != "fp64":
+        log(f"[bench] grid sharding leg ({args.shards} slices)")
+        res["grid_shard"] = shard_bench(fc, grid, form, args.form, args.scan, pr, d_t, p_t, pts_t,
+                                        so_t, outs, args.shards)
     grid.destroy()
     if args.fixed:
         log("[bench] one-matrix scan")

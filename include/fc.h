@@ -214,6 +214,76 @@ int fc_scan_points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int6
                              size_t *bytes);
 
 /*
+ * Grid-sliced scans: Algorithm 1's loop over the grid cut into slices
+ * [q0, q0 + nq) that run as separate calls -- one device's share when a grid
+ * is sharded over devices, or pieces of a scan that should not hold the GPU
+ * for its whole length.  Each universe carries a running state:
+ *   keys[k]   uint64: (FP32 bit pattern of the smallest chi2 seen << 32) | its q,
+ *             or the "none" value 0x7f800000ffffffff; chi2 >= 0, so the
+ *             unsigned order of keys is the order of (chi2, q), and the minimum
+ *             key is the strict-"<" running minimum of Algorithm 1 in list
+ *             order (lowest q among exact ties)
+ *   chi2_p[k] FP64: chi2(d[k], p[k]), written only by the slice that contains
+ *             p[k]; 0 until then
+ * Slices merge by a 64-bit unsigned MIN over keys and a SUM over chi2_p (every
+ * universe's true point lies in exactly one slice), in any order and
+ * grouping: slices that cover [0, G) once give, after fc_scan_state_finalize,
+ * exactly the result of the one-call scan in the same form (FP32 and the
+ * split forms; the FP64 form keeps FP64 minima and is not sliced:
+ * FC_ERR_UNSUPPORTED).  Calls on one device may share one state (their
+ * updates are atomic); calls on several devices keep their own states, merged
+ * by those two reductions (an all-reduce MIN and SUM) before finalizing.
+ */
+
+/* fc_scan_state_init -- keys = none, chi2_p = 0 for K universes (device
+ * arrays [K], caller-owned; 0 <= K <= 2^30).  Asynchronous. */
+int fc_scan_state_init(int64_t K, uint64_t *keys, double *chi2_p, hipStream_t stream);
+
+/*
+ * fc_scan_slice -- fc_scan over the grid points [q0, q0 + nq) only, merged
+ * into the state (keys, chi2_p).  Arguments as fc_scan; 0 <= q0, 0 <= nq,
+ * q0 + nq <= G (else FC_ERR_INVALID_ARG); nq = 0 or K = 0 enqueue nothing.
+ * form: FC_FORM_FP32 (the residual form of fc_scan) or a split form.
+ * Asynchronous.
+ */
+int fc_scan_slice(const fc_grid *g, int32_t form, int64_t K, const double *d,
+                  const int64_t *p_idx, int64_t q0, int64_t nq, uint64_t *keys, double *chi2_p,
+                  hipStream_t stream);
+
+/*
+ * fc_scan_points_slice -- fc_scan_points over the grid points [q0, q0 + nq)
+ * only, merged into the state (keys, chi2_p).  The FP32 form builds the
+ * offset table for the slice's grid points; a segment whose point is outside
+ * [0, G) is not scanned.  workspace: at least
+ * fc_scan_points_slice_workspace(..., nq) bytes, 256-byte aligned.
+ * Asynchronous.
+ */
+int fc_scan_points_slice(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t *p,
+                         const int64_t *seg_off, int64_t K, const double *d, int64_t q0,
+                         int64_t nq, void *workspace, size_t workspace_bytes, uint64_t *keys,
+                         double *chi2_p, hipStream_t stream);
+
+/* fc_scan_points_slice_workspace -- as fc_scan_points_workspace with the
+ * offset table sized for nq grid points (0 <= nq <= G): 8 K (+ alignment) and,
+ * for the FP32 form, 16 ns n_pts nq bytes. */
+int fc_scan_points_slice_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K,
+                                   int64_t nq, size_t *bytes);
+
+/*
+ * fc_scan_state_finalize -- the outputs of fc_scan from a merged state:
+ * chi2_min[k] = the FP32 chi2 of keys[k] (+inf for none), argmin[k] = its q
+ * (p_idx[k] for none), dchi2[k] = chi2_p[k] - chi2_min[k], NaN for none and
+ * for a true point p_idx[k] outside [0, G) (whose chi2_p no slice writes).
+ *   p_idx    device [K] int64, required (the universes' true points)
+ *   keys, chi2_p   device [K] merged state (read only)
+ *   dchi2, chi2_min   device out [K] FP64; argmin device out [K] int64
+ * Asynchronous.
+ */
+int fc_scan_state_finalize(const fc_grid *g, int64_t K, const int64_t *p_idx,
+                           const uint64_t *keys, const double *chi2_p, double *dchi2,
+                           double *chi2_min, int64_t *argmin, hipStream_t stream);
+
+/*
  * fc_scan_fixed_m -- Algorithm 1 as printed: one matrix M for the whole grid
  * scan of a universe, and its iteration (Section 2, step 5: update M at the
  * minimiser and scan again until the minimiser repeats).  Per universe k,

@@ -298,8 +298,9 @@ int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d, const in
     if (form == FC_FORM_FP32) {
         unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
         if ((e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
-            (e = fcx::launch_scan_fp32(g, K, d, p_idx, keys, chi2_p, stream)) != hipSuccess ||
-            (e = fcx::launch_finalize(K, p_idx, keys, argmin, chi2_p, dchi2, stream)) !=
+            (e = fcx::launch_scan_fp32(g, K, d, p_idx, 0, g->G, keys, chi2_p, stream)) !=
+                hipSuccess ||
+            (e = fcx::launch_finalize(K, p_idx, keys, chi2_min, argmin, chi2_p, dchi2, stream)) !=
                 hipSuccess)
             return hip_fail(e, "fc_scan: fp32 launch");
         return FC_OK;
@@ -307,9 +308,9 @@ int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d, const in
     if (form == FC_FORM_SPLIT_BF16 || form == FC_FORM_SPLIT_FP16) {
         unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
         if ((e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
-            (e = fcx::launch_scan_split(g, form == FC_FORM_SPLIT_FP16, K, d, p_idx, keys, chi2_p,
-                                        stream)) != hipSuccess ||
-            (e = fcx::launch_finalize(K, p_idx, keys, argmin, chi2_p, dchi2, stream)) !=
+            (e = fcx::launch_scan_split(g, form == FC_FORM_SPLIT_FP16, K, d, p_idx, 0, g->G, keys,
+                                        chi2_p, stream)) != hipSuccess ||
+            (e = fcx::launch_finalize(K, p_idx, keys, chi2_min, argmin, chi2_p, dchi2, stream)) !=
                 hipSuccess)
             return hip_fail(e, "fc_scan: split launch");
         return FC_OK;
@@ -321,15 +322,33 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Workspace of fc_scan_points: p_idx [K] int64 and, for the FP32 form, the
-// tile prefix [n_pts+1] int64 and the offset table [n_pts][G][4 ns] FP32.
-size_t points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K)
+// Workspace of a points scan over nq grid points: p_idx [K] int64 and, for
+// the FP32 form, the tile prefix [n_pts+1] int64 and the offset table
+// [n_pts][nq][4 ns] FP32.
+size_t points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K, int64_t nq)
 {
     size_t b = align256(sizeof(int64_t) * (size_t)K);
     if (form == FC_FORM_FP32)
         b += align256(sizeof(int64_t) * (size_t)(n_pts + 1)) +
-             sizeof(float) * (size_t)n_pts * (size_t)g->G * 4 * (size_t)g->ns;
+             sizeof(float) * (size_t)n_pts * (size_t)nq * 4 * (size_t)g->ns;
     return b;
+}
+
+struct PointsWs {
+    int64_t *p_idx;
+    int64_t *tile_start;
+    float *T;
+};
+
+PointsWs carve_points_ws(void *workspace, int64_t n_pts, int64_t K)
+{
+    char *ws = static_cast<char *>(workspace);
+    PointsWs w;
+    w.p_idx = reinterpret_cast<int64_t *>(ws);
+    w.tile_start = reinterpret_cast<int64_t *>(ws + align256(sizeof(int64_t) * (size_t)K));
+    w.T = reinterpret_cast<float *>(ws + align256(sizeof(int64_t) * (size_t)K) +
+                                    align256(sizeof(int64_t) * (size_t)(n_pts + 1)));
+    return w;
 }
 
 }  // namespace
@@ -341,7 +360,7 @@ int fc_scan_points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int6
     if (!g || !bytes) return fail(FC_ERR_INVALID_ARG, "fc_scan_points_workspace: NULL argument");
     if (n_pts < 0 || K < 0 || n_pts > 0x7fffffff)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points_workspace: bad n_pts or K");
-    *bytes = points_workspace(g, form, n_pts, K);
+    *bytes = points_workspace(g, form, n_pts, K, g->G);
     return FC_OK;
 }
 
@@ -367,27 +386,153 @@ int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t 
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points: NULL device pointer");
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points: workspace not 256-byte aligned");
-    const size_t need = points_workspace(g, form, n_pts, K);
+    const size_t need = points_workspace(g, form, n_pts, K, g->G);
     if (workspace_bytes < need)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points: workspace %zu B < %zu B", workspace_bytes,
                     need);
-    char *ws = static_cast<char *>(workspace);
-    int64_t *p_idx = reinterpret_cast<int64_t *>(ws);
-    int64_t *tile_start = reinterpret_cast<int64_t *>(ws + align256(sizeof(int64_t) * (size_t)K));
-    float *T = reinterpret_cast<float *>(ws + align256(sizeof(int64_t) * (size_t)K) +
-                                         align256(sizeof(int64_t) * (size_t)(n_pts + 1)));
+    const PointsWs w = carve_points_ws(workspace, n_pts, K);
     hipError_t e;
-    if ((e = fcx::launch_expand_segments(K, n_pts, seg_off, p, p_idx, stream)) != hipSuccess)
+    if ((e = fcx::launch_expand_segments(K, n_pts, seg_off, p, w.p_idx, stream)) != hipSuccess)
         return hip_fail(e, "fc_scan_points: segment expansion");
     if (form != FC_FORM_FP32)
-        return fc_scan(g, form, K, d, p_idx, dchi2, chi2_min, argmin, chi2_p, stream);
+        return fc_scan(g, form, K, d, w.p_idx, dchi2, chi2_min, argmin, chi2_p, stream);
     unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
-    if ((e = fcx::launch_offset_table(g, n_pts, p, T, stream)) != hipSuccess ||
+    if ((e = fcx::launch_offset_table(g, n_pts, p, 0, g->G, w.T, stream)) != hipSuccess ||
         (e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
-        (e = fcx::launch_scan_fp32_points(g, n_pts, p, seg_off, K, d, T, tile_start, keys,
-                                          chi2_p, stream)) != hipSuccess ||
-        (e = fcx::launch_finalize(K, p_idx, keys, argmin, chi2_p, dchi2, stream)) != hipSuccess)
+        (e = fcx::launch_scan_fp32_points(g, n_pts, p, seg_off, K, d, 0, g->G, w.T, w.tile_start,
+                                          keys, chi2_p, stream)) != hipSuccess ||
+        (e = fcx::launch_finalize(K, w.p_idx, keys, chi2_min, argmin, chi2_p, dchi2, stream)) !=
+            hipSuccess)
         return hip_fail(e, "fc_scan_points: fp32 launch");
+    return FC_OK;
+}
+
+// ---- grid-sliced scans ------------------------------------------------------
+
+int fc_scan_state_init(int64_t K, uint64_t *keys, double *chi2_p, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (K < 0 || K > (int64_t(1) << 30))
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_state_init: K=%lld out of [0, 2^30]",
+                    (long long)K);
+    if (K == 0) return FC_OK;
+    if (!keys || !chi2_p) return fail(FC_ERR_INVALID_ARG, "fc_scan_state_init: NULL pointer");
+    const hipError_t e = fcx::launch_init_keys(K, reinterpret_cast<unsigned long long *>(keys),
+                                               chi2_p, stream, 0.0);
+    if (e != hipSuccess) return hip_fail(e, "fc_scan_state_init: launch");
+    return FC_OK;
+}
+
+namespace {
+
+// Checks shared by the two slice entry points: FC_OK, or the error (message set).
+int check_slice(const char *fn, const fc_grid *g, int32_t form, int64_t K, int64_t q0, int64_t nq)
+{
+    if (!g) return fail(FC_ERR_INVALID_ARG, "%s: grid is NULL", fn);
+    if (form != FC_FORM_FP64 && form != FC_FORM_FP32 && form != FC_FORM_SPLIT_BF16 &&
+        form != FC_FORM_SPLIT_FP16)
+        return fail(FC_ERR_INVALID_ARG, "%s: bad form %d", fn, form);
+    if (form == FC_FORM_FP64)
+        return fail(FC_ERR_UNSUPPORTED,
+                    "%s: the FP64 form keeps FP64 minima, which a 64-bit key cannot merge", fn);
+    if (!(g->forms & (uint32_t)form))
+        return fail(FC_ERR_STATE, "%s: form %d was not built for this grid", fn, form);
+    if (K < 0 || K > (int64_t(1) << 30))
+        return fail(FC_ERR_INVALID_ARG, "%s: K=%lld out of [0, 2^30]", fn, (long long)K);
+    if (q0 < 0 || nq < 0 || q0 > g->G || nq > g->G - q0)
+        return fail(FC_ERR_INVALID_ARG, "%s: grid slice [%lld, %lld) outside [0, %lld)", fn,
+                    (long long)q0, (long long)(q0 + nq), (long long)g->G);
+    return FC_OK;
+}
+
+}  // namespace
+
+int fc_scan_slice(const fc_grid *g, int32_t form, int64_t K, const double *d, const int64_t *p_idx,
+                  int64_t q0, int64_t nq, uint64_t *keys, double *chi2_p, hipStream_t stream)
+{
+    g_last_error.clear();
+    int rc = check_slice("fc_scan_slice", g, form, K, q0, nq);
+    if (rc != FC_OK) return rc;
+    if (K == 0 || nq == 0) return FC_OK;
+    if (!d || !p_idx || !keys || !chi2_p)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_slice: NULL device pointer");
+    unsigned long long *k = reinterpret_cast<unsigned long long *>(keys);
+    const hipError_t e =
+        form == FC_FORM_FP32
+            ? fcx::launch_scan_fp32(g, K, d, p_idx, q0, nq, k, chi2_p, stream)
+            : fcx::launch_scan_split(g, form == FC_FORM_SPLIT_FP16, K, d, p_idx, q0, nq, k, chi2_p,
+                                     stream);
+    if (e != hipSuccess) return hip_fail(e, "fc_scan_slice: launch");
+    return FC_OK;
+}
+
+int fc_scan_points_slice_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K,
+                                   int64_t nq, size_t *bytes)
+{
+    g_last_error.clear();
+    if (!g || !bytes)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice_workspace: NULL argument");
+    if (n_pts < 0 || K < 0 || n_pts > 0x7fffffff || nq < 0 || nq > g->G)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice_workspace: bad n_pts, K or nq");
+    *bytes = points_workspace(g, form, n_pts, K, nq);
+    return FC_OK;
+}
+
+int fc_scan_points_slice(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t *p,
+                         const int64_t *seg_off, int64_t K, const double *d, int64_t q0,
+                         int64_t nq, void *workspace, size_t workspace_bytes, uint64_t *keys,
+                         double *chi2_p, hipStream_t stream)
+{
+    g_last_error.clear();
+    int rc = check_slice("fc_scan_points_slice", g, form, K, q0, nq);
+    if (rc != FC_OK) return rc;
+    if (n_pts < 0 || n_pts > 0x7fffffff)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice: bad n_pts");
+    if (K == 0 || nq == 0) return FC_OK;
+    if (n_pts == 0)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice: K > 0 universes, no points");
+    if (!p || !seg_off || !d || !workspace || !keys || !chi2_p)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice: NULL device pointer");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice: workspace not 256-byte aligned");
+    const size_t need = points_workspace(g, form, n_pts, K, nq);
+    if (workspace_bytes < need)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice: workspace %zu B < %zu B",
+                    workspace_bytes, need);
+    const PointsWs w = carve_points_ws(workspace, n_pts, K);
+    unsigned long long *k = reinterpret_cast<unsigned long long *>(keys);
+    hipError_t e;
+    if (form != FC_FORM_FP32) {
+        if ((e = fcx::launch_expand_segments(K, n_pts, seg_off, p, w.p_idx, stream)) !=
+                hipSuccess ||
+            (e = fcx::launch_scan_split(g, form == FC_FORM_SPLIT_FP16, K, d, w.p_idx, q0, nq, k,
+                                        chi2_p, stream)) != hipSuccess)
+            return hip_fail(e, "fc_scan_points_slice: split launch");
+        return FC_OK;
+    }
+    if ((e = fcx::launch_offset_table(g, n_pts, p, q0, nq, w.T, stream)) != hipSuccess ||
+        (e = fcx::launch_scan_fp32_points(g, n_pts, p, seg_off, K, d, q0, nq, w.T, w.tile_start,
+                                          k, chi2_p, stream)) != hipSuccess)
+        return hip_fail(e, "fc_scan_points_slice: fp32 launch");
+    return FC_OK;
+}
+
+int fc_scan_state_finalize(const fc_grid *g, int64_t K, const int64_t *p_idx,
+                           const uint64_t *keys, const double *chi2_p, double *dchi2,
+                           double *chi2_min, int64_t *argmin, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_scan_state_finalize: grid is NULL");
+    if (K < 0 || K > (int64_t(1) << 30))
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_state_finalize: K=%lld out of [0, 2^30]",
+                    (long long)K);
+    if (K == 0) return FC_OK;
+    if (!p_idx || !keys || !chi2_p || !dchi2 || !chi2_min || !argmin)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_state_finalize: NULL device pointer");
+    const hipError_t e =
+        fcx::launch_finalize(K, p_idx, reinterpret_cast<const unsigned long long *>(keys),
+                             chi2_min, argmin, chi2_p, dchi2, stream, -1, g->G);
+    if (e != hipSuccess) return hip_fail(e, "fc_scan_state_finalize: launch");
     return FC_OK;
 }
 

@@ -192,27 +192,36 @@ hipError_t launch_offset(const double *S64, int64_t G, int N, double *off, doubl
 hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *stat, int stat_mode,
                             uint32_t forms, double *W64, uint4 *R32, uint4 *RB16, uint4 *RH16,
                             unsigned long long *bad_q, hipStream_t st);
+// The keyed scans cover the grid points [q0, q0 + nq) (nq = G: the whole grid)
+// and merge into keys / chi2_p (see launch_init_keys).
 hipError_t launch_scan_split(const fc_grid *g, bool fp16, int64_t K, const double *d,
-                             const int64_t *p_idx, unsigned long long *keys, double *chi2_p,
-                             hipStream_t st);
+                             const int64_t *p_idx, int64_t q0, int64_t nq,
+                             unsigned long long *keys, double *chi2_p, hipStream_t st);
 hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                            unsigned long long *keys, double *chi2_p, hipStream_t st);
+                            int64_t q0, int64_t nq, unsigned long long *keys, double *chi2_p,
+                            hipStream_t st);
 hipError_t launch_scan_fp32_points(const fc_grid *g, int64_t n_pts, const int64_t *p,
-                                   const int64_t *seg_off, int64_t K, const double *d,
-                                   const float *T, int64_t *tile_start, unsigned long long *keys,
-                                   double *chi2_p, hipStream_t st);
-hipError_t launch_offset_table(const fc_grid *g, int64_t n_pts, const int64_t *p, float *T,
-                               hipStream_t st);
+                                   const int64_t *seg_off, int64_t K, const double *d, int64_t q0,
+                                   int64_t nq, const float *T, int64_t *tile_start,
+                                   unsigned long long *keys, double *chi2_p, hipStream_t st);
+// T [n_pts][nq][4 ns]: offset rows of the grid points [q0, q0 + nq).
+hipError_t launch_offset_table(const fc_grid *g, int64_t n_pts, const int64_t *p, int64_t q0,
+                               int64_t nq, float *T, hipStream_t st);
 hipError_t launch_expand_segments(int64_t K, int64_t n_pts, const int64_t *seg_off,
                                   const int64_t *p, int64_t *p_idx, hipStream_t st);
 hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
                             double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p,
                             hipStream_t st);
-hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p, hipStream_t st);
+// keys = no value yet, chi2_p = chi2_p_fill (NaN for a one-call scan; 0 for
+// the sliced-scan state, so that slices merge by summing chi2_p).
+hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p, hipStream_t st,
+                            double chi2_p_fill = __builtin_nan(""));
 // p_idx may be nullptr: then every universe's true point is p_uniform.
-hipError_t launch_finalize(int64_t K, const int64_t *p_idx, unsigned long long *keys_as_chi2_min,
-                           int64_t *argmin, const double *chi2_p, double *dchi2, hipStream_t st,
-                           int64_t p_uniform = -1);
+// chi2_min may alias keys (decoded in place).  p_limit > 0: a true point
+// outside [0, p_limit) gives dchi2 = NaN (its chi2_p was never written).
+hipError_t launch_finalize(int64_t K, const int64_t *p_idx, const unsigned long long *keys,
+                           double *chi2_min, int64_t *argmin, const double *chi2_p, double *dchi2,
+                           hipStream_t st, int64_t p_uniform = -1, int64_t p_limit = 0);
 hipError_t launch_inverse_cov(const fc_grid *g, int64_t q0, int64_t nq, double *out,
                               hipStream_t st);
 hipError_t launch_crit(int64_t n_seg, const int64_t *seg_off, const double *x, int n_alpha,

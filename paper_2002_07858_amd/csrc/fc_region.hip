@@ -87,11 +87,12 @@ static hipError_t scan_batch(const fc_grid *g, int form, int64_t R, const double
     hipError_t e = launch_init_keys(R, keys, chi2_p, st);
     if (e != hipSuccess) return e;
     if (form == FC_FORM_FP32)
-        e = launch_scan_fp32(g, R, d, p_idx, keys, chi2_p, st);
+        e = launch_scan_fp32(g, R, d, p_idx, 0, g->G, keys, chi2_p, st);
     else
-        e = launch_scan_split(g, form == FC_FORM_SPLIT_FP16, R, d, p_idx, keys, chi2_p, st);
+        e = launch_scan_split(g, form == FC_FORM_SPLIT_FP16, R, d, p_idx, 0, g->G, keys, chi2_p,
+                              st);
     if (e != hipSuccess) return e;
-    return launch_finalize(R, p_idx, keys, argmin, chi2_p, dchi2, st);
+    return launch_finalize(R, p_idx, keys, chi2_min, argmin, chi2_p, dchi2, st);
 }
 
 int region_run(const fc_grid *g, int form, int64_t n_pts, const int64_t *pts_host, int64_t K0,

@@ -360,8 +360,9 @@ bool fc_server::launch(Cls &c)
     // copy back (stream order puts all of their items before this)
     for (Req *r : completing) {
         const size_t K = (size_t)r->K;
-        if ((e = fcx::launch_finalize(r->K, nullptr, r->keys, r->argmin, r->chi2p, r->dchi2,
-                                      c.stream, r->p)) != hipSuccess ||
+        if ((e = fcx::launch_finalize(r->K, nullptr, r->keys, reinterpret_cast<double *>(r->keys),
+                                      r->argmin, r->chi2p, r->dchi2, c.stream, r->p)) !=
+                hipSuccess ||
             (e = fcx::launch_crit(1, r->seg, r->dchi2, n_alpha, alpha, r->crit, n_bins, hist_hi,
                                   r->hist, c.stream)) != hipSuccess ||
             (e = hipMemcpyAsync(r->h_dchi2, r->dchi2, sizeof(double) * K, hipMemcpyDeviceToHost,

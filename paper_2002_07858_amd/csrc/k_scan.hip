@@ -363,7 +363,7 @@ __device__ __forceinline__ void fp32_fast_pairs(v4f (&acc)[n_ksteps(N)], float4 
 
 template <int N>
 __device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint4 *__restrict__ R32,
-                                                const float *__restrict__ trow, const uint4 *cur,
+                                                const float *__restrict__ trow_q, const uint4 *cur,
                                                 uint4 *nxt, const float4 *tcur, float4 *tnxt,
                                                 Fp32Fast<N> &L)
 {
@@ -376,7 +376,7 @@ __device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint
 
     if (more) {
         record_to_lds<REC, THREADS>(R32 + (q + 1) * REC, nxt, tid);
-        if (tid < 64) trow_to_lds<NS>(trow + (q + 1) * NR, tnxt, lane);
+        if (tid < 64) trow_to_lds<NS>(trow_q + NR, tnxt, lane);
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -400,7 +400,7 @@ __device__ __forceinline__ void fp32_fast_point(int64_t q, bool more, const uint
 template <int N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32(
     const uint4 *__restrict__ R32, const double *__restrict__ d,
-    const int64_t *__restrict__ p_idx, int64_t K, int64_t G, int64_t n_utiles,
+    const int64_t *__restrict__ p_idx, int64_t K, int64_t q_lo, int64_t q_hi, int64_t n_utiles,
     int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
 {
     __shared__ uint4 buf0[rec_units(n_ksteps(N))], buf1[rec_units(n_ksteps(N))];
@@ -418,8 +418,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int64_t utile = blockIdx.x % n_utiles;
     const int64_t qchunk = blockIdx.x / n_utiles;
     it.u0 = utile * (int64_t)kFp32UnivPerBlock;
-    it.qb = qchunk * q_per_chunk;
-    it.qe = (it.qb + q_per_chunk < G) ? it.qb + q_per_chunk : G;
+    it.qb = q_lo + qchunk * q_per_chunk;
+    it.qe = (it.qb + q_per_chunk < q_hi) ? it.qb + q_per_chunk : q_hi;
     fp32_item<N>(it, buf0, buf1);
 }
 
@@ -455,13 +455,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // 8 (xcd + 8 j) + m of grid chunk c: eight consecutive tiles (a segment's,
 // mostly) run on one XCD at the same time and share its L2 for the offset
 // rows and the records, and the XCDs get equal shares of the tiles.
-// Segments whose true point is outside the grid do nothing.
+// The grid points scanned are [q_lo, q_hi): the whole grid, or one slice of it
+// when the grid is split over several launches or devices.  Segments whose
+// true point is outside the grid do nothing.
 template <int N>
 __global__ __launch_bounds__(kPtsTile) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_fp32_pts(
     const uint4 *__restrict__ R32, const double *__restrict__ S64, const double *__restrict__ d,
     int64_t G, int64_t n_pts, const int64_t *__restrict__ p, const int64_t *__restrict__ seg_off,
     const int64_t *__restrict__ tile_start, const float *__restrict__ T, int64_t groups_per_xcd,
-    int64_t q_per_chunk,
+    int64_t q_lo, int64_t q_hi, int64_t q_per_chunk,
     unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
 {
     constexpr int NS = n_ksteps(N);
@@ -475,8 +477,8 @@ __global__ __launch_bounds__(kPtsTile) __attribute__((amdgpu_waves_per_eu(2))) v
     const int64_t member = k % 8, rest = k / 8;
     const int64_t group = xcd + 8 * (rest % groups_per_xcd);
     const int64_t tile = 8 * group + member;
-    const int64_t qb = (rest / groups_per_xcd) * q_per_chunk;
-    const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
+    const int64_t qb = q_lo + (rest / groups_per_xcd) * q_per_chunk;
+    const int64_t qe = (qb + q_per_chunk < q_hi) ? qb + q_per_chunk : q_hi;
     if (tile >= tile_start[n_pts]) return;  // uniform per block
     // the tile's segment: the largest s with tile_start[s] <= tile (uniform)
     int64_t lo = 0, hi = n_pts - 1;
@@ -506,16 +508,17 @@ __global__ __launch_bounds__(kPtsTile) __attribute__((amdgpu_waves_per_eu(2))) v
     L.qbest = 0xffffffffu;
     L.cp = 0.0f;
     L.have_cp = false;
-    const float *__restrict__ trow = T + seg * G * NR;
+    // offset rows of this segment: one per grid point of [q_lo, q_hi)
+    const float *__restrict__ trow = T + (seg * (q_hi - q_lo) + (qb - q_lo)) * NR;
 
     record_to_lds<REC, THREADS>(R32 + qb * REC, buf0, tid);
-    if (tid < 64) trow_to_lds<NS>(trow + qb * NR, tb0, lane);
+    if (tid < 64) trow_to_lds<NS>(trow, tb0, lane);
     wait_record_loads();
     __syncthreads();
     int64_t q = qb;
-    for (; q + 1 < qe; q += 2) {
+    for (; q + 1 < qe; q += 2, trow += 2 * NR) {
         fp32_fast_point<N>(q, true, R32, trow, buf0, buf1, tb0, tb1, L);
-        fp32_fast_point<N>(q + 1, q + 2 < qe, R32, trow, buf1, buf0, tb1, tb0, L);
+        fp32_fast_point<N>(q + 1, q + 2 < qe, R32, trow + NR, buf1, buf0, tb1, tb0, L);
     }
     if (q < qe) fp32_fast_point<N>(q, false, R32, trow, buf0, buf1, tb0, tb1, L);
 
@@ -576,18 +579,21 @@ __global__ __launch_bounds__(64) void k_scan_fp64(
 }
 
 __global__ __launch_bounds__(256) void k_init_keys(int64_t K, unsigned long long *__restrict__ keys,
-                                                  double *__restrict__ chi2_p)
+                                                  double *__restrict__ chi2_p, double chi2_p_fill)
 {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= K) return;
     keys[u] = kKeyNone;
-    chi2_p[u] = __builtin_nan("");
+    chi2_p[u] = chi2_p_fill;
 }
 
-// Decode the keys in place (the key buffer is the caller's chi2_min array).
+// Decode the keys.  chi2_min may be the key buffer itself (decoded in place:
+// each thread reads its key before it writes the same element).  A universe
+// with no finite chi2 keeps Algorithm 1's initial state and gets a NaN dchi2,
+// and so does one whose true point is outside [0, p_limit) when p_limit > 0.
 __global__ __launch_bounds__(256) void k_finalize(int64_t K, const int64_t *__restrict__ p_idx,
-                                                 int64_t p_uniform,
-                                                 unsigned long long *__restrict__ keys,
+                                                 int64_t p_uniform, int64_t p_limit,
+                                                 const unsigned long long *keys, double *chi2_min,
                                                  int64_t *__restrict__ argmin,
                                                  const double *__restrict__ chi2_p,
                                                  double *__restrict__ dchi2)
@@ -596,18 +602,24 @@ __global__ __launch_bounds__(256) void k_finalize(int64_t K, const int64_t *__re
     if (u >= K) return;
     const unsigned long long key = keys[u];
     const uint32_t hi = (uint32_t)(key >> 32);
-    double cmin;
+    double cmin, dc;
     int64_t am;
     if (hi >= 0x7f800000u) {  // no chi2 < +inf was seen: Algorithm 1's initial state
         cmin = __builtin_inf();
         am = p_idx ? p_idx[u] : p_uniform;
+        dc = __builtin_nan("");
     } else {
         cmin = (double)__uint_as_float(hi);
         am = (int64_t)(uint32_t)(key & 0xffffffffu);
+        dc = chi2_p[u] - cmin;
+        if (p_limit > 0) {
+            const int64_t pu = p_idx ? p_idx[u] : p_uniform;
+            if (pu < 0 || pu >= p_limit) dc = __builtin_nan("");
+        }
     }
-    reinterpret_cast<double *>(keys)[u] = cmin;
+    chi2_min[u] = cmin;
     argmin[u] = am;
-    dchi2[u] = chi2_p[u] - cmin;
+    dchi2[u] = dc;
 }
 
 // ---------------------------------------------------------------------------
@@ -659,16 +671,17 @@ ScanGeometry scan_geometry(int64_t K, int64_t G, int slots, int univ_per_block)
 
 template <int N>
 static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                                unsigned long long *keys, double *chi2_p, hipStream_t st)
+                                int64_t q0, int64_t nq, unsigned long long *keys, double *chi2_p,
+                                hipStream_t st)
 {
     static int slots = 0;  // per instantiation; same device model for the process
     if (slots == 0)
         slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32<N>),
                                64 * kWavesPerBlock);
-    const ScanGeometry sg = scan_geometry(K, g->G, slots, kFp32UnivPerBlock);
+    const ScanGeometry sg = scan_geometry(K, nq, slots, kFp32UnivPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     hipLaunchKernelGGL((k_scan_fp32<N>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, st,
-                       g->R32, d, p_idx, K, g->G, sg.n_utiles, sg.q_per_chunk, keys, chi2_p);
+                       g->R32, d, p_idx, K, q0, q0 + nq, sg.n_utiles, sg.q_per_chunk, keys, chi2_p);
     return hipGetLastError();
 }
 
@@ -706,9 +719,9 @@ __global__ __launch_bounds__(1024) void k_tile_prefix(int64_t n_pts,
 
 template <int N>
 static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64_t *p,
-                                    const int64_t *seg_off, int64_t K, const double *d,
-                                    const float *T, int64_t *tile_start, unsigned long long *keys,
-                                    double *chi2_p, hipStream_t st)
+                                    const int64_t *seg_off, int64_t K, const double *d, int64_t q0,
+                                    int64_t nq, const float *T, int64_t *tile_start,
+                                    unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
     static int slots = 0;
     if (slots == 0)
@@ -716,17 +729,18 @@ static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64
     const int64_t max_tiles = K / kPtsTile + n_pts;  // bound on the dense tile count
     const int64_t groups_per_xcd = (max_tiles + 63) / 64;
     const int64_t n_tiles = 64 * groups_per_xcd;    // blocks per grid chunk
-    const ScanGeometry sg = scan_geometry(max_tiles * kPtsTile, g->G, slots, kPtsTile);
+    const ScanGeometry sg = scan_geometry(max_tiles * kPtsTile, nq, slots, kPtsTile);
     const int64_t blocks = n_tiles * sg.n_qchunks;
     hipLaunchKernelGGL(k_tile_prefix, dim3(1), dim3(1024), 0, st, n_pts, seg_off, tile_start);
     hipLaunchKernelGGL((k_scan_fp32_pts<N>), dim3((unsigned)blocks), dim3(kPtsTile), 0,
                        st, g->R32, g->S64, d, g->G, n_pts, p, seg_off, tile_start, T, groups_per_xcd,
-                       sg.q_per_chunk, keys, chi2_p);
+                       q0, q0 + nq, sg.q_per_chunk, keys, chi2_p);
     return hipGetLastError();
 }
 
-// Offset table of the FP32 offset form: T[pt][q][r'] = sum_k' W'_q[r'][k']
-// (S_p - S_q)[k' - P] for the true point p = p[pt] of every segment, in FP64
+// Offset table of the FP32 offset form: T[pt][q - q_lo][r'] = sum_k' W'_q[r'][k']
+// (S_p - S_q)[k' - P] for the true point p = p[pt] of every segment and every
+// grid point q of [q_lo, q_lo + nq), in FP64
 // arithmetic on the FP32 factor as the scan uses it (padded rows r' < 4 ns),
 // rounded once to FP32; rows of an out-of-range p are zero (such segments take
 // the residual form).  One block per grid point (grid-stride): the record's A
@@ -736,7 +750,8 @@ static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64
 template <int N>
 __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ R32,
                                                       const double *__restrict__ S64, int64_t G,
-                                                      int64_t n_pts, const int64_t *__restrict__ p,
+                                                      int64_t q_lo, int64_t nq, int64_t n_pts,
+                                                      const int64_t *__restrict__ p,
                                                       float *__restrict__ T)
 {
     constexpr int NS = n_ksteps(N), P = fp32_pad(NS, N), NR = 4 * NS;
@@ -755,7 +770,8 @@ __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ 
     }
     __syncthreads();
     float *wt = reinterpret_cast<float *>(Wt);
-    for (int64_t q = blockIdx.x; q < G; q += gridDim.x) {
+    for (int64_t j = blockIdx.x; j < nq; j += gridDim.x) {
+        const int64_t q = q_lo + j;
         for (int i = tid; i < NR * NR; i += blockDim.x) wt[i] = 0.0f;
         for (int i = tid; i < NR; i += blockDim.x) Sq[i] = (i >= P) ? S64[q * N + (i - P)] : 0.0;
         __syncthreads();
@@ -786,7 +802,7 @@ __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ 
                     }
                 }
             }
-            float4 *dst = reinterpret_cast<float4 *>(T + (pt * G + q) * NR);
+            float4 *dst = reinterpret_cast<float4 *>(T + (pt * nq + j) * NR);
 #pragma unroll
             for (int b = 0; b < NS; ++b)
                 dst[b] = make_float4((float)acc[4 * b], (float)acc[4 * b + 1], (float)acc[4 * b + 2],
@@ -818,12 +834,12 @@ __global__ __launch_bounds__(256) void k_expand_segments(int64_t K, int64_t n_pt
 }
 
 template <int N>
-static hipError_t launch_offset_table_n(const fc_grid *g, int64_t n_pts, const int64_t *p, float *T,
-                                        hipStream_t st)
+static hipError_t launch_offset_table_n(const fc_grid *g, int64_t n_pts, const int64_t *p,
+                                        int64_t q0, int64_t nq, float *T, hipStream_t st)
 {
-    const int64_t blocks = g->G < 65536 ? g->G : 65536;
+    const int64_t blocks = nq < 65536 ? nq : 65536;
     hipLaunchKernelGGL((k_offset_table<N>), dim3((unsigned)blocks), dim3(256), 0, st, g->R32, g->S64,
-                       g->G, n_pts, p, T);
+                       g->G, q0, nq, n_pts, p, T);
     return hipGetLastError();
 }
 
@@ -880,11 +896,12 @@ int serve_slots_fp32(int N)
 }
 
 hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                            unsigned long long *keys, double *chi2_p, hipStream_t st)
+                            int64_t q0, int64_t nq, unsigned long long *keys, double *chi2_p,
+                            hipStream_t st)
 {
     switch (g->N) {
 #define FC_CASE(n) \
-    case n: return launch_fp32_n<n>(g, K, d, p_idx, keys, chi2_p, st);
+    case n: return launch_fp32_n<n>(g, K, d, p_idx, q0, nq, keys, chi2_p, st);
         FC_EACH_N(FC_CASE)
 #undef FC_CASE
     default: return hipErrorInvalidValue;
@@ -892,25 +909,27 @@ hipError_t launch_scan_fp32(const fc_grid *g, int64_t K, const double *d, const 
 }
 
 hipError_t launch_scan_fp32_points(const fc_grid *g, int64_t n_pts, const int64_t *p,
-                                   const int64_t *seg_off, int64_t K, const double *d,
-                                   const float *T, int64_t *tile_start, unsigned long long *keys,
-                                   double *chi2_p, hipStream_t st)
+                                   const int64_t *seg_off, int64_t K, const double *d, int64_t q0,
+                                   int64_t nq, const float *T, int64_t *tile_start,
+                                   unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
     switch (g->N) {
-#define FC_CASE(n) \
-    case n: return launch_fp32_pts_n<n>(g, n_pts, p, seg_off, K, d, T, tile_start, keys, chi2_p, st);
+#define FC_CASE(n)                                                                             \
+    case n:                                                                                    \
+        return launch_fp32_pts_n<n>(g, n_pts, p, seg_off, K, d, q0, nq, T, tile_start, keys, \
+                                    chi2_p, st);
         FC_EACH_N(FC_CASE)
 #undef FC_CASE
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_offset_table(const fc_grid *g, int64_t n_pts, const int64_t *p, float *T,
-                               hipStream_t st)
+hipError_t launch_offset_table(const fc_grid *g, int64_t n_pts, const int64_t *p, int64_t q0,
+                               int64_t nq, float *T, hipStream_t st)
 {
     switch (g->N) {
 #define FC_CASE(n) \
-    case n: return launch_offset_table_n<n>(g, n_pts, p, T, st);
+    case n: return launch_offset_table_n<n>(g, n_pts, p, q0, nq, T, st);
         FC_EACH_N(FC_CASE)
 #undef FC_CASE
     default: return hipErrorInvalidValue;
@@ -954,20 +973,22 @@ hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const 
     }
 }
 
-hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p, hipStream_t st)
+hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p, hipStream_t st,
+                            double chi2_p_fill)
 {
     const int64_t blocks = (K + 255) / 256;
-    hipLaunchKernelGGL(k_init_keys, dim3((unsigned)blocks), dim3(256), 0, st, K, keys, chi2_p);
+    hipLaunchKernelGGL(k_init_keys, dim3((unsigned)blocks), dim3(256), 0, st, K, keys, chi2_p,
+                       chi2_p_fill);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(int64_t K, const int64_t *p_idx, unsigned long long *keys_as_chi2_min,
-                           int64_t *argmin, const double *chi2_p, double *dchi2, hipStream_t st,
-                           int64_t p_uniform)
+hipError_t launch_finalize(int64_t K, const int64_t *p_idx, const unsigned long long *keys,
+                           double *chi2_min, int64_t *argmin, const double *chi2_p, double *dchi2,
+                           hipStream_t st, int64_t p_uniform, int64_t p_limit)
 {
     const int64_t blocks = (K + 255) / 256;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, st, K, p_idx, p_uniform,
-                       keys_as_chi2_min, argmin, chi2_p, dchi2);
+                       p_limit, keys, chi2_min, argmin, chi2_p, dchi2);
     return hipGetLastError();
 }
 

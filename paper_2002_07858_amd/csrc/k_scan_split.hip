@@ -242,8 +242,9 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
 template <int NK, int NB, int NC, bool FP16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_split(
     const uint4 *__restrict__ R16, const double *__restrict__ d, const double *__restrict__ off,
-    int ed, const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
-    int64_t q_per_chunk, unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
+    int ed, const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t q_lo, int64_t q_hi,
+    int64_t n_utiles, int64_t q_per_chunk, unsigned long long *__restrict__ keys,
+    double *__restrict__ chi2_p)
 {
     __shared__ uint4 buf0[split_rec_units(NK, NB)], buf1[split_rec_units(NK, NB)];
     ScanItem it;
@@ -260,8 +261,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int64_t utile = blockIdx.x % n_utiles;
     const int64_t qchunk = blockIdx.x / n_utiles;
     it.u0 = utile * (int64_t)(16 * NC * kWavesPerBlock);
-    it.qb = qchunk * q_per_chunk;
-    it.qe = (it.qb + q_per_chunk < G) ? it.qb + q_per_chunk : G;
+    it.qb = q_lo + qchunk * q_per_chunk;
+    it.qe = (it.qb + q_per_chunk < q_hi) ? it.qb + q_per_chunk : q_hi;
     split_item<NK, NB, NC, FP16>(it, buf0, buf1);
 }
 
@@ -301,32 +302,34 @@ constexpr int kSplitColBlocks = 4;  // 64 universes per wave
 
 template <int NK, int NB, bool FP16>
 static hipError_t launch_split_t(const fc_grid *g, int64_t K, const double *d,
-                                 const int64_t *p_idx, unsigned long long *keys, double *chi2_p,
-                                 hipStream_t st)
+                                 const int64_t *p_idx, int64_t q0, int64_t nq,
+                                 unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
     constexpr int NC = kSplitColBlocks;
     static int slots = 0;
     if (slots == 0)
         slots = resident_slots_split(reinterpret_cast<const void *>(&k_scan_split<NK, NB, NC, FP16>));
-    const ScanGeometry sg = scan_geometry(K, g->G, slots, 16 * NC * kWavesPerBlock);
+    const ScanGeometry sg = scan_geometry(K, nq, slots, 16 * NC * kWavesPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     const uint4 *R = FP16 ? g->RH16 : g->RB16;
     hipLaunchKernelGGL((k_scan_split<NK, NB, NC, FP16>), dim3((unsigned)blocks), dim3(256), 0, st, R,
-                       d, g->off, FP16 ? g->ed16 : 0, p_idx, K, g->N, g->G, sg.n_utiles,
+                       d, g->off, FP16 ? g->ed16 : 0, p_idx, K, g->N, q0, q0 + nq, sg.n_utiles,
                        sg.q_per_chunk, keys, chi2_p);
     return hipGetLastError();
 }
 
 template <bool FP16>
 static hipError_t launch_split_f(const fc_grid *g, int64_t K, const double *d,
-                                 const int64_t *p_idx, unsigned long long *keys, double *chi2_p,
-                                 hipStream_t st)
+                                 const int64_t *p_idx, int64_t q0, int64_t nq,
+                                 unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
     const int nk = split_nk(g->N), nb = split_nb(g->N);
-    if (nk == 1 && nb == 1) return launch_split_t<1, 1, FP16>(g, K, d, p_idx, keys, chi2_p, st);
-    if (nk == 1 && nb == 2) return launch_split_t<1, 2, FP16>(g, K, d, p_idx, keys, chi2_p, st);
-    if (nk == 2 && nb == 3) return launch_split_t<2, 3, FP16>(g, K, d, p_idx, keys, chi2_p, st);
-    if (nk == 2 && nb == 4) return launch_split_t<2, 4, FP16>(g, K, d, p_idx, keys, chi2_p, st);
+#define FC_T(a, b) launch_split_t<a, b, FP16>(g, K, d, p_idx, q0, nq, keys, chi2_p, st)
+    if (nk == 1 && nb == 1) return FC_T(1, 1);
+    if (nk == 1 && nb == 2) return FC_T(1, 2);
+    if (nk == 2 && nb == 3) return FC_T(2, 3);
+    if (nk == 2 && nb == 4) return FC_T(2, 4);
+#undef FC_T
     return hipErrorInvalidValue;
 }
 
@@ -382,11 +385,11 @@ int serve_slots_split(int nk, int nb, bool fp16)
 }
 
 hipError_t launch_scan_split(const fc_grid *g, bool fp16, int64_t K, const double *d,
-                             const int64_t *p_idx, unsigned long long *keys, double *chi2_p,
-                             hipStream_t st)
+                             const int64_t *p_idx, int64_t q0, int64_t nq,
+                             unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
-    return fp16 ? launch_split_f<true>(g, K, d, p_idx, keys, chi2_p, st)
-                : launch_split_f<false>(g, K, d, p_idx, keys, chi2_p, st);
+    return fp16 ? launch_split_f<true>(g, K, d, p_idx, q0, nq, keys, chi2_p, st)
+                : launch_split_f<false>(g, K, d, p_idx, q0, nq, keys, chi2_p, st);
 }
 
 }  // namespace fcx

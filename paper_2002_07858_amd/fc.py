@@ -42,7 +42,9 @@ FC_REQ_DONE = 2
 FC_REQ_FAILED = -1
 
 EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_scan_points",
-            "fc_scan_points_workspace", "fc_critical_value",
+            "fc_scan_points_workspace", "fc_scan_state_init", "fc_scan_slice",
+            "fc_scan_points_slice", "fc_scan_points_slice_workspace", "fc_scan_state_finalize",
+            "fc_critical_value",
             "fc_scan_fixed_m", "fc_generate_universes", "fc_region", "fc_data_scan",
             "fc_acceptance",
             "fc_grid_inverse_cov", "fc_grid_info",
@@ -78,6 +80,12 @@ def lib():
         L.fc_scan_points.argtypes = [_p, _i32, _i64, _p, _p, _i64, _p, _p, ctypes.c_size_t, _p,
                                      _p, _p, _p, _p]
         L.fc_scan_points_workspace.argtypes = [_p, _i32, _i64, _i64, _p]
+        L.fc_scan_state_init.argtypes = [_i64, _p, _p, _p]
+        L.fc_scan_slice.argtypes = [_p, _i32, _i64, _p, _p, _i64, _i64, _p, _p, _p]
+        L.fc_scan_points_slice.argtypes = [_p, _i32, _i64, _p, _p, _i64, _p, _i64, _i64, _p,
+                                           ctypes.c_size_t, _p, _p, _p]
+        L.fc_scan_points_slice_workspace.argtypes = [_p, _i32, _i64, _i64, _i64, _p]
+        L.fc_scan_state_finalize.argtypes = [_p, _i64, _p, _p, _p, _p, _p, _p, _p]
         L.fc_critical_value.argtypes = [_i64, _p, _p, _i32, _p, _p, _i32, _dbl, _p, _p]
         L.fc_generate_universes.argtypes = [_p, _i64, _p, _p, _p, ctypes.c_uint64, _i64, _p, _p,
                                             _p, _p]
@@ -106,7 +114,9 @@ def lib():
                      "fc_server_poll", "fc_server_stats"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_scan_points",
-                     "fc_scan_points_workspace", "fc_critical_value",
+                     "fc_scan_points_workspace", "fc_scan_state_init", "fc_scan_slice",
+                     "fc_scan_points_slice", "fc_scan_points_slice_workspace",
+                     "fc_scan_state_finalize", "fc_critical_value",
                      "fc_scan_fixed_m", "fc_generate_universes", "fc_region", "fc_data_scan",
             "fc_acceptance",
             "fc_grid_inverse_cov", "fc_grid_info"):
@@ -252,6 +262,60 @@ def fc_scan_points(grid: Grid, form: int, p, seg_off, d, dchi2, chi2_min, argmin
                                 _dev(argmin, "i64", "argmin"), _dev(chi2_p, "f64", "chi2_p"),
                                 _stream(stream)))
     return workspace
+
+
+def fc_scan_state_init(keys, chi2_p, stream=None):
+    """Enqueue keys = none, chi2_p = 0 for a grid-sliced scan.  keys is an
+    int64 CUDA tensor holding the uint64 keys bit for bit."""
+    K = int(keys.numel())
+    _check(lib().fc_scan_state_init(K, _dev(keys, "i64", "keys"), _dev(chi2_p, "f64", "chi2_p"),
+                                    _stream(stream)))
+
+
+def fc_scan_slice(grid: Grid, form: int, d, p_idx, q0: int, nq: int, keys, chi2_p, stream=None):
+    """Enqueue the scan of grid points [q0, q0 + nq), merged into (keys, chi2_p)."""
+    K = int(d.shape[0])
+    _check(lib().fc_scan_slice(grid._h, int(form), K, _dev(d, "f64", "d"),
+                               _dev(p_idx, "i64", "p_idx"), int(q0), int(nq),
+                               _dev(keys, "i64", "keys"), _dev(chi2_p, "f64", "chi2_p"),
+                               _stream(stream)))
+
+
+def fc_scan_points_slice_workspace(grid: Grid, form: int, n_pts: int, K: int, nq: int) -> int:
+    """Bytes of workspace fc_scan_points_slice needs for nq grid points."""
+    b = ctypes.c_size_t()
+    _check(lib().fc_scan_points_slice_workspace(grid._h, int(form), int(n_pts), int(K), int(nq),
+                                                ctypes.byref(b)))
+    return b.value
+
+
+def fc_scan_points_slice(grid: Grid, form: int, p, seg_off, d, q0: int, nq: int, keys, chi2_p,
+                         workspace=None, stream=None):
+    """Enqueue the points scan of grid points [q0, q0 + nq), merged into
+    (keys, chi2_p).  The workspace is allocated here when not given."""
+    import torch
+    K = int(d.shape[0])
+    n_pts = int(p.numel())
+    need = fc_scan_points_slice_workspace(grid, form, n_pts, K, nq)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=d.device)
+    _check(lib().fc_scan_points_slice(grid._h, int(form), n_pts, _dev(p, "i64", "p"),
+                                      _dev(seg_off, "i64", "seg_off"), K, _dev(d, "f64", "d"),
+                                      int(q0), int(nq), _dev(workspace, "u8", "workspace"),
+                                      int(workspace.numel()), _dev(keys, "i64", "keys"),
+                                      _dev(chi2_p, "f64", "chi2_p"), _stream(stream)))
+    return workspace
+
+
+def fc_scan_state_finalize(grid: Grid, p_idx, keys, chi2_p, dchi2, chi2_min, argmin,
+                           stream=None):
+    """Enqueue the decoding of a merged sliced-scan state into fc_scan's outputs."""
+    K = int(keys.numel())
+    _check(lib().fc_scan_state_finalize(grid._h, K, _dev(p_idx, "i64", "p_idx"),
+                                        _dev(keys, "i64", "keys"), _dev(chi2_p, "f64", "chi2_p"),
+                                        _dev(dchi2, "f64", "dchi2"),
+                                        _dev(chi2_min, "f64", "chi2_min"),
+                                        _dev(argmin, "i64", "argmin"), _stream(stream)))
 
 
 def fc_critical_value(seg_off, dchi2, alpha, crit, n_bins=200, hist_hi=50.0, hist=None,
