@@ -145,6 +145,10 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
  * packed (chi2, q) minimum keys until the final pass rewrites it.
  * Universes with NaN/inf data get chi2_min = +inf, argmin = p, dchi2 = NaN;
  * other universes are unaffected.
+ * The FP64 form, when K is too small to fill the GPU, splits the grid into
+ * chunks whose minima are merged in grid order (the same result); it then
+ * takes a stream-ordered scratch of at most 4 MB (hipMallocAsync and
+ * hipFreeAsync on `stream`; FC_ERR_NOMEM or FC_ERR_DEVICE if that fails).
  */
 int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d,
             const int64_t *p_idx, double *dchi2, double *chi2_min, int64_t *argmin,

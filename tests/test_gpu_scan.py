@@ -262,7 +262,7 @@ def test_exact_ties_pick_lowest_grid_index(fc):
 # ---------------------------------------------------------------------------
 # determinism: rerun and batch composition do not change a single bit
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("form", ["fp32", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "split_bf16", "split_fp16"])
 def test_bitwise_determinism_and_batch_invariance(fc, form):
     pr = fcgen.make_problem("c2", K=600, true_subset=[3, 100, 250])
     g = make_grid(fc, pr, FORM[form])
