@@ -704,12 +704,15 @@ int resident_slots(const void *kernel, int block_threads)
 }
 
 // Pick the number of grid chunks so that tiles x chunks fills the resident
-// block slots with the smallest tail: minimise ceil(tiles*c/slots)/c.
+// block slots with the smallest tail: minimise ceil(tiles*c/slots)/c, with a
+// small charge per chunk.  With few tiles (a small K) every chunk count up to
+// G / min_chunk fits in one round and the most chunks win, so min_chunk sets
+// how far a small scan spreads over the CUs; at large K the tail term decides.
 ScanGeometry scan_geometry(int64_t K, int64_t G, int slots, int univ_per_block)
 {
     ScanGeometry sg;
     sg.n_utiles = (K + univ_per_block - 1) / univ_per_block;
-    const int64_t min_chunk = 64;
+    const int64_t min_chunk = 8;
     int64_t cmax = G / min_chunk;
     if (cmax < 1) cmax = 1;
     if (cmax > 256) cmax = 256;
