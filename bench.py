@@ -76,10 +76,10 @@ FP32_SOURCES = ("paper_2002_07858_amd/csrc/k_scan.hip", "paper_2002_07858_amd/cs
 SPLIT_SOURCES = ("paper_2002_07858_amd/csrc/k_scan_split.hip",
                  "paper_2002_07858_amd/csrc/fc_internal.h")
 TRAFFIC = {
-    ("c2", "fp32", "points"): {"bytes_per_launch": 7840363978, "source_hash": "2426118e904371a9",
+    ("c2", "fp32", "points"): {"bytes_per_launch": 7839467090, "source_hash": "9c6b8146bc171591",
                                "sources": FP32_SOURCES,
                                "profile": "profiles/k_scan_fp32_pts_c2_counters.md"},
-    ("c2", "fp32", "universes"): {"bytes_per_launch": 14205767975, "source_hash": "2426118e904371a9",
+    ("c2", "fp32", "universes"): {"bytes_per_launch": 14043728812, "source_hash": "9c6b8146bc171591",
                                   "sources": FP32_SOURCES,
                                   "profile": "profiles/k_scan_fp32_pts_c2_counters.md"},
     ("c2", "split_fp16", "universes"): {"bytes_per_launch": 10699201253,
@@ -418,6 +418,26 @@ def shard_bench(fc, grid, form, form_name, scan_entry, pr, d_t, p_t, pts_t, so_t
             "merged_equals_one_call": equal}
 
 
+def device_record():
+    """The device and software the line was measured on, and the peak
+    denominators of the roofline fractions."""
+    import ctypes
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    rec = {"name": props.name, "arch": getattr(props, "gcnArchName", None),
+           "compute_units": props.multi_processor_count,
+           "hbm_bytes": props.total_memory, "hip": torch.version.hip, "torch": torch.__version__,
+           "peaks_per_s": {**{k: v for k, v in PEAK.items()}, "hbm_bytes": 8.0e12}}
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+        v = ctypes.c_int(0)
+        if hip.hipDeviceGetAttribute(ctypes.byref(v), 5, 0) == 0:  # hipDeviceAttributeClockRate (kHz)
+            rec["max_sclk_mhz"] = v.value / 1000.0
+    except OSError:
+        pass
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -583,7 +603,8 @@ def main():
            "phases_ms": {k: float(np.mean(v)) for k, v in times.items()},
            "scan_evals_per_s": evals / (scan_ms * 1e-3),
            "bitwise_deterministic": deterministic,
-           "roofline": roofline}
+           "roofline": roofline,
+           "device": device_record()}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         base, rep = cpu_baseline(pr, args.cpu_per_point, dev_out, TOL[args.form])

@@ -3,9 +3,10 @@ the FP64 oracle (which computes them one by one) and on properties that hold
 at any size.
 
 c3: D=3 grid 60^3 (216 000 points), N=57, 64 true points x 4000 universes,
-    FP32 and split BF16 / FP16 forms on the same inputs.
+    FP32 (per-universe and grouped-by-point entries) and split BF16 / FP16
+    forms on the same inputs.
 c5: D=5 grid 16^5 (1 048 576 points), N=57, 16 true points x 10 000
-    universes, FP32 and split FP16.
+    universes, FP32 (both entries) and split FP16.
 """
 from __future__ import annotations
 
@@ -43,6 +44,20 @@ def scan(fc, grid, form, d_t, p_t):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
+def scan_points(fc, grid, pr, d_t):
+    """The FP32 offset form through fc_scan_points, as the benchmark times it."""
+    K = d_t.shape[0]
+    out = {k: torch.empty(K, dtype=torch.float64, device="cuda")
+           for k in ("dchi2", "chi2_min", "chi2_p")}
+    out["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
+    pts = torch.as_tensor(pr.p_idx[pr.seg_off[:-1]]).cuda()
+    seg = torch.as_tensor(pr.seg_off).cuda()
+    fc.fc_scan_points(grid, 2, pts, seg, d_t, out["dchi2"], out["chi2_min"], out["argmin"],
+                      out["chi2_p"])
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
 def sample_idx(pr, per_point):
     idx = []
     for s in range(len(pr.seg_off) - 1):
@@ -59,31 +74,37 @@ def c3(fc):
     d_t = torch.as_tensor(pr.d).cuda()
     p_t = torch.as_tensor(pr.p_idx).cuda()
     outs = {f: scan(fc, grid, FORM[f], d_t, p_t) for f in FORM}
+    outs["fp32_points"] = scan_points(fc, grid, pr, d_t)
     idx = sample_idx(pr, 1)
     ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx])
     yield pr, outs, idx, ref
     grid.destroy()
 
 
-@pytest.mark.parametrize("form", list(FORM))
+@pytest.mark.parametrize("form", list(FORM) + ["fp32_points"])
 def test_c3_sampled_parity(c3, form):
     pr, outs, idx, ref = c3
     dev = outs[form]
+    tol = parity.TOL[form.replace("_points", "")]
     parity.check_invariants(dev, pr.G)
-    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, parity.TOL[form])
+    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, tol)
     print(form, rep)
-    assert rep["e_rel"] <= parity.TOL[form]
+    assert rep["e_rel"] <= tol
     assert rep["argmin_agree"] >= 0.98
 
 
 def test_c3_forms_agree_on_every_universe(c3):
-    """All 256 000 universes: split forms against the FP32 form on the same inputs."""
+    """All 256 000 universes: the split forms and the FP32 offset form against the
+    FP32 residual form on the same inputs."""
     pr, outs, _, _ = c3
     base = outs["fp32"]
     scale = np.maximum(1.0, base["chi2_p"])
     for form in ("split_bf16", "split_fp16"):
         e = np.abs(outs[form]["dchi2"] - base["dchi2"]) / scale
         assert e.max() <= parity.TOL[form] + parity.TOL["fp32"], (form, e.max())
+    # the FP32 offset form (fc_scan_points) against the residual form
+    e = np.abs(outs["fp32_points"]["dchi2"] - base["dchi2"]) / scale
+    assert e.max() <= 2 * parity.TOL["fp32"], e.max()
     # per-point 90 % critical values agree within the same Lipschitz bound
     for form in ("split_bf16", "split_fp16"):
         c_a, _ = oracle.critical_value(base["dchi2"], pr.seg_off, [0.9], with_hist=False)
@@ -100,19 +121,21 @@ def c5(fc):
     d_t = torch.as_tensor(pr.d).cuda()
     p_t = torch.as_tensor(pr.p_idx).cuda()
     outs = {f: scan(fc, grid, FORM[f], d_t, p_t) for f in ("fp32", "split_fp16")}
+    outs["fp32_points"] = scan_points(fc, grid, pr, d_t)
     idx = sample_idx(pr, 1)
     ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx])
     yield pr, outs, idx, ref
     grid.destroy()
 
 
-@pytest.mark.parametrize("form", ["fp32", "split_fp16"])
+@pytest.mark.parametrize("form", ["fp32", "split_fp16", "fp32_points"])
 def test_c5_sampled_parity(c5, form):
     pr, outs, idx, ref = c5
     assert pr.G == 16 ** 5
     dev = outs[form]
+    tol = parity.TOL[form.replace("_points", "")]
     parity.check_invariants(dev, pr.G)
-    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, parity.TOL[form])
+    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, tol)
     print(form, rep)
-    assert rep["e_rel"] <= parity.TOL[form]
+    assert rep["e_rel"] <= tol
     assert rep["argmin_agree"] >= 0.95
