@@ -10,12 +10,21 @@
 //
 // One wave (64 lanes) per grid point: lane i owns row i during the Cholesky
 // and column i during the inversion.  A non-positive (or NaN) pivot marks the
-// point as not positive definite.
+// point as not positive definite.  L and W share one LDS matrix: L in the
+// lower triangle, W_q's column c transposed into the strict upper part of row
+// c and its diagonal into the spare column kMaxBins (33 KB per point, so four
+// points fit a CU's LDS at once).
 #include "fc_internal.h"
 
 namespace fcx {
 
 constexpr int kLdsStride = kMaxBins + 1;
+
+// W_q[r][c] (r >= c) from the shared matrix.
+__device__ inline double wget(const double *A, int r, int c)
+{
+    return (r == c) ? A[c * kLdsStride + kMaxBins] : A[c * kLdsStride + r];
+}
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -46,8 +55,7 @@ __device__ inline void split8(const float (&x)[8], uint4 &hi, uint4 &lo)
 
 // One split-form record (see fc_internal.h) from the FP64 factor in LDS.
 template <bool FP16>
-__device__ void write_split_record(const double *Wc, const double *Sq, const double *off, int N,
-                                   int ed, uint4 *rq)
+__device__ void write_split_record(const double *A, const double *sdo, int N, int ed, uint4 *rq)
 {
     const int i = threadIdx.x;
     const int nk = split_nk(N), nb = split_nb(N);
@@ -56,7 +64,7 @@ __device__ void write_split_record(const double *Wc, const double *Sq, const dou
     if constexpr (FP16) {
         double wm = 0.0;
         if (i < N)
-            for (int r = i; r < N; ++r) wm = fmax(wm, fabs(Wc[r * kLdsStride + i]));
+            for (int r = i; r < N; ++r) wm = fmax(wm, fabs(wget(A, r, i)));
         for (int m = 32; m > 0; m >>= 1) wm = fmax(wm, __shfl_xor(wm, m));
         eq = (wm > 0.0) ? 13 - ilogb(wm) : 0;
     }
@@ -68,7 +76,7 @@ __device__ void write_split_record(const double *Wc, const double *Sq, const dou
             float x[8];
             for (int e = 0; e < 8; ++e) {
                 const int cc = c0 + e;
-                x[e] = (rr < N && cc <= rr) ? (float)ldexp(Wc[rr * kLdsStride + cc], eq) : 0.0f;
+                x[e] = (rr < N && cc <= rr) ? (float)ldexp(wget(A, rr, cc), eq) : 0.0f;
             }
             uint4 hi, lo;
             split8<FP16>(x, hi, lo);
@@ -81,8 +89,10 @@ __device__ void write_split_record(const double *Wc, const double *Sq, const dou
         const int g = i >> 4, b = (i >> 2) & 3, j = i & 3;
         const int row = 16 * b + 4 * g + j;
         double u = 0.0;
-        if (row < N)
-            for (int k = 0; k <= row; ++k) u += Wc[row * kLdsStride + k] * (Sq[k] - off[k]);
+        if (row < N) {
+#pragma unroll 4
+            for (int k = 0; k <= row; ++k) u += wget(A, row, k) * sdo[k];
+        }
         reinterpret_cast<float *>(rq + split_u_unit(nk, nb))[i] = (float)ldexp(-u, eq + ed);
     }
     const int su = split_scale_unit(nk, nb), ru = split_rec_units(nk, nb);
@@ -97,20 +107,27 @@ __global__ __launch_bounds__(64) void k_cov_build(
     uint4 *__restrict__ RH16, unsigned long long *__restrict__ bad_q)
 {
     __shared__ double A[kMaxBins * kLdsStride];
-    __shared__ double Wc[kMaxBins * kLdsStride];
+    __shared__ double colj[kMaxBins];  // column j of L, read by the trailing update
+    __shared__ double sdl[kMaxBins];   // S_q - fl32(S_q)
+    __shared__ double sdo[kMaxBins];   // S_q - o
     const int i = threadIdx.x;
+    // row i of F stays in registers for every grid point of this block
+    double frow[kMaxBins];
+#pragma unroll
+    for (int j = 0; j < kMaxBins; ++j) frow[j] = (i < N && j < N) ? F[i * N + j] : 0.0;
+    const double stat_i = (i < N && stat_mode != FC_STAT_PEARSON) ? stat[i] : 0.0;
 
     for (int64_t q = blockIdx.x; q < G; q += gridDim.x) {
         const double *Sq = S64 + q * N;
         // ---- Sigma_q, row i ------------------------------------------------
         const double si = (i < N) ? Sq[i] : 0.0;
-        for (int j = 0; j < N; ++j) {
-            double v = 0.0;
-            if (i < N) {
-                v = F[i * N + j] * (si * Sq[j]);
-                if (i == j) v += (stat_mode == FC_STAT_PEARSON) ? si : stat[i];
-            }
-            A[i * kLdsStride + j] = v;
+#pragma unroll
+        for (int j = 0; j < kMaxBins; ++j)
+            if (j < N) A[i * kLdsStride + j] = frow[j] * (si * Sq[j]);
+        if (i < N) {
+            A[i * kLdsStride + i] += (stat_mode == FC_STAT_PEARSON) ? si : stat_i;
+            sdl[i] = si - (double)(float)si;
+            sdo[i] = si - off[i];
         }
         __syncthreads();
 
@@ -124,13 +141,19 @@ __global__ __launch_bounds__(64) void k_cov_build(
             }
             const double ljj = sqrt(piv);
             __syncthreads();
+            double lij = 0.0;
             if (i == j) A[j * kLdsStride + j] = ljj;
-            if (i > j && i < N) A[i * kLdsStride + j] = A[i * kLdsStride + j] / ljj;
-            __syncthreads();
             if (i > j && i < N) {
-                const double lij = A[i * kLdsStride + j];
-                for (int k = j + 1; k <= i; ++k)
-                    A[i * kLdsStride + k] -= lij * A[k * kLdsStride + j];
+                lij = A[i * kLdsStride + j] / ljj;
+                A[i * kLdsStride + j] = lij;
+                colj[i] = lij;
+            }
+            __syncthreads();
+            // lane i updates its own row from the column copy: the loads come
+            // from another array than the stores, so they can be issued ahead
+            if (i > j && i < N) {
+#pragma unroll 4
+                for (int k = j + 1; k <= i; ++k) A[i * kLdsStride + k] -= lij * colj[k];
             }
             __syncthreads();
         }
@@ -141,11 +164,17 @@ __global__ __launch_bounds__(64) void k_cov_build(
         }
 
         // ---- W = L^{-1}: lane c solves L w = e_c for its own column ----------
+        // (w[k] = 0 for k < c, so the sums start at k = c; the stores go to row
+        // c's strict upper part and its spare column, which no other lane reads)
         const int c = i;
-        for (int r = 0; r < N; ++r) {
-            double acc = (r == c) ? 1.0 : 0.0;
-            for (int k = 0; k < r; ++k) acc -= A[r * kLdsStride + k] * Wc[k * kLdsStride + c];
-            Wc[r * kLdsStride + c] = (c < N && r >= c) ? acc / A[r * kLdsStride + r] : 0.0;
+        if (c < N) {
+            A[c * kLdsStride + kMaxBins] = 1.0 / A[c * kLdsStride + c];
+            for (int r = c + 1; r < N; ++r) {
+                double acc = 0.0;
+#pragma unroll 4
+                for (int k = c; k < r; ++k) acc -= A[r * kLdsStride + k] * wget(A, k, c);
+                A[c * kLdsStride + r] = acc / A[r * kLdsStride + r];
+            }
         }
         __syncthreads();
 
@@ -153,7 +182,7 @@ __global__ __launch_bounds__(64) void k_cov_build(
         if (forms & FC_FORM_FP64) {
             double *Wq = W64 + q * ((int64_t)N * (N + 1) / 2);
             if (c < N)
-                for (int r = c; r < N; ++r) Wq[tri_index(r, c)] = Wc[r * kLdsStride + c];
+                for (int r = c; r < N; ++r) Wq[tri_index(r, c)] = wget(A, r, c);
         }
         if (forms & FC_FORM_FP32) {
             // A register v, lane i = 4 X + m: pair t = 16 v + X, i.e. padded
@@ -169,7 +198,7 @@ __global__ __launch_bounds__(64) void k_cov_build(
                 if (t < np) {
                     const int kp = fp32_pair_kp(ns, t), b = fp32_pair_b(ns, t);
                     const int rr = 4 * b + m - P, cc = kp - P;
-                    if (rr >= 0 && rr < N && cc >= 0 && cc <= rr) val = (float)Wc[rr * kLdsStride + cc];
+                    if (rr >= 0 && rr < N && cc >= 0 && cc <= rr) val = (float)wget(A, rr, cc);
                 }
                 Wq[((v >> 2) * 64 + i) * 4 + (v & 3)] = val;
             }
@@ -180,18 +209,19 @@ __global__ __launch_bounds__(64) void k_cov_build(
                 Sp[i] = (i < N) ? (float)Sq[i] : 0.0f;
                 const int rr = i - P;
                 double cv = 0.0;
-                if (rr >= 0 && rr < N)
-                    for (int kk = 0; kk <= rr; ++kk)
-                        cv -= Wc[rr * kLdsStride + kk] * (Sq[kk] - (double)(float)Sq[kk]);
+                if (rr >= 0 && rr < N) {
+#pragma unroll 4
+                    for (int kk = 0; kk <= rr; ++kk) cv -= wget(A, rr, kk) * sdl[kk];
+                }
                 Sp[64 + i] = (float)cv;
             }
         }
         if (forms & (FC_FORM_SPLIT_BF16 | FC_FORM_SPLIT_FP16)) {
             const int64_t sru = split_rec_units(split_nk(N), split_nb(N));
             if (forms & FC_FORM_SPLIT_BF16)
-                write_split_record<false>(Wc, Sq, off, N, 0, RB16 + q * sru);
+                write_split_record<false>(A, sdo, N, 0, RB16 + q * sru);
             if (forms & FC_FORM_SPLIT_FP16)
-                write_split_record<true>(Wc, Sq, off, N, ed16, RH16 + q * sru);
+                write_split_record<true>(A, sdo, N, ed16, RH16 + q * sru);
         }
         __syncthreads();
     }
