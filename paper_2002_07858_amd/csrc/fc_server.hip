@@ -2,11 +2,14 @@
 //
 // Requests (one true point of one resident grid, K universes) are admitted in
 // arrival order while their device memory fits a fixed arena.  A scheduler
-// thread keeps at most two batched launches queued per bin-count class; each
+// thread keeps at most two batched launches in flight per bin-count class; each
 // launch is a persistent-style kernel over a table of work items (a tile of
-// universes x a range of grid points) drawn round-robin from every admitted
-// request of that class, so requests that arrive while others run join the
-// next launch and share the device with them.  The device work per
+// universes x a range of grid points) drawn from every admitted request of that
+// class, so requests that arrive while others run join the next launch and
+// share the device with them.  The two launch slots of a class run on two
+// streams, so the next launch's blocks take the CUs that the current one's
+// last items leave idle; a request's results are finalised once every launch
+// holding its items has ended.  The device work per
 // (universe, grid point) is the same code as fc_scan, and the running minimum
 // is merged with an order-independent atomicMin, so a request's results do
 // not depend on the mix it ran in.
@@ -130,7 +133,9 @@ struct Req {
 
 struct Cls {
     int ns = 0, nk = 0, nb = 0, N = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t lst[2] = {nullptr, nullptr};   // stream of each launch slot
+    hipEvent_t ev_admit[2] = {nullptr, nullptr};  // after the latest admission on lst[k]
+    bool admit_wait[2] = {false, false};  // slot k must wait for ev_admit[k ^ 1]
     fcx::ScanItem *d_items[2] = {nullptr, nullptr};
     fcx::ScanItem *h_items[2] = {nullptr, nullptr};
     int *d_counter[2] = {nullptr, nullptr};
@@ -246,16 +251,21 @@ bool fc_server::admit()
         r.seg = carve<int64_t>(dv, 2);
         r.pu = carve<int64_t>(dv, 2);
         Cls &c = classes[r.cls];
+        // admitted on the stream of the slot that launches next; the other
+        // slot waits for it before its next launch
+        const int a = c.next_slot;
+        hipStream_t ast = c.lst[a];
         hipError_t e;
         if ((e = hipMemcpyAsync(r.seg, r.h_seg, sizeof(int64_t) * 2, hipMemcpyHostToDevice,
-                                c.stream)) != hipSuccess ||
+                                ast)) != hipSuccess ||
             (e = hipMemcpyAsync(r.pu, r.h_pu, sizeof(int64_t) * 2, hipMemcpyHostToDevice,
-                                c.stream)) != hipSuccess ||
+                                ast)) != hipSuccess ||
             (e = r.drawn ? fcx::launch_gen_universes(grids[r.grid], 1, r.pu, r.seg, r.pu + 1,
-                                                     r.seed, r.K, r.d, nullptr, nullptr, c.stream)
+                                                     r.seed, r.K, r.d, nullptr, nullptr, ast)
                          : hipMemcpyAsync(r.d, r.h_d, sizeof(double) * (size_t)r.K * N,
-                                          hipMemcpyHostToDevice, c.stream)) != hipSuccess ||
-            (e = fcx::launch_init_keys(r.K, r.keys, r.chi2p, c.stream)) != hipSuccess ||
+                                          hipMemcpyHostToDevice, ast)) != hipSuccess ||
+            (e = fcx::launch_init_keys(r.K, r.keys, r.chi2p, ast)) != hipSuccess ||
+            (e = hipEventRecord(c.ev_admit[a], ast)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&r.ev_done, hipEventDisableTiming)) != hipSuccess) {
             device_error = true;
             error_msg = std::string("fc_server: admission: ") + hipGetErrorString(e);
@@ -265,6 +275,7 @@ bool fc_server::admit()
         }
         r.state = FC_REQ_RUNNING;
         r.q_next = 0;
+        c.admit_wait[a ^ 1] = true;
         c.active.push_back(r.id);
         queue.pop_front();
         progress = true;
@@ -342,42 +353,63 @@ bool fc_server::launch(Cls &c)
 
     hipError_t e;
     const int blocks = n < c.slots ? n : c.slots;
+    hipStream_t st = c.lst[slot];
+    // admissions made on the other slot's stream (universes uploaded or drawn,
+    // keys initialised) come first
+    if (c.admit_wait[slot]) {
+        if ((e = hipStreamWaitEvent(st, c.ev_admit[slot ^ 1], 0)) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu);
+            device_error = true;
+            error_msg = std::string("fc_server: wait: ") + hipGetErrorString(e);
+            return false;
+        }
+        c.admit_wait[slot] = false;
+    }
     if ((e = hipMemcpyAsync(c.d_items[slot], items, sizeof(fcx::ScanItem) * n,
-                            hipMemcpyHostToDevice, c.stream)) != hipSuccess ||
-        (e = hipMemsetAsync(c.d_counter[slot], 0, sizeof(int), c.stream)) != hipSuccess ||
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemsetAsync(c.d_counter[slot], 0, sizeof(int), st)) != hipSuccess ||
         (e = (form == FC_FORM_FP32)
-                 ? fcx::launch_serve_fp32(c.N, c.d_items[slot], n, c.d_counter[slot], blocks,
-                                          c.stream)
+                 ? fcx::launch_serve_fp32(c.N, c.d_items[slot], n, c.d_counter[slot], blocks, st)
                  : fcx::launch_serve_split(c.nk, c.nb, form == FC_FORM_SPLIT_FP16,
                                            c.d_items[slot], n, c.d_counter[slot], blocks,
-                                           c.stream)) != hipSuccess) {
+                                           st)) != hipSuccess) {
         std::lock_guard<std::mutex> lk(mu);
         device_error = true;
         error_msg = std::string("fc_server: launch: ") + hipGetErrorString(e);
         return false;
     }
     // requests whose last items are in this launch: finalize, critical values,
-    // copy back (stream order puts all of their items before this)
+    // copy back.  Their earlier items are in earlier launches of this stream
+    // (stream order) or in the other slot's launches: wait for the latest of
+    // those if it may still run.
+    const int other = slot ^ 1;
+    if (!completing.empty() && c.busy[other] &&
+        (e = hipStreamWaitEvent(st, c.ev[other], 0)) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(mu);
+        device_error = true;
+        error_msg = std::string("fc_server: wait: ") + hipGetErrorString(e);
+        return false;
+    }
     for (Req *r : completing) {
         const size_t K = (size_t)r->K;
         if ((e = fcx::launch_finalize(r->K, nullptr, r->keys, reinterpret_cast<double *>(r->keys),
-                                      r->argmin, r->chi2p, r->dchi2, c.stream, r->p)) !=
+                                      r->argmin, r->chi2p, r->dchi2, st, r->p)) !=
                 hipSuccess ||
             (e = fcx::launch_crit(1, r->seg, r->dchi2, n_alpha, alpha, r->crit, n_bins, hist_hi,
-                                  r->hist, c.stream)) != hipSuccess ||
+                                  r->hist, st)) != hipSuccess ||
             (e = hipMemcpyAsync(r->h_dchi2, r->dchi2, sizeof(double) * K, hipMemcpyDeviceToHost,
-                                c.stream)) != hipSuccess ||
+                                st)) != hipSuccess ||
             (e = hipMemcpyAsync(r->h_cmin, r->keys, sizeof(double) * K, hipMemcpyDeviceToHost,
-                                c.stream)) != hipSuccess ||
+                                st)) != hipSuccess ||
             (e = hipMemcpyAsync(r->h_chi2p, r->chi2p, sizeof(double) * K, hipMemcpyDeviceToHost,
-                                c.stream)) != hipSuccess ||
+                                st)) != hipSuccess ||
             (e = hipMemcpyAsync(r->h_argmin, r->argmin, sizeof(int64_t) * K,
-                                hipMemcpyDeviceToHost, c.stream)) != hipSuccess ||
+                                hipMemcpyDeviceToHost, st)) != hipSuccess ||
             (e = hipMemcpyAsync(r->h_crit, r->crit, sizeof(double) * n_alpha,
-                                hipMemcpyDeviceToHost, c.stream)) != hipSuccess ||
+                                hipMemcpyDeviceToHost, st)) != hipSuccess ||
             (e = hipMemcpyAsync(r->h_hist, r->hist, sizeof(int64_t) * (n_bins + 1),
-                                hipMemcpyDeviceToHost, c.stream)) != hipSuccess ||
-            (e = hipEventRecord(r->ev_done, c.stream)) != hipSuccess) {
+                                hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipEventRecord(r->ev_done, st)) != hipSuccess) {
             std::lock_guard<std::mutex> lk(mu);
             device_error = true;
             error_msg = std::string("fc_server: finish: ") + hipGetErrorString(e);
@@ -385,7 +417,7 @@ bool fc_server::launch(Cls &c)
         }
         r->finishing = true;
     }
-    if ((e = hipEventRecord(c.ev[slot], c.stream)) != hipSuccess) {
+    if ((e = hipEventRecord(c.ev[slot], st)) != hipSuccess) {
         std::lock_guard<std::mutex> lk(mu);
         device_error = true;
         error_msg = std::string("fc_server: event: ") + hipGetErrorString(e);
@@ -556,8 +588,9 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
                 if (c.h_items[k]) (void)hipHostFree(c.h_items[k]);
                 if (c.d_counter[k]) (void)hipFree(c.d_counter[k]);
                 if (c.ev[k]) (void)hipEventDestroy(c.ev[k]);
+                if (c.ev_admit[k]) (void)hipEventDestroy(c.ev_admit[k]);
+                if (c.lst[k]) (void)hipStreamDestroy(c.lst[k]);
             }
-            if (c.stream) (void)hipStreamDestroy(c.stream);
         }
         if (s->dev_base) (void)hipFree(s->dev_base);
         if (s->host_base) (void)hipHostFree(s->host_base);
@@ -571,8 +604,11 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
     s->dev_arena.init(hbm_budget);
     s->host_arena.init(host_budget);
     for (Cls &c : s->classes) {
-        if ((e = hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking)) != hipSuccess)
-            return cleanup_fail("fc_server_create: stream");
+        for (int k = 0; k < 2; ++k)
+            if ((e = hipStreamCreateWithFlags(&c.lst[k], hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&c.ev_admit[k], hipEventDisableTiming)) !=
+                    hipSuccess)
+                return cleanup_fail("fc_server_create: stream");
         for (int k = 0; k < 2; ++k) {
             if ((e = hipMalloc(&c.d_items[k], sizeof(fcx::ScanItem) * kMaxItems)) != hipSuccess ||
                 (e = hipHostMalloc(reinterpret_cast<void **>(&c.h_items[k]),
@@ -715,14 +751,16 @@ void fc_server_destroy(fc_server *s)
     }
     if (s->worker.joinable()) s->worker.join();
     for (Cls &c : s->classes) {
-        if (c.stream) (void)hipStreamSynchronize(c.stream);
+        for (int k = 0; k < 2; ++k)
+            if (c.lst[k]) (void)hipStreamSynchronize(c.lst[k]);
         for (int k = 0; k < 2; ++k) {
             if (c.d_items[k]) (void)hipFree(c.d_items[k]);
             if (c.h_items[k]) (void)hipHostFree(c.h_items[k]);
             if (c.d_counter[k]) (void)hipFree(c.d_counter[k]);
             if (c.ev[k]) (void)hipEventDestroy(c.ev[k]);
+            if (c.ev_admit[k]) (void)hipEventDestroy(c.ev_admit[k]);
+            if (c.lst[k]) (void)hipStreamDestroy(c.lst[k]);
         }
-        if (c.stream) (void)hipStreamDestroy(c.stream);
     }
     for (auto &kv : s->reqs)
         if (kv.second->ev_done) (void)hipEventDestroy(kv.second->ev_done);

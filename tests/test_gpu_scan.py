@@ -277,6 +277,38 @@ def test_bitwise_determinism_and_batch_invariance(fc, form):
         np.testing.assert_array_equal(a[k][sub], c[k])
 
 
+def test_fp64_chunked_and_single_chunk_paths_agree(fc):
+    """The FP64 form splits the grid into chunks (merged in grid order) when K
+    is small and scans it in one pass when K is large: 140 000 universes take
+    the one-pass path, a 1000-universe subset the chunked one, and every
+    output agrees bit for bit; sampled universes against the oracle."""
+    rng = np.random.default_rng(77)
+    G, N, K = 37, 8, 140_000
+    S = rng.uniform(50, 300, size=(G, N))
+    A = rng.normal(size=(N, 2 * N))
+    W = A @ A.T
+    dw = np.sqrt(np.diag(W))
+    F = 0.5 * ((W / np.outer(dw, dw)) + (W / np.outer(dw, dw)).T) * 0.01
+    p = rng.integers(0, G, K)
+    d = S[p] + rng.normal(size=(K, N)) * np.sqrt(S[p])
+    d[[5, 70_000]] = S[[3, 30]]                       # unfluctuated, on-grid universes
+    p[[5, 70_000]] = [3, 30]
+    g = fc.fc_build_grid([np.arange(float(G))], S)
+    fc.fc_build_covariance(g, F, forms=1)
+    big = run_scan(fc, g, 1, d, p)
+    sub = np.r_[0:500, 69_800:70_300]
+    small = run_scan(fc, g, 1, d[sub], p[sub])
+    g.destroy()
+    for k in big:
+        np.testing.assert_array_equal(big[k][sub], small[k], err_msg=k)
+    assert big["dchi2"][5] == 0.0 and big["dchi2"][70_000] == 0.0
+    idx = np.r_[0:40, 69_990:70_010, K - 40:K]
+    ref = oracle.scan(S, F, d[idx], p[idx])
+    rep = parity.report({k: v[idx] for k, v in big.items()}, ref, parity.TOL["fp64"])
+    assert rep["e_rel"] <= parity.TOL["fp64"], rep
+    assert rep["argmin_agree"] == 1.0, rep
+
+
 # ---------------------------------------------------------------------------
 # critical values and histograms
 # ---------------------------------------------------------------------------
