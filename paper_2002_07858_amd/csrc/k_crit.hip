@@ -96,19 +96,43 @@ __global__ __launch_bounds__(256) void k_crit(const int64_t *__restrict__ seg_lo
                 if ((key & himask) == prefix[a]) atomicAdd(&cnt[a][digit], 1u);
         }
         __syncthreads();
-        if (tid < n_alpha) {
-            long long r = rank[tid];
-            unsigned int dsel = 255;
-            for (unsigned int dg = 0; dg < 256; ++dg) {
-                const long long c = cnt[tid][dg];
-                if (r < c) {
-                    dsel = dg;
-                    break;
-                }
-                r -= c;
+        // digit of rank r: one wave per fraction, lane l holding digits 4l..4l+3;
+        // a prefix sum over the lanes finds the lane whose digits cover r
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int a = wave; a < n_alpha; a += 4) {
+            const long long r = rank[a];
+            const long long c0 = cnt[a][4 * lane], c1 = cnt[a][4 * lane + 1],
+                            c2 = cnt[a][4 * lane + 2], c3 = cnt[a][4 * lane + 3];
+            const long long own = c0 + c1 + c2 + c3;
+            long long incl = own;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const long long up = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += up;
             }
-            rank[tid] = r;
-            prefix[tid] |= ((unsigned long long)dsel) << shift;
+            const long long excl = incl - own;
+            const long long total = __shfl(incl, 63, 64);
+            if (excl <= r && r < incl) {
+                long long rr = r - excl;
+                unsigned int d = 4 * lane;
+                if (rr >= c0) {
+                    rr -= c0;
+                    ++d;
+                    if (rr >= c1) {
+                        rr -= c1;
+                        ++d;
+                        if (rr >= c2) {
+                            rr -= c2;
+                            ++d;
+                        }
+                    }
+                }
+                rank[a] = rr;
+                prefix[a] |= ((unsigned long long)d) << shift;
+            } else if (lane == 63 && r >= total) {  // not reached for a consistent count
+                rank[a] = r - total;
+                prefix[a] |= 255ull << shift;
+            }
         }
         __syncthreads();
     }
