@@ -117,3 +117,34 @@ def test_critical_value_validation(fcmod):
 def test_binding_refuses_host_arrays(fcmod):
     with pytest.raises(TypeError):
         fcmod._dev(np.zeros(3), "f64", "d")
+
+
+def test_slice_entry_points_validate_on_host(fcmod):
+    """Grid-sliced scans: argument errors are reported before any device work."""
+    L = fcmod.lib()
+    assert L.fc_scan_state_init(-1, None, None, None) == fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_scan_state_init((1 << 30) + 1, None, None, None) == fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_scan_state_init(0, None, None, None) == fcmod.FC_OK        # nothing to do
+    assert L.fc_scan_state_init(5, None, None, None) == fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_scan_slice(None, 2, 10, None, None, 0, 1, None, None, None) == \
+        fcmod.FC_ERR_INVALID_ARG
+    assert "grid is NULL" in fcmod.fc_last_error()
+    assert L.fc_scan_points_slice(None, 2, 1, None, None, 10, None, 0, 1, None, 0, None, None,
+                                  None) == fcmod.FC_ERR_INVALID_ARG
+    b = ctypes.c_size_t(7)
+    assert L.fc_scan_points_slice_workspace(None, 2, 1, 10, 1, ctypes.byref(b)) == \
+        fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_scan_state_finalize(None, 10, None, None, None, None, None, None, None) == \
+        fcmod.FC_ERR_INVALID_ARG
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark runs on one GPU; asked for more it exits with a message."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
