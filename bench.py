@@ -145,6 +145,7 @@ def cpu_baseline(pr, per_point: int, dev_out: dict, tol: float):
     c_dev, _ = oracle.critical_value(dev_out["dchi2"][idx], seg, ALPHA, with_hist=False)
     c_ref, _ = oracle.critical_value(ref["dchi2"], seg, ALPHA, with_hist=False)
     rep["crit_abs_err_sample"] = float(np.abs(c_dev - c_ref).max())
+    rep["_sample"] = (idx, ref)   # reused by the split-form leg, removed before printing
     base = {"value": evals / dt, "unit": "evals/s", "cores": nt, "kind": "oracle",
             "sample": f"first {min(per_point, int(pr.seg_off[1]))} universes of each of the {len(pr.seg_off) - 1} true "
                       f"points x all {pr.G} grid points ({evals:.3g} evals, {dt:.1f} s, "
@@ -418,6 +419,49 @@ def shard_bench(fc, grid, form, form_name, scan_entry, pr, d_t, p_t, pts_t, so_t
             "merged_equals_one_call": equal}
 
 
+# ---------------------------------------------------------------------------
+# The split hi+lo forms on the same inputs: scan time (HIP events, grouped
+# entry), 16-bit MFMA and FP32-equivalent fractions, and the error on the
+# CPU-baseline sample.
+# ---------------------------------------------------------------------------
+def split_leg(fc, grid, pr, pts_t, so_t, d_t, sample, steps=3):
+    import torch
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import parity
+    K, G, N = pr.K, pr.G, pr.N
+    out = {}
+    o = {k: torch.empty(K, dtype=torch.float64, device="cuda") for k in ("dchi2", "chi2_min",
+                                                                       "chi2_p")}
+    o["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for name, form in (("split_fp16", fc.FC_FORM_SPLIT_FP16), ("split_bf16", fc.FC_FORM_SPLIT_BF16)):
+        fc.fc_build_covariance(grid, pr.F, pr.stat_mode, pr.stat_diag, forms=form)
+        ws = torch.empty(fc.fc_scan_points_workspace(grid, form, int(so_t.numel()) - 1, K),
+                         dtype=torch.uint8, device="cuda")
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for i in range(steps + 1):          # the first pass is a warm-up
+            ev0.record(stream)
+            fc.fc_scan_points(grid, form, pts_t, so_t, d_t, o["dchi2"], o["chi2_min"],
+                              o["argmin"], o["chi2_p"], workspace=ws)
+            ev1.record(stream)
+            ev1.synchronize()
+            if i:
+                ms.append(ev0.elapsed_time(ev1))
+        t = float(np.mean(ms)) * 1e-3
+        r = {"scan_ms": t * 1e3, "evals_per_s": K * G / t,
+             "mfma16_frac": K * G * split_flop_per_eval(N) / t / PEAK[name],
+             "fp32_equivalent_frac": K * G * flop_per_eval(N) / t / PEAK["fp32"]}
+        if sample is not None:
+            idx, ref = sample
+            dev = {k: v.cpu().numpy()[idx] for k, v in o.items()}
+            e = parity.report(dev, ref, TOL[name])
+            r.update({"e_rel": e["e_rel"], "argmin_agree": e["argmin_agree"],
+                      "near_tie_frac": e["near_tie_frac"]})
+        out[name] = r
+    return out
+
+
 def device_record():
     """The device and software the line was measured on, and the peak
     denominators of the roofline fractions."""
@@ -458,6 +502,10 @@ def main():
                     help="1: also run the one-matrix scan leg (default on for c2)")
     ap.add_argument("--region", type=int, default=None,
                     help="1: also run the full-surface region leg (default on for c2)")
+    ap.add_argument("--split-leg", type=int, default=None,
+                    help="also time the split BF16/FP16 forms on the same inputs, with their "
+                         "error on the CPU-baseline sample (default: c2 only; skipped without "
+                         "the CPU baseline)")
     ap.add_argument("--shards", type=int, default=8,
                     help="grid-sharding leg: slices of the grid scanned by separate calls "
                          "(0: off; not for the fp64 form)")
@@ -481,6 +529,8 @@ def main():
         args.region = 1 if args.workload == "c2" else 0
     if args.fixed is None:
         args.fixed = 1 if args.workload == "c2" else 0
+    if args.split_leg is None:
+        args.split_leg = 1 if args.workload == "c2" else 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the scan is "
               "single-GPU by design; see the multi-GPU section of the design notes.",
@@ -610,10 +660,14 @@ def main():
         base, rep = cpu_baseline(pr, args.cpu_per_point, dev_out, TOL[args.form])
         res["cpu_baseline"] = base
         res["err_vs_fp64"] = rep
+    sample = res.get("err_vs_fp64", {}).pop("_sample", None)
     if args.shards > 0 and args.form != "fp64":
         log(f"[bench] grid sharding leg ({args.shards} slices)")
         res["grid_shard"] = shard_bench(fc, grid, form, args.form, args.scan, pr, d_t, p_t, pts_t,
                                         so_t, outs, args.shards)
+    if args.split_leg and args.form == "fp32" and sample is not None:
+        log("[bench] split-form leg")   # rebuilds the grid's records in the split forms
+        res["split_forms"] = split_leg(fc, grid, pr, pts_t, so_t, d_t, sample)
     grid.destroy()
     if args.fixed:
         log("[bench] one-matrix scan")
