@@ -213,6 +213,7 @@ int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t 
  * fc_scan_points_workspace -- bytes of workspace fc_scan_points needs for
  * (form, n_pts, K) on this grid: 8 K (+ alignment) and, for the FP32 form,
  * 16 ns n_pts G for the offset table (C2: 256 points: 614 MB).
+ * FC_ERR_INVALID_ARG if that is beyond 2^60 bytes.
  */
 int fc_scan_points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K,
                              size_t *bytes);

@@ -327,6 +327,11 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // [n_pts][nq][4 ns] FP32.
 size_t points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int64_t K, int64_t nq)
 {
+    // a size past 2^60 bytes (no device holds it) is reported as SIZE_MAX
+    // rather than wrapped around
+    const double table =
+        (form == FC_FORM_FP32) ? 4.0 * (double)n_pts * (double)nq * 4.0 * (double)g->ns : 0.0;
+    if (8.0 * (double)K + table > 1.152921504606847e18) return SIZE_MAX;
     size_t b = align256(sizeof(int64_t) * (size_t)K);
     if (form == FC_FORM_FP32)
         b += align256(sizeof(int64_t) * (size_t)(n_pts + 1)) +
@@ -361,6 +366,8 @@ int fc_scan_points_workspace(const fc_grid *g, int32_t form, int64_t n_pts, int6
     if (n_pts < 0 || K < 0 || n_pts > 0x7fffffff)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points_workspace: bad n_pts or K");
     *bytes = points_workspace(g, form, n_pts, K, g->G);
+    if (*bytes == SIZE_MAX)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_workspace: size beyond 2^60 bytes");
     return FC_OK;
 }
 
@@ -387,7 +394,7 @@ int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t 
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points: workspace not 256-byte aligned");
     const size_t need = points_workspace(g, form, n_pts, K, g->G);
-    if (workspace_bytes < need)
+    if (need == SIZE_MAX || workspace_bytes < need)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points: workspace %zu B < %zu B", workspace_bytes,
                     need);
     const PointsWs w = carve_points_ws(workspace, n_pts, K);
@@ -475,6 +482,8 @@ int fc_scan_points_slice_workspace(const fc_grid *g, int32_t form, int64_t n_pts
     if (n_pts < 0 || K < 0 || n_pts > 0x7fffffff || nq < 0 || nq > g->G)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice_workspace: bad n_pts, K or nq");
     *bytes = points_workspace(g, form, n_pts, K, nq);
+    if (*bytes == SIZE_MAX)
+        return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice_workspace: size beyond 2^60 bytes");
     return FC_OK;
 }
 
@@ -496,7 +505,7 @@ int fc_scan_points_slice(const fc_grid *g, int32_t form, int64_t n_pts, const in
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice: workspace not 256-byte aligned");
     const size_t need = points_workspace(g, form, n_pts, K, nq);
-    if (workspace_bytes < need)
+    if (need == SIZE_MAX || workspace_bytes < need)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points_slice: workspace %zu B < %zu B",
                     workspace_bytes, need);
     const PointsWs w = carve_points_ws(workspace, n_pts, K);
