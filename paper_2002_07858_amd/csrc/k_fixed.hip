@@ -176,12 +176,15 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
         av[c] = in ? a[r] : 0.0;
         pv[c] = in ? (int32_t)p_of_row[r] : -1;
     }
-    double best[4];
+    double best[4], cpv[4];
     int32_t bq[4];
+    bool hasp[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         best[c] = __builtin_inf();
         bq[c] = INT32_MAX;
+        cpv[c] = 0.0;
+        hasp[c] = false;
     }
 
     // the t tile of grid points q0 .. q0+63 (and their b) into LDS with
@@ -190,14 +193,26 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
     const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
     auto stage = [&](uint4 *tdst, uint4 *bdst, int64_t q0) {
         const uint4 *src = reinterpret_cast<const uint4 *>(Tm + q0 * NP);
+        if (q0 + kFxTile <= qe) {  // uniform: a whole tile, no per-row check
 #pragma unroll
-        for (int c = 0; c < TC; ++c) {
-            const int unit = c * kFxThreads + tid;
-            if (unit < TU && q0 + unit / (NP / 2) < qe)
-                __builtin_amdgcn_global_load_lds(
-                    (const void *)(src + unit),
-                    (__attribute__((address_space(3))) void *)(tdst + c * kFxThreads + wbase), 16,
-                    0, 0);
+            for (int c = 0; c < TC; ++c) {
+                const int unit = c * kFxThreads + tid;
+                if (unit < TU)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(src + unit),
+                        (__attribute__((address_space(3))) void *)(tdst + c * kFxThreads + wbase),
+                        16, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < TC; ++c) {
+                const int unit = c * kFxThreads + tid;
+                if (unit < TU && q0 + unit / (NP / 2) < qe)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(src + unit),
+                        (__attribute__((address_space(3))) void *)(tdst + c * kFxThreads + wbase),
+                        16, 0, 0);
+            }
         }
         // b in pairs of rows (rows are padded so a pair may pass qe)
         if (tid < kFxTile / 2 && q0 + 2 * tid < qe)
@@ -244,7 +259,10 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const double v = (av[c] + bqv) - 2.0 * acc[c][j];
-                    if (q == pv[c]) cp[td.r0 + 16 * c + col] = v;
+                    if (q == pv[c]) {  // kept in registers, stored once after the loop
+                        cpv[c] = v;
+                        hasp[c] = true;
+                    }
                     if (v < best[c]) {
                         best[c] = v;
                         bq[c] = q;
@@ -256,6 +274,9 @@ __global__ __launch_bounds__(kFxThreads) __attribute__((amdgpu_waves_per_eu(2)))
         __syncthreads();
         buf ^= 1;
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        if (hasp[c]) cp[td.r0 + 16 * c + col] = cpv[c];
     // minimum over the 4 lane groups (rows) of each wave, then over waves;
     // ties go to the lower q
 #pragma unroll
