@@ -341,7 +341,7 @@ def test_critical_values_edge_distributions(fc):
              np.array([-0.0, 0.0, 2.0, 60.0, 49.999999]), rng.chisquare(3, size=20000)]
     x = np.concatenate(parts)
     off = np.concatenate([[0], np.cumsum([len(p) for p in parts])])
-    alphas = [1e-9, 0.5, 0.6827, 0.9, 0.95, 0.99, 1.0]
+    alphas = [1e-9, 0.5, 0.6827, 0.9, 0.95, 0.99, 1.0, 0.25]   # the maximum of 8 fractions
     crit = torch.empty((len(parts), len(alphas)), dtype=torch.float64, device="cuda")
     hist = torch.empty((len(parts), 51), dtype=torch.int64, device="cuda")
     fc.fc_critical_value(to_dev(off, torch.int64), to_dev(x, torch.float64), alphas, crit, 50,
