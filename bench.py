@@ -220,7 +220,11 @@ def run_batched(fc, grids, reqs, arrivals, form, policy):
     th = threading.Thread(target=submitter)
     th.start()
     lat = {}
+    hbm_peak, t_stat = 0, 0.0
     while len(lat) < len(reqs):
+        if time.perf_counter() - t_stat > 0.01:   # request data resident in HBM
+            hbm_peak = max(hbm_peak, server.stats()["hbm_in_use"])
+            t_stat = time.perf_counter()
         for k, i in enumerate(ids):
             if i is None or k in lat:
                 continue
@@ -236,14 +240,24 @@ def run_batched(fc, grids, reqs, arrivals, form, policy):
     wall = time.perf_counter() - t0
     st = server.stats()
     server.destroy()
-    return [lat[k] for k in range(len(reqs))], wall, st["evals"], st["launches"]
+    return [lat[k] for k in range(len(reqs))], wall, st["evals"], st["launches"], hbm_peak
 
 
-def summarize(lat, wall, evals, n):
-    a = np.sort(np.asarray(lat)) * 1e3
-    return {"p50_ms": float(np.percentile(a, 50)), "p99_ms": float(np.percentile(a, 99)),
-            "mean_ms": float(a.mean()), "throughput_req_s": n / wall,
-            "evals_per_s": evals / wall}
+GRID_NAMES = ("20x20 N=38", "100x100 N=57", "60^3 N=57")
+
+
+def summarize(lat, wall, evals, n, grid_of=None):
+    a = np.asarray(lat) * 1e3
+    out = {"p50_ms": float(np.percentile(a, 50)), "p99_ms": float(np.percentile(a, 99)),
+           "mean_ms": float(a.mean()), "throughput_req_s": n / wall,
+           "evals_per_s": evals / wall}
+    if grid_of is not None:  # latency per grid class
+        gi = np.asarray(grid_of)
+        out["per_grid"] = {GRID_NAMES[k]: {"n": int((gi == k).sum()),
+                                           "p50_ms": float(np.percentile(a[gi == k], 50)),
+                                           "p99_ms": float(np.percentile(a[gi == k], 99))}
+                           for k in range(len(GRID_NAMES)) if (gi == k).any()}
+    return out
 
 
 def serving_bench(n_req: int, loads=(0.8,)):
@@ -261,7 +275,8 @@ def serving_bench(n_req: int, loads=(0.8,)):
     n_cap = min(40, n_req)
     lat, wall, _ = run_plain(fc, grids, reqs[:n_cap], [0.0] * n_cap)
     capacity = n_cap / wall
-    out = {"requests": n_req, "grids": ["20x20 N=38", "100x100 N=57", "60^3 N=57"],
+    out = {"requests": n_req, "grids": list(GRID_NAMES),
+           "grid_hbm_bytes": [int(fc.fc_grid_device_bytes(g)) for _, g in grids],
            "K": "log-uniform [500, 20000]", "plain_capacity_req_s": capacity, "loads": {}}
     rng = fcgen.rng_for(4, 3, 1)
     gaps = rng.exponential(1.0, size=n_req)
@@ -270,15 +285,17 @@ def serving_bench(n_req: int, loads=(0.8,)):
         arrivals = np.cumsum(gaps / lam) - gaps[0] / lam
         log(f"[bench] serving load {load}: lambda {lam:.1f}/s")
         res = {"lambda_req_s": lam}
+        grid_of = [r[0] for r in reqs]
         lat, wall, ev = run_plain(fc, grids, reqs, arrivals)
-        res["plain_fp32"] = summarize(lat, wall, ev, n_req)
+        res["plain_fp32"] = summarize(lat, wall, ev, n_req, grid_of)
         for name, form, policy in (
                 ("batched_fp32_fifo", fc.FC_FORM_FP32, fc.FC_SCHED_FIFO),
                 ("batched_fp32_fair", fc.FC_FORM_FP32, fc.FC_SCHED_FAIR),
                 ("batched_split_fp16_fifo", fc.FC_FORM_SPLIT_FP16, fc.FC_SCHED_FIFO)):
-            lat, wall, ev, launches = run_batched(fc, grids, reqs, arrivals, form, policy)
-            res[name] = summarize(lat, wall, ev, n_req)
+            lat, wall, ev, launches, hbm = run_batched(fc, grids, reqs, arrivals, form, policy)
+            res[name] = summarize(lat, wall, ev, n_req, grid_of)
             res[name]["launches"] = launches
+            res[name]["request_hbm_peak_bytes"] = hbm
         out["loads"][str(load)] = res
     for _, g in grids:
         g.destroy()
