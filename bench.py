@@ -286,12 +286,14 @@ def serving_bench(n_req: int, loads=(0.8,)):
         log(f"[bench] serving load {load}: lambda {lam:.1f}/s")
         res = {"lambda_req_s": lam}
         grid_of = [r[0] for r in reqs]
+        log("[bench]   plain_fp32")
         lat, wall, ev = run_plain(fc, grids, reqs, arrivals)
         res["plain_fp32"] = summarize(lat, wall, ev, n_req, grid_of)
         for name, form, policy in (
                 ("batched_fp32_fifo", fc.FC_FORM_FP32, fc.FC_SCHED_FIFO),
                 ("batched_fp32_fair", fc.FC_FORM_FP32, fc.FC_SCHED_FAIR),
                 ("batched_split_fp16_fifo", fc.FC_FORM_SPLIT_FP16, fc.FC_SCHED_FIFO)):
+            log(f"[bench]   {name}")
             lat, wall, ev, launches, hbm = run_batched(fc, grids, reqs, arrivals, form, policy)
             res[name] = summarize(lat, wall, ev, n_req, grid_of)
             res[name]["launches"] = launches
