@@ -76,10 +76,10 @@ FP32_SOURCES = ("paper_2002_07858_amd/csrc/k_scan.hip", "paper_2002_07858_amd/cs
 SPLIT_SOURCES = ("paper_2002_07858_amd/csrc/k_scan_split.hip",
                  "paper_2002_07858_amd/csrc/fc_internal.h")
 TRAFFIC = {
-    ("c2", "fp32", "points"): {"bytes_per_launch": 7839467090, "source_hash": "9c6b8146bc171591",
+    ("c2", "fp32", "points"): {"bytes_per_launch": 7840002564, "source_hash": "7ddf1a367cb43521",
                                "sources": FP32_SOURCES,
                                "profile": "profiles/k_scan_fp32_pts_c2_counters.md"},
-    ("c2", "fp32", "universes"): {"bytes_per_launch": 14043728812, "source_hash": "9c6b8146bc171591",
+    ("c2", "fp32", "universes"): {"bytes_per_launch": 14261856235, "source_hash": "7ddf1a367cb43521",
                                   "sources": FP32_SOURCES,
                                   "profile": "profiles/k_scan_fp32_pts_c2_counters.md"},
     ("c2", "split_fp16", "universes"): {"bytes_per_launch": 10699201253,

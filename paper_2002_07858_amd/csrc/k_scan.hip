@@ -812,7 +812,7 @@ static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64
 // rounded once to FP32; rows of an out-of-range p are zero (such segments take
 // the residual form).  One block per grid point (grid-stride): the record's A
 // slices are expanded into the transposed dense factor W'^T in LDS (zero above
-// the diagonal), and each thread accumulates all 4 ns rows of one segment,
+// the diagonal), and each thread accumulates one 4-row block of one segment,
 // bin by bin, from float4 columns of W'^T.
 template <int N>
 __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ R32,
@@ -850,30 +850,26 @@ __global__ __launch_bounds__(256) void k_offset_table(const uint4 *__restrict__ 
             if (t < NP) wt[pk[t] * NR + 4 * pb[t] + (ln & 3)] = rec[f];
         }
         __syncthreads();
-        for (int64_t pt = tid; pt < n_pts; pt += blockDim.x) {
+        // one thread per (segment, 4-row block): few segments still use the
+        // whole block, and a row's sum runs over k' in ascending order
+        for (int64_t w = tid; w < n_pts * NS; w += blockDim.x) {
+            const int64_t pt = w / NS;
+            const int b = (int)(w - pt * NS);
             const int64_t pp = p[pt];
-            double acc[NR];
-#pragma unroll
-            for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
             if (pp >= 0 && pp < G) {
                 const double *sp = S64 + pp * N - P;
                 for (int kp = P; kp < NR; ++kp) {
                     const double dk = sp[kp] - Sq[kp];
-#pragma unroll
-                    for (int b = 0; b < NS; ++b) {
-                        const float4 w = Wt[kp * NS + b];
-                        acc[4 * b] = fma((double)w.x, dk, acc[4 * b]);
-                        acc[4 * b + 1] = fma((double)w.y, dk, acc[4 * b + 1]);
-                        acc[4 * b + 2] = fma((double)w.z, dk, acc[4 * b + 2]);
-                        acc[4 * b + 3] = fma((double)w.w, dk, acc[4 * b + 3]);
-                    }
+                    const float4 wv = Wt[kp * NS + b];
+                    a0 = fma((double)wv.x, dk, a0);
+                    a1 = fma((double)wv.y, dk, a1);
+                    a2 = fma((double)wv.z, dk, a2);
+                    a3 = fma((double)wv.w, dk, a3);
                 }
             }
-            float4 *dst = reinterpret_cast<float4 *>(T + (pt * nq + j) * NR);
-#pragma unroll
-            for (int b = 0; b < NS; ++b)
-                dst[b] = make_float4((float)acc[4 * b], (float)acc[4 * b + 1], (float)acc[4 * b + 2],
-                                     (float)acc[4 * b + 3]);
+            reinterpret_cast<float4 *>(T + (pt * nq + j) * NR)[b] =
+                make_float4((float)a0, (float)a1, (float)a2, (float)a3);
         }
         __syncthreads();
     }
