@@ -464,9 +464,8 @@ static hipError_t fixed_round(const fc_grid *g, int64_t R, const std::vector<int
         const int64_t r_end = r, nr = r_end - r_begin, n_slots = (int64_t)slot_m.size();
         const int64_t n_tiles = (int64_t)tiles.size();
         // grid chunks: enough blocks to fill the chip, chunks of whole tiles
-        static int slots_res = 0;
-        if (slots_res == 0) slots_res = resident_slots(reinterpret_cast<const void *>(
-                                                           &k_fixed_min<15>), kFxThreads);
+        static const int slots_res =  // queried once (thread-safe)
+            resident_slots(reinterpret_cast<const void *>(&k_fixed_min<15>), kFxThreads);
         int n_chunks = (int)std::max<int64_t>(1, (4 * (int64_t)slots_res + n_tiles - 1) / n_tiles);
         const int64_t max_chunks = std::max<int64_t>(1, (G + kFxTile - 1) / kFxTile);
         n_chunks = (int)std::min<int64_t>(n_chunks, max_chunks);

@@ -741,10 +741,9 @@ static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, co
                                 int64_t q0, int64_t nq, unsigned long long *keys, double *chi2_p,
                                 hipStream_t st)
 {
-    static int slots = 0;  // per instantiation; same device model for the process
-    if (slots == 0)
-        slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32<N>),
-                               64 * kWavesPerBlock);
+    // resident block slots: queried once per instantiation (thread-safe)
+    static const int slots =
+        resident_slots(reinterpret_cast<const void *>(&k_scan_fp32<N>), 64 * kWavesPerBlock);
     const ScanGeometry sg = scan_geometry(K, nq, slots, kFp32UnivPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     hipLaunchKernelGGL((k_scan_fp32<N>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, st,
@@ -790,9 +789,9 @@ static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64
                                     int64_t nq, const float *T, int64_t *tile_start,
                                     unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
-    static int slots = 0;
-    if (slots == 0)
-        slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp32_pts<N>), kPtsTile);
+    // resident block slots: queried once per instantiation (thread-safe)
+    static const int slots =
+        resident_slots(reinterpret_cast<const void *>(&k_scan_fp32_pts<N>), kPtsTile);
     const int64_t max_tiles = K / kPtsTile + n_pts;  // bound on the dense tile count
     const int64_t groups_per_xcd = (max_tiles + 63) / 64;
     const int64_t n_tiles = 64 * groups_per_xcd;    // blocks per grid chunk
@@ -918,9 +917,9 @@ static hipError_t launch_serve_fp32_n(const ScanItem *items, int n_items, int *c
 template <int N>
 static int serve_slots_fp32_n()
 {
-    static int slots = 0;
-    if (slots == 0)
-        slots = resident_slots(reinterpret_cast<const void *>(&k_serve_fp32<N>), 256);
+    // resident block slots: queried once per instantiation (thread-safe)
+    static const int slots =
+        resident_slots(reinterpret_cast<const void *>(&k_serve_fp32<N>), 256);
     return slots;
 }
 
@@ -1016,8 +1015,9 @@ static hipError_t launch_fp64_np(const fc_grid *g, int64_t K, const double *d, c
                                  hipStream_t st)
 {
     if (K <= 0) return hipSuccess;
-    static int slots = 0;
-    if (slots == 0) slots = resident_slots(reinterpret_cast<const void *>(&k_scan_fp64<NP>), 64);
+    // resident block slots: queried once per instantiation (thread-safe)
+    static const int slots =
+        resident_slots(reinterpret_cast<const void *>(&k_scan_fp64<NP>), 64);
     // grid chunks so that tiles x chunks is about two rounds of the resident
     // slots; at most 256 chunks and 2^18 (chunk, universe) partials (4 MB)
     const int64_t n_utiles = (K + 63) / 64;

@@ -306,9 +306,9 @@ static hipError_t launch_split_t(const fc_grid *g, int64_t K, const double *d,
                                  unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
     constexpr int NC = kSplitColBlocks;
-    static int slots = 0;
-    if (slots == 0)
-        slots = resident_slots_split(reinterpret_cast<const void *>(&k_scan_split<NK, NB, NC, FP16>));
+    // resident block slots: queried once per instantiation (thread-safe)
+    static const int slots =
+        resident_slots_split(reinterpret_cast<const void *>(&k_scan_split<NK, NB, NC, FP16>));
     const ScanGeometry sg = scan_geometry(K, nq, slots, 16 * NC * kWavesPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     const uint4 *R = FP16 ? g->RH16 : g->RB16;
@@ -336,10 +336,10 @@ static hipError_t launch_split_f(const fc_grid *g, int64_t K, const double *d,
 template <int NK, int NB, bool FP16>
 static int serve_slots_split_t()
 {
-    static int slots = 0;
-    if (slots == 0)
-        slots = resident_slots_split(
-            reinterpret_cast<const void *>(&k_serve_split<NK, NB, kSplitColBlocks, FP16>));
+    // resident block slots: queried once per instantiation (thread-safe)
+    static const int slots =
+        resident_slots_split(reinterpret_cast<const void *>(
+            &k_serve_split<NK, NB, kSplitColBlocks, FP16>));
     return slots;
 }
 
