@@ -12,18 +12,28 @@
 // and column i during the inversion.  A non-positive (or NaN) pivot marks the
 // point as not positive definite.  L and W share one LDS matrix: L in the
 // lower triangle, W_q's column c transposed into the strict upper part of row
-// c and its diagonal into the spare column kMaxBins (33 KB per point, so four
-// points fit a CU's LDS at once).
+// c and its diagonal into a spare last column (28 KB per point at N = 57, so
+// five points fit a CU's LDS at once; 13 KB at N = 38).
 #include "fc_internal.h"
 
 namespace fcx {
 
-constexpr int kLdsStride = kMaxBins + 1;
+// Row stride of the LDS matrix: N + 1 rounded up to an odd count of doubles
+// (consecutive rows then start on different bank pairs); its last column holds
+// W_q's diagonal.
+__host__ __device__ inline int cov_ld(int N) { return (N + 1) | 1; }
+
+// LDS bytes of one point: the N x ld matrix, then column j of L, S_q - fl32(S_q)
+// and S_q - o.
+inline size_t cov_lds_bytes(int N)
+{
+    return sizeof(double) * ((size_t)N * cov_ld(N) + 3 * kMaxBins);
+}
 
 // W_q[r][c] (r >= c) from the shared matrix.
-__device__ inline double wget(const double *A, int r, int c)
+__device__ inline double wget(const double *A, int ld, int r, int c)
 {
-    return (r == c) ? A[c * kLdsStride + kMaxBins] : A[c * kLdsStride + r];
+    return (r == c) ? A[c * ld + ld - 1] : A[c * ld + r];
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -55,7 +65,8 @@ __device__ inline void split8(const float (&x)[8], uint4 &hi, uint4 &lo)
 
 // One split-form record (see fc_internal.h) from the FP64 factor in LDS.
 template <bool FP16>
-__device__ void write_split_record(const double *A, const double *sdo, int N, int ed, uint4 *rq)
+__device__ void write_split_record(const double *A, int ld, const double *sdo, int N, int ed,
+                                   uint4 *rq)
 {
     const int i = threadIdx.x;
     const int nk = split_nk(N), nb = split_nb(N);
@@ -64,7 +75,7 @@ __device__ void write_split_record(const double *A, const double *sdo, int N, in
     if constexpr (FP16) {
         double wm = 0.0;
         if (i < N)
-            for (int r = i; r < N; ++r) wm = fmax(wm, fabs(wget(A, r, i)));
+            for (int r = i; r < N; ++r) wm = fmax(wm, fabs(wget(A, ld, r, i)));
         for (int m = 32; m > 0; m >>= 1) wm = fmax(wm, __shfl_xor(wm, m));
         eq = (wm > 0.0) ? 13 - ilogb(wm) : 0;
     }
@@ -76,7 +87,7 @@ __device__ void write_split_record(const double *A, const double *sdo, int N, in
             float x[8];
             for (int e = 0; e < 8; ++e) {
                 const int cc = c0 + e;
-                x[e] = (rr < N && cc <= rr) ? (float)ldexp(wget(A, rr, cc), eq) : 0.0f;
+                x[e] = (rr < N && cc <= rr) ? (float)ldexp(wget(A, ld, rr, cc), eq) : 0.0f;
             }
             uint4 hi, lo;
             split8<FP16>(x, hi, lo);
@@ -91,7 +102,7 @@ __device__ void write_split_record(const double *A, const double *sdo, int N, in
         double u = 0.0;
         if (row < N) {
 #pragma unroll 4
-            for (int k = 0; k <= row; ++k) u += wget(A, row, k) * sdo[k];
+            for (int k = 0; k <= row; ++k) u += wget(A, ld, row, k) * sdo[k];
         }
         reinterpret_cast<float *>(rq + split_u_unit(nk, nb))[i] = (float)ldexp(-u, eq + ed);
     }
@@ -106,26 +117,27 @@ __global__ __launch_bounds__(64) void k_cov_build(
     int ed16, double *__restrict__ W64, uint4 *__restrict__ R32, uint4 *__restrict__ RB16,
     uint4 *__restrict__ RH16, unsigned long long *__restrict__ bad_q)
 {
-    __shared__ double A[kMaxBins * kLdsStride];
-    __shared__ double colj[kMaxBins];  // column j of L, read by the trailing update
-    __shared__ double sdl[kMaxBins];   // S_q - fl32(S_q)
-    __shared__ double sdo[kMaxBins];   // S_q - o
+    extern __shared__ double smem[];
+    const int ld = cov_ld(N);
+    // disjoint pieces of the block's LDS (restrict: the trailing update's loads
+    // of colj are not ordered behind its stores to A)
+    double *__restrict__ A = smem;               // [N][ld]: L, W^T above it, W's diagonal last
+    double *__restrict__ colj = A + N * ld;      // column j of L
+    double *__restrict__ sdl = colj + kMaxBins;  // S_q - fl32(S_q)
+    double *__restrict__ sdo = sdl + kMaxBins;   // S_q - o
     const int i = threadIdx.x;
-    // row i of F stays in registers for every grid point of this block
-    double frow[kMaxBins];
-#pragma unroll
-    for (int j = 0; j < kMaxBins; ++j) frow[j] = (i < N && j < N) ? F[i * N + j] : 0.0;
     const double stat_i = (i < N && stat_mode != FC_STAT_PEARSON) ? stat[i] : 0.0;
 
     for (int64_t q = blockIdx.x; q < G; q += gridDim.x) {
         const double *Sq = S64 + q * N;
         // ---- Sigma_q, row i ------------------------------------------------
         const double si = (i < N) ? Sq[i] : 0.0;
-#pragma unroll
-        for (int j = 0; j < kMaxBins; ++j)
-            if (j < N) A[i * kLdsStride + j] = frow[j] * (si * Sq[j]);
         if (i < N) {
-            A[i * kLdsStride + i] += (stat_mode == FC_STAT_PEARSON) ? si : stat_i;
+#pragma unroll 8
+            for (int j = 0; j < N; ++j) A[i * ld + j] = F[i * N + j] * (si * Sq[j]);
+        }
+        if (i < N) {
+            A[i * ld + i] += (stat_mode == FC_STAT_PEARSON) ? si : stat_i;
             sdl[i] = si - (double)(float)si;
             sdo[i] = si - off[i];
         }
@@ -134,7 +146,7 @@ __global__ __launch_bounds__(64) void k_cov_build(
         // ---- right-looking Cholesky ----------------------------------------
         bool ok = true;
         for (int j = 0; j < N; ++j) {
-            const double piv = A[j * kLdsStride + j];
+            const double piv = A[j * ld + j];
             if (!(piv > 0.0)) {  // uniform: every lane read the same pivot
                 ok = false;
                 break;
@@ -142,18 +154,28 @@ __global__ __launch_bounds__(64) void k_cov_build(
             const double ljj = sqrt(piv);
             __syncthreads();
             double lij = 0.0;
-            if (i == j) A[j * kLdsStride + j] = ljj;
+            if (i == j) A[j * ld + j] = ljj;
             if (i > j && i < N) {
-                lij = A[i * kLdsStride + j] / ljj;
-                A[i * kLdsStride + j] = lij;
+                lij = A[i * ld + j] / ljj;
+                A[i * ld + j] = lij;
                 colj[i] = lij;
             }
             __syncthreads();
             // lane i updates its own row from the column copy: the loads come
             // from another array than the stores, so they can be issued ahead
             if (i > j && i < N) {
-#pragma unroll 4
-                for (int k = j + 1; k <= i; ++k) A[i * kLdsStride + k] -= lij * colj[k];
+                double *__restrict__ row = A + i * ld;
+                int k = j + 1;
+                for (; k + 3 <= i; k += 4) {  // four loads of each array, then the stores
+                    const double c0 = colj[k], c1 = colj[k + 1], c2 = colj[k + 2],
+                                 c3 = colj[k + 3];
+                    const double a0 = row[k], a1 = row[k + 1], a2 = row[k + 2], a3 = row[k + 3];
+                    row[k] = a0 - lij * c0;
+                    row[k + 1] = a1 - lij * c1;
+                    row[k + 2] = a2 - lij * c2;
+                    row[k + 3] = a3 - lij * c3;
+                }
+                for (; k <= i; ++k) row[k] -= lij * colj[k];
             }
             __syncthreads();
         }
@@ -168,12 +190,12 @@ __global__ __launch_bounds__(64) void k_cov_build(
         // c's strict upper part and its spare column, which no other lane reads)
         const int c = i;
         if (c < N) {
-            A[c * kLdsStride + kMaxBins] = 1.0 / A[c * kLdsStride + c];
+            A[c * ld + ld - 1] = 1.0 / A[c * ld + c];
             for (int r = c + 1; r < N; ++r) {
                 double acc = 0.0;
 #pragma unroll 4
-                for (int k = c; k < r; ++k) acc -= A[r * kLdsStride + k] * wget(A, k, c);
-                A[c * kLdsStride + r] = acc / A[r * kLdsStride + r];
+                for (int k = c; k < r; ++k) acc -= A[r * ld + k] * wget(A, ld, k, c);
+                A[c * ld + r] = acc / A[r * ld + r];
             }
         }
         __syncthreads();
@@ -182,7 +204,7 @@ __global__ __launch_bounds__(64) void k_cov_build(
         if (forms & FC_FORM_FP64) {
             double *Wq = W64 + q * ((int64_t)N * (N + 1) / 2);
             if (c < N)
-                for (int r = c; r < N; ++r) Wq[tri_index(r, c)] = wget(A, r, c);
+                for (int r = c; r < N; ++r) Wq[tri_index(r, c)] = wget(A, ld, r, c);
         }
         if (forms & FC_FORM_FP32) {
             // A register v, lane i = 4 X + m: pair t = 16 v + X, i.e. padded
@@ -198,7 +220,7 @@ __global__ __launch_bounds__(64) void k_cov_build(
                 if (t < np) {
                     const int kp = fp32_pair_kp(ns, t), b = fp32_pair_b(ns, t);
                     const int rr = 4 * b + m - P, cc = kp - P;
-                    if (rr >= 0 && rr < N && cc >= 0 && cc <= rr) val = (float)wget(A, rr, cc);
+                    if (rr >= 0 && rr < N && cc >= 0 && cc <= rr) val = (float)wget(A, ld, rr, cc);
                 }
                 Wq[((v >> 2) * 64 + i) * 4 + (v & 3)] = val;
             }
@@ -211,7 +233,7 @@ __global__ __launch_bounds__(64) void k_cov_build(
                 double cv = 0.0;
                 if (rr >= 0 && rr < N) {
 #pragma unroll 4
-                    for (int kk = 0; kk <= rr; ++kk) cv -= wget(A, rr, kk) * sdl[kk];
+                    for (int kk = 0; kk <= rr; ++kk) cv -= wget(A, ld, rr, kk) * sdl[kk];
                 }
                 Sp[64 + i] = (float)cv;
             }
@@ -219,9 +241,9 @@ __global__ __launch_bounds__(64) void k_cov_build(
         if (forms & (FC_FORM_SPLIT_BF16 | FC_FORM_SPLIT_FP16)) {
             const int64_t sru = split_rec_units(split_nk(N), split_nb(N));
             if (forms & FC_FORM_SPLIT_BF16)
-                write_split_record<false>(A, sdo, N, 0, RB16 + q * sru);
+                write_split_record<false>(A, ld, sdo, N, 0, RB16 + q * sru);
             if (forms & FC_FORM_SPLIT_FP16)
-                write_split_record<true>(A, sdo, N, ed16, RH16 + q * sru);
+                write_split_record<true>(A, ld, sdo, N, ed16, RH16 + q * sru);
         }
         __syncthreads();
     }
@@ -232,7 +254,8 @@ hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *sta
                             unsigned long long *bad_q, hipStream_t st)
 {
     const int64_t blocks = g->G < 65536 ? g->G : 65536;
-    hipLaunchKernelGGL(k_cov_build, dim3((unsigned)blocks), dim3(64), 0, st, g->S64, F, stat,
+    hipLaunchKernelGGL(k_cov_build, dim3((unsigned)blocks), dim3(64), cov_lds_bytes(g->N), st,
+                       g->S64, F, stat,
                        g->off, g->N, g->G, stat_mode, forms, g->ns, g->ed16, W64, R32, RB16, RH16,
                        bad_q);
     return hipGetLastError();
