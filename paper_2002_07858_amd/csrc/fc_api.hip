@@ -43,12 +43,14 @@ int hip_fail(hipError_t e, const char *what)
 void free_forms(fc_grid *g)
 {
     if (g->W64) (void)hipFree(g->W64);
+    if (g->R64) (void)hipFree(g->R64);
     if (g->R32) (void)hipFree(g->R32);
     if (g->RB16) (void)hipFree(g->RB16);
     if (g->RH16) (void)hipFree(g->RH16);
     if (g->F64) (void)hipFree(g->F64);
     if (g->LF64) (void)hipFree(g->LF64);
     g->W64 = nullptr;
+    g->R64 = nullptr;
     g->R32 = nullptr;
     g->RB16 = nullptr;
     g->RH16 = nullptr;
@@ -68,6 +70,7 @@ size_t grid_bytes(const fc_grid *g)
     size_t b = 0;
     b += sizeof(double) * (size_t)g->G * g->N;  // S64
     if (g->W64) b += sizeof(double) * (size_t)g->G * ((size_t)g->N * (g->N + 1) / 2);
+    if (g->R64) b += sizeof(uint4) * (size_t)g->G * fcx::f64_rec_units(fcx::f64_nb(g->N));
     b += sizeof(double) * 128;                  // off, dev
     if (g->R32) b += sizeof(uint4) * (size_t)g->G * fcx::rec_units(g->ns);
     if (g->RB16) b += (size_t)g->G * split_record_bytes(g);
@@ -191,7 +194,7 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
     double *dF = nullptr, *dstat = nullptr, *dLF = nullptr;
     unsigned long long *dbad = nullptr;
     double *W64 = nullptr;
-    uint4 *R32 = nullptr, *RB16 = nullptr, *RH16 = nullptr;
+    uint4 *R64 = nullptr, *R32 = nullptr, *RB16 = nullptr, *RH16 = nullptr;
     hipError_t e = hipSuccess;
     auto cleanup = [&]() {
         if (dF) (void)hipFree(dF);
@@ -206,6 +209,9 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
         (e = hipMalloc(&dbad, sizeof(unsigned long long))) != hipSuccess ||
         ((forms & FC_FORM_FP64) &&
          (e = hipMalloc(&W64, sizeof(double) * (size_t)g->G * nt)) != hipSuccess) ||
+        ((forms & FC_FORM_FP64) &&
+         (e = hipMalloc(&R64, sizeof(uint4) * (size_t)g->G *
+                                  fcx::f64_rec_units(fcx::f64_nb(N)))) != hipSuccess) ||
         ((forms & FC_FORM_FP32) &&
          (e = hipMalloc(&R32, sizeof(uint4) * (size_t)g->G * fcx::rec_units(g->ns))) !=
              hipSuccess) ||
@@ -215,6 +221,7 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
          (e = hipMalloc(&RH16, (size_t)g->G * split_record_bytes(g))) != hipSuccess)) {
         cleanup();
         if (W64) (void)hipFree(W64);
+        if (R64) (void)hipFree(R64);
         if (R32) (void)hipFree(R32);
         if (RB16) (void)hipFree(RB16);
         if (RH16) (void)hipFree(RH16);
@@ -229,8 +236,8 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
                              stream)) != hipSuccess) ||
         (e = hipMemcpyAsync(dbad, &none, sizeof(none), hipMemcpyHostToDevice, stream)) !=
             hipSuccess ||
-        (e = fcx::launch_cov_build(g, dF, dstat, stat_mode, forms, W64, R32, RB16, RH16, dbad,
-                                   stream)) !=
+        (e = fcx::launch_cov_build(g, dF, dstat, stat_mode, forms, W64, R64, R32, RB16, RH16,
+                                   dbad, stream)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(&hbad, dbad, sizeof(hbad), hipMemcpyDeviceToHost, stream)) !=
             hipSuccess ||
@@ -242,6 +249,7 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
         (e = hipStreamSynchronize(stream)) != hipSuccess) {
         cleanup();
         if (W64) (void)hipFree(W64);
+        if (R64) (void)hipFree(R64);
         if (R32) (void)hipFree(R32);
         if (RB16) (void)hipFree(RB16);
         if (RH16) (void)hipFree(RH16);
@@ -250,6 +258,7 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
     if (hbad != none) {
         cleanup();
         if (W64) (void)hipFree(W64);
+        if (R64) (void)hipFree(R64);
         if (R32) (void)hipFree(R32);
         if (RB16) (void)hipFree(RB16);
         if (RH16) (void)hipFree(RH16);
@@ -259,6 +268,7 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
                     (long long)hbad);
     }
     g->W64 = W64;
+    g->R64 = R64;
     g->R32 = R32;
     g->RB16 = RB16;
     g->RH16 = RH16;

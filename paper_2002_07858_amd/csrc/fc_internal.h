@@ -124,6 +124,57 @@ __host__ __device__ constexpr int split_rec_units(int nk, int nb)
     return split_scale_unit(nk, nb) + 1;
 }
 
+// ---------------------------------------------------------------------------
+// FP64 tile form for v_mfma_f64_4x4x4f64 (four 4x4x4 blocks; the tile of W is
+// the A operand of every block).  Bins and rows are padded to NP = 4 nb with
+// nb = ceil(N / 4) blocks of four, real bins / rows at padded positions
+// P .. NP-1 (P = NP - N): W'[r'][k'] = W_q[r' - P][k' - P] for P <= k' <= r',
+// else 0.  Tiles (kb, r) with kb <= r (rows 4r .. 4r+3, bins 4kb .. 4kb+3)
+// run kb outer, r inner: nb (nb + 1) / 2 tiles.  Tile t's element
+// A[i][k] = W'[4r + i][4kb + k] is stored at position 4k + i of the tile;
+// tiles are stored in pairs, [pair][position][tile 2 pair + {0, 1}] doubles
+// (an odd last pair padded with zeros), so that one 16-byte LDS read at
+// pair * 256 + (4 (lane / 16) + lane % 4) * 16 gives a lane the A operands of
+// two consecutive tiles.  The signal follows in the order the residual needs
+// it: Sp[g][kb] = S_q[4kb + g - P] (0 for padding), g = 0..3, kb < nbe =
+// nb rounded up to even, so that a lane reads its nb values (g = lane / 16)
+// with 16-byte loads.  N = 57: nb = 15, 120 tiles, 15.5 KB per grid point.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int f64_nb(int N) { return (N + 3) / 4; }
+__host__ __device__ constexpr int f64_nbe(int nb) { return (nb + 1) & ~1; }
+__host__ __device__ constexpr int f64_ntile(int nb) { return nb * (nb + 1) / 2; }
+__host__ __device__ constexpr int f64_npair(int nb) { return (f64_ntile(nb) + 1) / 2; }
+__host__ __device__ constexpr int f64_sig_double(int nb) { return 32 * f64_npair(nb); }
+__host__ __device__ constexpr int f64_rec_doubles(int nb)
+{
+    return f64_sig_double(nb) + 4 * f64_nbe(nb);
+}
+__host__ __device__ constexpr int f64_rec_units(int nb) { return f64_rec_doubles(nb) / 2; }
+__host__ __device__ constexpr int f64_tile_kb(int nb, int t)
+{
+    int kb = 0;
+    while (t >= nb - kb) {
+        t -= nb - kb;
+        ++kb;
+    }
+    return kb;
+}
+__host__ __device__ constexpr int f64_tile_r(int nb, int t)
+{
+    int kb = 0;
+    while (t >= nb - kb) {
+        t -= nb - kb;
+        ++kb;
+    }
+    return kb + t;
+}
+
+// (minimum, first grid point reaching it) of one grid chunk of the FP64 scan.
+struct Fp64Part {
+    double v;
+    int64_t q;
+};
+
 // Copy one record of REC 16-byte units into LDS with direct global -> LDS
 // loads: thread tid moves units tid, tid + 256, ...; each wave's 64 lanes land
 // contiguously at its own base, so the LDS image equals the global record.  The loads are
@@ -174,6 +225,7 @@ struct fc_grid {
     uint4 *R32 = nullptr;   // device [G][rec_units(ns)] FP32-form records (see above)
     uint4 *RB16 = nullptr;  // device [G][split_rec_units] split-BF16 records
     uint4 *RH16 = nullptr;  // device [G][split_rec_units] split-FP16 records
+    uint4 *R64 = nullptr;   // device [G][f64_rec_units] FP64 tile records (see above)
     double *off = nullptr;  // device [64] per-bin offset o (grid mean of S), zero past N
     double *dev = nullptr;  // device [64] per-bin max |S - o|
     int ed16 = 0;           // power-of-two scale of (d - o) in the split-FP16 form
@@ -190,8 +242,8 @@ namespace fcx {
 hipError_t launch_offset(const double *S64, int64_t G, int N, double *off, double *dev,
                          hipStream_t st);
 hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *stat, int stat_mode,
-                            uint32_t forms, double *W64, uint4 *R32, uint4 *RB16, uint4 *RH16,
-                            unsigned long long *bad_q, hipStream_t st);
+                            uint32_t forms, double *W64, uint4 *R64, uint4 *R32, uint4 *RB16,
+                            uint4 *RH16, unsigned long long *bad_q, hipStream_t st);
 // The keyed scans cover the grid points [q0, q0 + nq) (nq = G: the whole grid)
 // and merge into keys / chi2_p (see launch_init_keys).
 hipError_t launch_scan_split(const fc_grid *g, bool fp16, int64_t K, const double *d,
@@ -209,9 +261,12 @@ hipError_t launch_offset_table(const fc_grid *g, int64_t n_pts, const int64_t *p
                                int64_t nq, float *T, hipStream_t st);
 hipError_t launch_expand_segments(int64_t K, int64_t n_pts, const int64_t *seg_off,
                                   const int64_t *p, int64_t *p_idx, hipStream_t st);
+// FP64 form; the chunk partials go to `scratch` (scratch_bytes, caller-owned)
+// when it is given (fewer chunks if it is small), else to a stream-ordered
+// allocation.
 hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
                             double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p,
-                            hipStream_t st);
+                            hipStream_t st, Fp64Part *scratch = nullptr, size_t scratch_bytes = 0);
 // keys = no value yet, chi2_p = chi2_p_fill (NaN for a one-call scan; 0 for
 // the sliced-scan state, so that slices merge by summing chi2_p).
 hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p, hipStream_t st,

@@ -114,8 +114,8 @@ __device__ void write_split_record(const double *A, int ld, const double *sdo, i
 __global__ __launch_bounds__(64) void k_cov_build(
     const double *__restrict__ S64, const double *__restrict__ F, const double *__restrict__ stat,
     const double *__restrict__ off, int N, int64_t G, int stat_mode, uint32_t forms, int ns,
-    int ed16, double *__restrict__ W64, uint4 *__restrict__ R32, uint4 *__restrict__ RB16,
-    uint4 *__restrict__ RH16, unsigned long long *__restrict__ bad_q)
+    int ed16, double *__restrict__ W64, uint4 *__restrict__ R64, uint4 *__restrict__ R32,
+    uint4 *__restrict__ RB16, uint4 *__restrict__ RH16, unsigned long long *__restrict__ bad_q)
 {
     extern __shared__ double smem[];
     const int ld = cov_ld(N);
@@ -206,6 +206,27 @@ __global__ __launch_bounds__(64) void k_cov_build(
             if (c < N)
                 for (int r = c; r < N; ++r) Wq[tri_index(r, c)] = wget(A, ld, r, c);
         }
+        if (forms & FC_FORM_FP64) {
+            // tile records of the FP64 MFMA form: element e of the record is
+            // (pair, position, tile of the pair), then the signal in residual order
+            const int nb = f64_nb(N), nt = f64_ntile(nb), P = 4 * nb - N;
+            const int sig = f64_sig_double(nb), nbe = f64_nbe(nb);
+            double *rq = reinterpret_cast<double *>(R64 + q * (int64_t)f64_rec_units(nb));
+            for (int e = i; e < sig; e += 64) {
+                const int t = 2 * (e >> 5) + (e & 1), pos = (e >> 1) & 15;
+                double val = 0.0;
+                if (t < nt) {
+                    const int rr = 4 * f64_tile_r(nb, t) + (pos & 3) - P;
+                    const int cc = 4 * f64_tile_kb(nb, t) + (pos >> 2) - P;
+                    if (rr >= 0 && rr < N && cc >= 0 && cc <= rr) val = wget(A, ld, rr, cc);
+                }
+                rq[e] = val;
+            }
+            for (int e = i; e < 4 * nbe; e += 64) {
+                const int g = e / nbe, kb = e % nbe, k = 4 * kb + g - P;
+                rq[sig + e] = (k >= 0 && k < N) ? Sq[k] : 0.0;
+            }
+        }
         if (forms & FC_FORM_FP32) {
             // A register v, lane i = 4 X + m: pair t = 16 v + X, i.e. padded
             // row 4b + m and padded bin k' of that pair
@@ -250,14 +271,14 @@ __global__ __launch_bounds__(64) void k_cov_build(
 }
 
 hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *stat, int stat_mode,
-                            uint32_t forms, double *W64, uint4 *R32, uint4 *RB16, uint4 *RH16,
-                            unsigned long long *bad_q, hipStream_t st)
+                            uint32_t forms, double *W64, uint4 *R64, uint4 *R32, uint4 *RB16,
+                            uint4 *RH16, unsigned long long *bad_q, hipStream_t st)
 {
     const int64_t blocks = g->G < 65536 ? g->G : 65536;
     hipLaunchKernelGGL(k_cov_build, dim3((unsigned)blocks), dim3(64), cov_lds_bytes(g->N), st,
                        g->S64, F, stat,
-                       g->off, g->N, g->G, stat_mode, forms, g->ns, g->ed16, W64, R32, RB16, RH16,
-                       bad_q);
+                       g->off, g->N, g->G, stat_mode, forms, g->ns, g->ed16, W64, R64, R32, RB16,
+                       RH16, bad_q);
     return hipGetLastError();
 }
 

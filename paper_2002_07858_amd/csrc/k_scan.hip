@@ -532,116 +532,6 @@ __global__ __launch_bounds__(kPtsTile) __attribute__((amdgpu_waves_per_eu(2))) v
     }
 }
 
-// FP64 form (the parity anchor): one thread per universe, W_q uniform across
-// the wave, so its entries arrive through scalar loads.  The blocks of one
-// 64-universe tile split the grid into chunks (a small K alone would occupy a
-// few CUs).  With one chunk the thread writes the outputs; with several, each
-// chunk's minimum (value, first q reaching it) goes to part[chunk][u], the
-// chunk that holds p writes chi2_p, and k_fp64_merge takes the minimum over
-// the chunks in grid order with the same strict "<" -- the sequential scan's
-// result exactly.
-struct Fp64Part {
-    double v;
-    int64_t q;
-};
-
-template <int NP>
-__global__ __launch_bounds__(64) void k_scan_fp64(
-    const double *__restrict__ W64, const double *__restrict__ S64, const double *__restrict__ d,
-    const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t G, int64_t n_utiles,
-    int64_t q_per_chunk, Fp64Part *__restrict__ part, double *__restrict__ dchi2,
-    double *__restrict__ chi2_min, int64_t *__restrict__ argmin, double *__restrict__ chi2_p)
-{
-    const int64_t utile = blockIdx.x % n_utiles, chunk = blockIdx.x / n_utiles;
-    const int64_t u = utile * 64 + threadIdx.x;
-    if (u >= K) return;
-    const int64_t qb = chunk * q_per_chunk;
-    const int64_t qe = (qb + q_per_chunk < G) ? qb + q_per_chunk : G;
-    const int64_t NT = (int64_t)N * (N + 1) / 2;
-    double dv[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) dv[j] = (j < N) ? d[u * N + j] : 0.0;
-    const int64_t p = p_idx[u];
-    double best = __builtin_inf();
-    int64_t qbest = p;
-    double cp = __builtin_nan("");
-    for (int64_t q = qb; q < qe; ++q) {
-        const double *Wq = W64 + q * NT;
-        const double *Sq = S64 + q * N;
-        double r[NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) r[j] = (j < N) ? dv[j] - Sq[j] : 0.0;
-        double chi2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            if (i < N) {
-                double z = 0.0;
-#pragma unroll
-                for (int j = 0; j <= i; ++j) z = fma(Wq[tri_index(i, j)], r[j], z);
-                chi2 = fma(z, z, chi2);
-            }
-        }
-        if (q == p) cp = chi2;
-        if (chi2 < best) {
-            best = chi2;
-            qbest = q;
-        }
-    }
-    if (part) {
-        part[chunk * K + u] = Fp64Part{best, qbest};
-        if (p >= qb && p < qe) chi2_p[u] = cp;
-        return;
-    }
-    chi2_min[u] = best;
-    argmin[u] = qbest;
-    chi2_p[u] = cp;
-    dchi2[u] = cp - best;
-}
-
-// Merge of the FP64 chunks: one wave per universe.  Lane l takes chunks l,
-// l + 64, ... in grid order with the strict "<", then the wave reduces the 64
-// (value, q) pairs by shuffles, keeping the lower q among equal values: the
-// chunks partition the grid in order, so that is the earlier chunk, and the
-// result is the sequential scan's.  Chunk values are never NaN (a NaN chi2
-// never passes "<"), and a chunk with no finite value reports (+inf, p).  A
-// true point outside [0, G) was owned by no chunk: chi2_p = NaN.
-__global__ __launch_bounds__(256) void k_fp64_merge(const Fp64Part *__restrict__ part,
-                                                   int64_t n_chunks, const int64_t *__restrict__ p_idx,
-                                                   int64_t K, int64_t G, double *__restrict__ dchi2,
-                                                   double *__restrict__ chi2_min,
-                                                   int64_t *__restrict__ argmin,
-                                                   double *__restrict__ chi2_p)
-{
-    const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (u >= K) return;  // uniform per wave
-    const int64_t p = p_idx[u];
-    double best = __builtin_inf();
-    int64_t qbest = p;
-    for (int64_t c = lane; c < n_chunks; c += 64) {
-        const Fp64Part x = part[c * K + u];
-        if (x.v < best) {
-            best = x.v;
-            qbest = x.q;
-        }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(best, off, 64);
-        const int64_t oq = __shfl_xor(qbest, off, 64);
-        if (ov < best || (ov == best && oq < qbest)) {
-            best = ov;
-            qbest = oq;
-        }
-    }
-    if (lane != 0) return;
-    const double cp = (p >= 0 && p < G) ? chi2_p[u] : __builtin_nan("");
-    chi2_min[u] = best;
-    argmin[u] = qbest;
-    chi2_p[u] = cp;
-    dchi2[u] = cp - best;
-}
-
 __global__ __launch_bounds__(256) void k_init_keys(int64_t K, unsigned long long *__restrict__ keys,
                                                   double *__restrict__ chi2_p, double chi2_p_fill)
 {
@@ -1008,63 +898,6 @@ hipError_t launch_expand_segments(int64_t K, int64_t n_pts, const int64_t *seg_o
     return hipGetLastError();
 }
 #undef FC_EACH_N
-
-template <int NP>
-static hipError_t launch_fp64_np(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                                 double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p,
-                                 hipStream_t st)
-{
-    if (K <= 0) return hipSuccess;
-    // resident block slots: queried once per instantiation (thread-safe)
-    static const int slots =
-        resident_slots(reinterpret_cast<const void *>(&k_scan_fp64<NP>), 64);
-    // grid chunks so that tiles x chunks is about two rounds of the resident
-    // slots; at most 256 chunks and 2^18 (chunk, universe) partials (4 MB)
-    const int64_t n_utiles = (K + 63) / 64;
-    int64_t chunks = (2 * (int64_t)slots) / n_utiles;
-    if (chunks > 256) chunks = 256;
-    if (chunks > (int64_t(1) << 18) / K) chunks = (int64_t(1) << 18) / K;
-    if (chunks > g->G) chunks = g->G;
-    if (chunks < 1) chunks = 1;
-    const int64_t qpc = (g->G + chunks - 1) / chunks;
-    chunks = (g->G + qpc - 1) / qpc;
-    Fp64Part *part = nullptr;
-    hipError_t e;
-    if (chunks > 1 &&
-        (e = hipMallocAsync(reinterpret_cast<void **>(&part),
-                            sizeof(Fp64Part) * (size_t)chunks * (size_t)K, st)) != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_scan_fp64<NP>, dim3((unsigned)(n_utiles * chunks)), dim3(64), 0, st,
-                       g->W64, g->S64, d, p_idx, K, g->N, g->G, n_utiles, qpc, part, dchi2,
-                       chi2_min, argmin, chi2_p);
-    if ((e = hipGetLastError()) != hipSuccess) {
-        if (part) (void)hipFreeAsync(part, st);
-        return e;
-    }
-    if (part) {
-        hipLaunchKernelGGL(k_fp64_merge, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, st, part,
-                           chunks, p_idx, K, g->G, dchi2, chi2_min, argmin, chi2_p);
-        e = hipGetLastError();
-        const hipError_t ef = hipFreeAsync(part, st);
-        if (e == hipSuccess) e = ef;
-    }
-    return e;
-}
-
-hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
-                            double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p,
-                            hipStream_t st)
-{
-    const int np = ((g->N + 7) / 8) * 8;
-    switch (np) {
-#define FC_CASE(n) \
-    case n: return launch_fp64_np<n>(g, K, d, p_idx, dchi2, chi2_min, argmin, chi2_p, st);
-        FC_CASE(8) FC_CASE(16) FC_CASE(24) FC_CASE(32) FC_CASE(40) FC_CASE(48) FC_CASE(56)
-        FC_CASE(64)
-#undef FC_CASE
-    default: return hipErrorInvalidValue;
-    }
-}
 
 hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p, hipStream_t st,
                             double chi2_p_fill)
