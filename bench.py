@@ -1,26 +1,28 @@
 """Benchmark of the FC grid-scan hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--form fp32] [--workload c2]
-                    [--serving-requests R] [--copy-probe-mib M]
+    python bench.py [--steps K] [--warmup W] [--workload c5] [--form fp64]
+                    [--legs fp32,split_bf16,split_fp16] [--serving-requests R]
 
-Default workload (c2): D = 2 grid 100 x 100 (G = 10^4), N = 57 bins, 256 true
-points x 2000 universes (512 000 universes, 5.12e9 universe x grid-point chi^2
-evaluations per step), FP32 scan, 0.6827 / 0.90 / 0.95 critical values and a
-200-bin histogram per true point.  The other workloads: c1 (D = 2 20 x 20,
-N = 38, one true point x 1000 universes, FP64), c3 (D = 3 60^3, N = 57, 64 x
-4000) and c5 (D = 5 16^5, N = 57, 16 x 10 000).  Inputs are seeded synthetic
-data from the toy oscillation model, resident in HBM before the timed region.
+Default workload (c5): D = 5 grid 16^5 (G = 1 048 576 points), N = 57 bins, 16
+true points x 10 000 universes (160 000 universes, 1.68e11 universe x
+grid-point chi^2 evaluations per step), scanned in FP64 (the paper's
+arithmetic), with 0.6827 / 0.90 / 0.95 critical values and a 200-bin
+histogram per true point.  The other workloads: c1 (D = 2 20 x 20, N = 38,
+one true point x 1000 universes), c2 (D = 2 100 x 100, N = 57, 256 x 2000)
+and c3 (D = 3 60^3, N = 57, 64 x 4000).  Inputs are seeded synthetic data from
+the toy oscillation model, resident in HBM before the timed region.
 
 One step = covariance factors for every grid point (FP64 Cholesky + inverse,
 stored in the scan form) + the scan of all universes (minimum, argmin,
-Delta chi^2) + critical values.  A one-matrix leg runs Algorithm 1 as
-printed (one M per universe, and its iteration) on the FP64 matrix cores; a
-region leg then builds the whole FC
-surface (every grid point a true point, universes drawn on the device, counts
-refined near the contour), and a serving leg replays a seeded Poisson
-stream of FC requests (K log-uniform in [500, 20000], three resident grids)
-through a plain FIFO loop and through the continuous-batching server and
-reports p50/p99 latency beside throughput.  Prints one JSON line.
+Delta chi^2) + critical values.  The dominant kernel is also timed alone
+(HIP events around its launches, on its stream).  Legs on the same inputs: the
+FP32 and split BF16 / FP16 forms (scan time, roofline, error against the FP64
+result on every universe and against the oracle on a sample).  Further legs:
+the one-matrix scan (Algorithm 1 as printed, and its iteration) and the
+full-surface region on the c2 grid, and a serving leg that replays a seeded
+Poisson stream of FC requests (K log-uniform in [500, 20000], three resident
+grids) through a plain FIFO loop and through the continuous-batching server,
+with p50/p99 latency beside throughput.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -46,9 +48,21 @@ N_BINS, HIST_HI = 200, 50.0
 
 
 def flop_per_eval(N: int) -> int:
-    # factor form: N subtractions, triangular W r (N(N+1)/2 multiply-adds),
-    # N squares and N adds
+    # the method's work per evaluation in factor form: N subtractions, the
+    # triangular W r (N(N+1)/2 multiply-adds), N squares and N adds
     return N * N + 4 * N
+
+
+def mfma_flop_per_eval(N: int) -> int:
+    # the part of it on the matrix cores: the triangular W r
+    return N * (N + 1)
+
+
+def vector_flop_per_eval(N: int, form: str, scan: str) -> int:
+    # the rest, on the vector ALUs: the residual's N subtractions (not in the
+    # FP32 grouped form, whose residual is formed once per universe) and the
+    # N squares and adds
+    return (2 * N if (form == "fp32" and scan == "points") else 3 * N)
 
 
 def split_flop_per_eval(N: int) -> int:
@@ -57,15 +71,19 @@ def split_flop_per_eval(N: int) -> int:
     return 3 * N * (N + 1)
 
 
+KERNEL = {"fp64": "k_scan_f64m", "fp32": "k_scan_fp32_pts", "split_bf16": "k_scan_split",
+          "split_fp16": "k_scan_split"}
+
+
 WORKLOADS = {
     "c1": dict(desc="c1: D=2 grid 20x20 (G=400), N=38, 1 true point x 1000 universes",
                steps=10, warmup=2, cpu_per_point=1000, serving=0),
     "c2": dict(desc="c2: D=2 grid 100x100 (G=10000), N=57, 256 true points x 2000 universes",
-               steps=10, warmup=2, cpu_per_point=100, serving=200),
+               steps=5, warmup=1, cpu_per_point=100, serving=200),
     "c3": dict(desc="c3: D=3 grid 60^3 (G=216000), N=57, 64 true points x 4000 universes",
                steps=3, warmup=1, cpu_per_point=8, serving=0),
     "c5": dict(desc="c5: D=5 grid 16^5 (G=1048576), N=57, 16 true points x 10000 universes",
-               steps=2, warmup=1, cpu_per_point=4, serving=0),
+               steps=2, warmup=1, cpu_per_point=16, serving=200),
 }
 
 # HBM traffic of the scan kernel per launch, from rocprofv3 FETCH_SIZE and
@@ -124,6 +142,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_threads():
+    """Threads for the oracle: the CPUs this process may run on, capped by the
+    host share the environment grants (OMP_NUM_THREADS when set)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    share = int(env) if env.isdigit() and int(env) > 0 else n
+    return max(1, min(n, share)), n
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(pr, per_point: int, dev_out: dict, tol: float):
     """Time the FP64 oracle on a bounded sample and measure the device error on it."""
     import oracle
@@ -135,7 +173,7 @@ def cpu_baseline(pr, per_point: int, dev_out: dict, tol: float):
         idx += list(range(lo, min(hi, lo + per_point)))
         seg.append(len(idx))
     idx = np.array(idx)
-    nt = oracle.default_threads()
+    nt, visible = host_threads()
     t0 = time.perf_counter()
     ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx], nthreads=nt)
     dt = time.perf_counter() - t0
@@ -145,11 +183,13 @@ def cpu_baseline(pr, per_point: int, dev_out: dict, tol: float):
     c_dev, _ = oracle.critical_value(dev_out["dchi2"][idx], seg, ALPHA, with_hist=False)
     c_ref, _ = oracle.critical_value(ref["dchi2"], seg, ALPHA, with_hist=False)
     rep["crit_abs_err_sample"] = float(np.abs(c_dev - c_ref).max())
-    rep["_sample"] = (idx, ref)   # reused by the split-form leg, removed before printing
+    rep["_sample"] = (idx, ref)   # reused by the form legs, removed before printing
     base = {"value": evals / dt, "unit": "evals/s", "cores": nt, "kind": "oracle",
-            "sample": f"first {min(per_point, int(pr.seg_off[1]))} universes of each of the {len(pr.seg_off) - 1} true "
-                      f"points x all {pr.G} grid points ({evals:.3g} evals, {dt:.1f} s, "
-                      f"FP64 Cholesky + forward substitution)"}
+            "cpu_model": cpu_model(), "cpus_visible": visible,
+            "sample": f"first {min(per_point, int(pr.seg_off[1]))} universes of each of the "
+                      f"{len(pr.seg_off) - 1} true points x all {pr.G} grid points "
+                      f"({evals:.3g} evals, {dt:.1f} s on {nt} threads, FP64 Cholesky per grid "
+                      f"point + forward substitution)"}
     return base, rep
 
 
@@ -281,10 +321,15 @@ def serving_bench(n_req: int, loads=(0.8,)):
     rng = fcgen.rng_for(4, 3, 1)
     gaps = rng.exponential(1.0, size=n_req)
     for load in loads:
-        lam = load * capacity
-        arrivals = np.cumsum(gaps / lam) - gaps[0] / lam
+        if load == "sat":
+            # every request queued at once: throughput is each mode's capacity
+            lam = float("inf")
+            arrivals = np.zeros(n_req)
+        else:
+            lam = float(load) * capacity
+            arrivals = np.cumsum(gaps / lam) - gaps[0] / lam
         log(f"[bench] serving load {load}: lambda {lam:.1f}/s")
-        res = {"lambda_req_s": lam}
+        res = {"lambda_req_s": lam if np.isfinite(lam) else "all at t=0"}
         grid_of = [r[0] for r in reqs]
         log("[bench]   plain_fp32")
         lat, wall, ev = run_plain(fc, grids, reqs, arrivals)
@@ -429,7 +474,7 @@ def shard_bench(fc, grid, form, form_name, scan_entry, pr, d_t, p_t, pts_t, so_t
                                                                                   ref["chi2_p"]))
     slice_evals = [float(K) * (b - a) for a, b in zip(edges[:-1], edges[1:])]
     flops = slice_evals[0] * (split_flop_per_eval(pr.N) if form_name.startswith("split")
-                              else flop_per_eval(pr.N))
+                              else mfma_flop_per_eval(pr.N))
     return {"shards": n_shards, "grid_points_per_shard": edges[1] - edges[0],
             "universes": K, "scan_entry": scan_entry, "slice_ms": ms,
             "slice_evals_per_s": slice_evals[0] / (mid * 1e-3),
@@ -439,11 +484,36 @@ def shard_bench(fc, grid, form, form_name, scan_entry, pr, d_t, p_t, pts_t, so_t
 
 
 # ---------------------------------------------------------------------------
-# The split hi+lo forms on the same inputs: scan time (HIP events, grouped
-# entry), 16-bit MFMA and FP32-equivalent fractions, and the error on the
+# The other arithmetic forms on the same inputs: scan time (HIP events around
+# the call and around the dominant kernel alone), roofline, and the error
+# against the FP64 result on every universe and against the oracle on the
 # CPU-baseline sample.
 # ---------------------------------------------------------------------------
-def split_leg(fc, grid, pr, pts_t, so_t, d_t, sample, steps=3):
+def roofline_of(form: str, scan: str, N: int, evals: float, kernel_s: float):
+    """Roofline of the dominant kernel: the matrix-core work of the contraction
+    (the triangular W r; split forms: three 16-bit products per multiply-add)
+    against the peak of the form's datatype; the vector work beside it."""
+    split = form.startswith("split")
+    mf = split_flop_per_eval(N) if split else mfma_flop_per_eval(N)
+    achieved = evals * mf / kernel_s
+    r = {"kernel": KERNEL[form] if scan == "points" or form != "fp32" else "k_scan_fp32",
+         "bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[form] / 1e12,
+         "unit": "TFLOP/s", "frac": achieved / PEAK[form],
+         "flop_per_eval_mfma": mf,
+         "flop_per_eval_vector": vector_flop_per_eval(N, form, scan),
+         "frac_method_flops": evals * flop_per_eval(N) / kernel_s /
+         PEAK["fp32" if split else form],
+         "kernel_ms": kernel_s * 1e3, "traffic": None}
+    return r
+
+
+def profiled_kernel_s(fc, form: str, scan: str):
+    name = KERNEL[form] if scan == "points" or form != "fp32" else "k_scan_fp32"
+    n, ms = fc.fc_profile_read(name)
+    return (ms / n * 1e-3) if n else None
+
+
+def forms_leg(fc, grid, pr, forms, pts_t, so_t, d_t, ref64, sample, steps=2):
     import torch
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import parity
@@ -453,30 +523,48 @@ def split_leg(fc, grid, pr, pts_t, so_t, d_t, sample, steps=3):
                                                                        "chi2_p")}
     o["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
-    for name, form in (("split_fp16", fc.FC_FORM_SPLIT_FP16), ("split_bf16", fc.FC_FORM_SPLIT_BF16)):
+    code = {"fp32": fc.FC_FORM_FP32, "fp64": fc.FC_FORM_FP64,
+            "split_bf16": fc.FC_FORM_SPLIT_BF16, "split_fp16": fc.FC_FORM_SPLIT_FP16}
+    scale = np.maximum(1.0, ref64["chi2_p"])
+    for name in forms:
+        form = code[name]
+        log(f"[bench] leg {name}")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
         fc.fc_build_covariance(grid, pr.F, pr.stat_mode, pr.stat_diag, forms=form)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        cov_ms = ev[0].elapsed_time(ev[1])
         ws = torch.empty(fc.fc_scan_points_workspace(grid, form, int(so_t.numel()) - 1, K),
                          dtype=torch.uint8, device="cuda")
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ms = []
         for i in range(steps + 1):          # the first pass is a warm-up
-            ev0.record(stream)
+            if i == 1:
+                fc.fc_profile_enable(True)
+            ev[0].record(stream)
             fc.fc_scan_points(grid, form, pts_t, so_t, d_t, o["dchi2"], o["chi2_min"],
                               o["argmin"], o["chi2_p"], workspace=ws)
-            ev1.record(stream)
-            ev1.synchronize()
+            ev[2].record(stream)
+            ev[2].synchronize()
             if i:
-                ms.append(ev0.elapsed_time(ev1))
+                ms.append(ev[0].elapsed_time(ev[2]))
+        ks = profiled_kernel_s(fc, name, "points")
+        fc.fc_profile_enable(False)
         t = float(np.mean(ms)) * 1e-3
-        r = {"scan_ms": t * 1e3, "evals_per_s": K * G / t,
-             "mfma16_frac": K * G * split_flop_per_eval(N) / t / PEAK[name],
-             "fp32_equivalent_frac": K * G * flop_per_eval(N) / t / PEAK["fp32"]}
+        dev = {k: v.cpu().numpy() for k, v in o.items()}
+        e_all = np.abs(dev["dchi2"] - ref64["dchi2"]) / scale
+        r = {"scan_ms": t * 1e3, "covariance_ms": cov_ms, "evals_per_s": K * G / t,
+             "roofline": roofline_of(name, "points", N, float(K) * G, ks if ks else t),
+             "vs_fp64_all_universes": {"n": K, "e_rel": float(e_all.max()),
+                                       "e_abs": float(np.abs(dev["dchi2"] - ref64["dchi2"]).max()),
+                                       "argmin_equal_frac": float((dev["argmin"] ==
+                                                                   ref64["argmin"]).mean())}}
         if sample is not None:
             idx, ref = sample
-            dev = {k: v.cpu().numpy()[idx] for k, v in o.items()}
-            e = parity.report(dev, ref, TOL[name])
-            r.update({"e_rel": e["e_rel"], "argmin_agree": e["argmin_agree"],
-                      "near_tie_frac": e["near_tie_frac"]})
+            e = parity.report({k: v[idx] for k, v in dev.items()}, ref, TOL[name])
+            e.update(parity.argmin_validity(pr, {k: v[idx] for k, v in dev.items()},
+                                            pr.d[idx], ref, TOL[name]))
+            r["vs_oracle_sample"] = e
         out[name] = r
     return out
 
@@ -506,50 +594,46 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--form", default=None, choices=["fp32", "fp64", "split_bf16", "split_fp16"],
-                    help="scan form (default fp32; fp64 for c1)")
+    ap.add_argument("--form", default="fp64", choices=["fp32", "fp64", "split_bf16", "split_fp16"],
+                    help="scan form of the headline (default fp64, the paper's arithmetic)")
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated other forms run on the same inputs (default: all "
+                         "other forms; 'none' to skip)")
     ap.add_argument("--scan", default="points", choices=["points", "universes"],
                     help="scan entry: fc_scan_points (universes grouped by true point, "
                     "default) or fc_scan (per-universe true points)")
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-per-point", type=int, default=None,
                     help="universes per true point in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=None,
-                    help="requests in the serving leg (0 to skip it; default 200 for c2)")
-    ap.add_argument("--fixed", type=int, default=None,
-                    help="1: also run the one-matrix scan leg (default on for c2)")
-    ap.add_argument("--region", type=int, default=None,
-                    help="1: also run the full-surface region leg (default on for c2)")
-    ap.add_argument("--split-leg", type=int, default=None,
-                    help="also time the split BF16/FP16 forms on the same inputs, with their "
-                         "error on the CPU-baseline sample (default: c2 only; skipped without "
-                         "the CPU baseline)")
+                    help="requests in the serving leg (0 to skip it; default 200)")
+    ap.add_argument("--fixed", type=int, default=1,
+                    help="1: the one-matrix scan leg on the c2 grid (0 to skip)")
+    ap.add_argument("--region", type=int, default=1,
+                    help="1: the full-surface region leg on the c2 grid (0 to skip)")
     ap.add_argument("--shards", type=int, default=8,
-                    help="grid-sharding leg: slices of the grid scanned by separate calls "
-                         "(0: off; not for the fp64 form)")
+                    help="grid-sharding leg in the FP32 form: slices of the grid scanned by "
+                         "separate calls (0: off)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (counter calibration)")
-    ap.add_argument("--serving-loads", default="0.5,0.8",
-                    help="comma-separated arrival rates as fractions of the plain capacity")
+    ap.add_argument("--serving-loads", default="0.5,0.8,sat",
+                    help="comma-separated arrival rates as fractions of the plain capacity "
+                         "('sat': every request queued at t = 0, which measures capacity)")
     args = ap.parse_args()
     wl = WORKLOADS[args.workload]
     if args.steps is None:
         args.steps = wl["steps"]
     if args.warmup is None:
         args.warmup = wl["warmup"]
-    if args.form is None:
-        args.form = "fp64" if args.workload == "c1" else "fp32"
     if args.cpu_per_point is None:
         args.cpu_per_point = wl["cpu_per_point"]
     if args.serving_requests is None:
         args.serving_requests = wl["serving"]
-    if args.region is None:
-        args.region = 1 if args.workload == "c2" else 0
-    if args.fixed is None:
-        args.fixed = 1 if args.workload == "c2" else 0
-    if args.split_leg is None:
-        args.split_leg = 1 if args.workload == "c2" else 0
+    if args.legs is None:
+        legs = [f for f in ("fp32", "split_bf16", "split_fp16", "fp64") if f != args.form]
+    else:
+        legs = [] if args.legs == "none" else [f for f in args.legs.split(",") if f]
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the scan is "
               "single-GPU by design; see the multi-GPU section of the design notes.",
@@ -565,8 +649,9 @@ def main():
         copy_probe(args.copy_probe_mib)
         return
     fc.lib()
-    form = {"fp32": fc.FC_FORM_FP32, "fp64": fc.FC_FORM_FP64, "split_bf16": fc.FC_FORM_SPLIT_BF16,
-            "split_fp16": fc.FC_FORM_SPLIT_FP16}[args.form]
+    code = {"fp32": fc.FC_FORM_FP32, "fp64": fc.FC_FORM_FP64,
+            "split_bf16": fc.FC_FORM_SPLIT_BF16, "split_fp16": fc.FC_FORM_SPLIT_FP16}
+    form = code[args.form]
 
     log(f"[bench] generating {args.workload} inputs")
     pr = fcgen.make_problem(args.workload)
@@ -623,6 +708,7 @@ def main():
     first = None
     times = {"cov": [], "scan": [], "crit": []}
     log(f"[bench] timing {args.steps} steps")
+    fc.fc_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -632,29 +718,21 @@ def main():
             first = (outs["dchi2"].clone(), outs["argmin"].clone(), crit.clone())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    kernel_s = profiled_kernel_s(fc, args.form, args.scan)
+    fc.fc_profile_enable(False)
 
     evals = K * G
     value = evals * args.steps / wall
     scan_ms = float(np.mean(times["scan"]))
-    fpe = flop_per_eval(N)
-    split = args.form.startswith("split")
-    achieved = evals * (split_flop_per_eval(N) if split else fpe) / (scan_ms * 1e-3)
-    peak = PEAK[args.form]
-    kernel = {"fp64": "k_scan_fp64", "fp32": "k_scan_fp32_pts" if args.scan == "points"
-              else "k_scan_fp32"}.get(args.form, "k_scan_split")
-    roofline = {"kernel": kernel, "bound": "alu" if args.form == "fp64" else "mfma",
-                "achieved": achieved / 1e12,
-                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None}
+    roofline = roofline_of(args.form, args.scan, N, float(evals),
+                           kernel_s if kernel_s else scan_ms * 1e-3)
+    roofline["kernel_timing"] = ("HIP events around each launch of the kernel on its stream, "
+                                 f"mean over the {args.steps} timed steps")
     tr = TRAFFIC.get((args.workload, args.form, args.scan))
     if tr is not None and tr["source_hash"] == kernel_source_hash(tr["sources"]):
         roofline["traffic"] = tr["bytes_per_launch"]
-        roofline["traffic_GBps"] = tr["bytes_per_launch"] / (scan_ms * 1e-3) / 1e9
+        roofline["traffic_GBps"] = tr["bytes_per_launch"] / (roofline["kernel_ms"] * 1e-3) / 1e9
         roofline["traffic_source"] = tr["profile"]
-    if split:
-        fp32_equiv = evals * fpe / (scan_ms * 1e-3)
-        roofline["fp32_equivalent"] = {"achieved": fp32_equiv / 1e12, "peak": PEAK["fp32"] / 1e12,
-                                       "frac": fp32_equiv / PEAK["fp32"]}
 
     deterministic = bool(torch.equal(first[0], outs["dchi2"]) and
                          torch.equal(first[1], outs["argmin"]) and
@@ -674,31 +752,53 @@ def main():
            "bitwise_deterministic": deterministic,
            "roofline": roofline,
            "device": device_record()}
+    sample = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         base, rep = cpu_baseline(pr, args.cpu_per_point, dev_out, TOL[args.form])
         res["cpu_baseline"] = base
+        sample = rep.pop("_sample")
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        import parity
+        idx, ref = sample
+        rep.update(parity.argmin_validity(pr, {k: v[idx] for k, v in dev_out.items()},
+                                          pr.d[idx], ref, TOL[args.form]))
         res["err_vs_fp64"] = rep
-    sample = res.get("err_vs_fp64", {}).pop("_sample", None)
-    if args.shards > 0 and args.form != "fp64":
-        log(f"[bench] grid sharding leg ({args.shards} slices)")
-        res["grid_shard"] = shard_bench(fc, grid, form, args.form, args.scan, pr, d_t, p_t, pts_t,
-                                        so_t, outs, args.shards)
-    if args.split_leg and args.form == "fp32" and sample is not None:
-        log("[bench] split-form leg")   # rebuilds the grid's records in the split forms
-        res["split_forms"] = split_leg(fc, grid, pr, pts_t, so_t, d_t, sample)
+    if legs:
+        res["forms_same_inputs"] = forms_leg(fc, grid, pr, legs, pts_t, so_t, d_t, dev_out,
+                                             sample)
+    if args.shards > 0:
+        log(f"[bench] grid sharding leg ({args.shards} slices, FP32)")
+        fc.fc_build_covariance(grid, pr.F, pr.stat_mode, pr.stat_diag, forms=fc.FC_FORM_FP32)
+        ref32 = {k: torch.empty(K, dtype=torch.float64, device=dev) for k in ("dchi2", "chi2_min",
+                                                                            "chi2_p")}
+        ref32["argmin"] = torch.empty(K, dtype=torch.int64, device=dev)
+        fc.fc_scan_points(grid, fc.FC_FORM_FP32, pts_t, so_t, d_t, ref32["dchi2"],
+                          ref32["chi2_min"], ref32["argmin"], ref32["chi2_p"])
+        res["grid_shard"] = shard_bench(fc, grid, fc.FC_FORM_FP32, "fp32", "points", pr, d_t, p_t,
+                                        pts_t, so_t, ref32, args.shards)
+        del ref32
     grid.destroy()
+    del d_t, p_t, outs
+    torch.cuda.empty_cache()
+    if args.fixed or args.region:
+        pr2 = pr if args.workload == "c2" else fcgen.make_problem("c2")
     if args.fixed:
-        log("[bench] one-matrix scan")
-        res["fixed_matrix"], fixed_dev = fixed_bench(pr, d_t, p_t)
+        log("[bench] one-matrix scan (c2 grid)")
+        d2 = torch.as_tensor(pr2.d).to(dev)
+        p2 = torch.as_tensor(pr2.p_idx).to(dev)
+        res["fixed_matrix"], fixed_dev = fixed_bench(pr2, d2, p2)
+        res["fixed_matrix"]["workload"] = WORKLOADS["c2"]["desc"]
         if not args.no_cpu_baseline:
-            res["fixed_matrix"]["iterated"]["err_vs_oracle"] = fixed_err(pr, fixed_dev)
+            res["fixed_matrix"]["iterated"]["err_vs_oracle"] = fixed_err(pr2, fixed_dev)
+        del d2, p2
     if args.region:
-        log("[bench] full-surface region")
-        res["region"] = region_bench(pr, args.form)
+        log("[bench] full-surface region (c2 grid)")
+        res["region"] = region_bench(pr2, "fp32")
     if args.serving_requests > 0:
         res["serving"] = serving_bench(args.serving_requests,
-                                       tuple(float(x) for x in args.serving_loads.split(",")))
+                                       tuple(x if x == "sat" else float(x)
+                                             for x in args.serving_loads.split(",")))
     print(json.dumps(res))
 
 

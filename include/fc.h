@@ -136,19 +136,25 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
  *   form     one fc_form value
  *   K        number of universes, 0 <= K <= 2^30 (K = 0 enqueues nothing)
  *   d        device [K][N] FP64, row-major
- *   p_idx    device [K] int64 true-point grid indices.  They are checked on
- *            the device only: an index outside [0, G) gives that universe
- *            chi2_p = NaN and dchi2 = NaN and touches no other memory.
- *   dchi2, chi2_min, chi2_p   device [K] FP64 outputs
- *   argmin   device [K] int64 output
- * All four outputs are required; chi2_min's storage doubles as the scan's
- * packed (chi2, q) minimum keys until the final pass rewrites it.
+ *   p_idx    device [K] int64 true-point grid indices.  They live in device
+ *            memory and are checked there, so that the call stays
+ *            asynchronous: an index outside [0, G) gives that universe
+ *            chi2_p = NaN and dchi2 = NaN (chi2_min and argmin as for any
+ *            other universe) and touches no other memory.
+ *   dchi2    device [K] FP64 output (required)
+ *   chi2_min, chi2_p   device [K] FP64 outputs, each optional (NULL)
+ *   argmin   device [K] int64 output, optional (NULL)
+ * The FP32 and split forms keep the running minimum as packed (chi2, q) keys
+ * in chi2_min's storage (decoded in place by the final pass), or, when
+ * chi2_min is NULL, in a stream-ordered scratch of 8 K bytes; a NULL chi2_p
+ * takes another 8 K bytes.  The FP64 form splits the grid into chunks when K
+ * alone would leave CUs idle and merges their minima in grid order (the
+ * same result); the chunk minima take a stream-ordered scratch of 16 bytes
+ * per (chunk, universe).  Scratch is allocated with hipMallocAsync and
+ * released with hipFreeAsync on `stream` (FC_ERR_NOMEM or FC_ERR_DEVICE if
+ * that fails).
  * Universes with NaN/inf data get chi2_min = +inf, argmin = p, dchi2 = NaN;
  * other universes are unaffected.
- * The FP64 form, when K is too small to fill the GPU, splits the grid into
- * chunks whose minima are merged in grid order (the same result); it then
- * takes a stream-ordered scratch of at most 4 MB (hipMallocAsync and
- * hipFreeAsync on `stream`; FC_ERR_NOMEM or FC_ERR_DEVICE if that fails).
  */
 int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d,
             const int64_t *p_idx, double *dchi2, double *chi2_min, int64_t *argmin,
@@ -201,7 +207,9 @@ int fc_critical_value(int64_t n_seg, const int64_t *seg_off, const double *dchi2
  *   workspace      device scratch of at least fc_scan_points_workspace()
  *                  bytes, 256-byte aligned, owned by the caller; calls that
  *                  overlap in time need separate workspaces
- *   dchi2, chi2_min, argmin, chi2_p   as fc_scan
+ *   dchi2, chi2_min, argmin, chi2_p   as fc_scan (chi2_min, argmin and chi2_p
+ *                  optional; the FP32 form then keeps its keys / chi2_p in
+ *                  stream-ordered scratch of 8 K bytes each)
  * Asynchronous; FC_ERR_INVALID_ARG for a short or misaligned workspace.
  */
 int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t *p,
@@ -421,6 +429,19 @@ void fc_grid_destroy(fc_grid *g);
 
 /* fc_last_error -- message of the last failure on this thread ("" if none). */
 const char *fc_last_error(void);
+
+/*
+ * Kernel timing for measurement tools (no paper passage: instrumentation).
+ * fc_profile_enable(1) clears earlier records and starts bracketing every
+ * launch of the scan kernels (k_scan_f64m, k_scan_fp32, k_scan_fp32_pts,
+ * k_offset_table, k_scan_split) with two HIP events recorded on the stream the
+ * kernel is launched on; fc_profile_enable(0) stops (records are kept).
+ * fc_profile_read waits for the recorded launches of one kernel and returns
+ * their count and summed duration in milliseconds.  Thread-safe; profiling
+ * adds two event records per launch.
+ */
+int fc_profile_enable(int32_t on);
+int fc_profile_read(const char *kernel, int64_t *launches, double *total_ms);
 
 /* ------------------------------------------------------------------------
  * Serving: FC requests against resident grids, with continuous batching.

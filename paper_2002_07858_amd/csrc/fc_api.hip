@@ -282,55 +282,136 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
     return FC_OK;
 }
 
-int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d, const int64_t *p_idx,
-            double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p, hipStream_t stream)
-{
-    g_last_error.clear();
-    if (!g) return fail(FC_ERR_INVALID_ARG, "fc_scan: grid is NULL");
-    if (form != FC_FORM_FP64 && form != FC_FORM_FP32 && form != FC_FORM_SPLIT_BF16 &&
-        form != FC_FORM_SPLIT_FP16)
-        return fail(FC_ERR_INVALID_ARG, "fc_scan: bad form %d", form);
-    if (!(g->forms & (uint32_t)form))
-        return fail(FC_ERR_STATE, "fc_scan: form %d was not built for this grid", form);
-    if (K < 0) return fail(FC_ERR_INVALID_ARG, "fc_scan: K=%lld < 0", (long long)K);
-    if (K == 0) return FC_OK;
-    if (!d || !p_idx || !dchi2 || !chi2_min || !argmin || !chi2_p)
-        return fail(FC_ERR_INVALID_ARG, "fc_scan: NULL device pointer");
-    if (K > (int64_t(1) << 30))
-        return fail(FC_ERR_INVALID_ARG, "fc_scan: K=%lld > 2^30 universes per call", (long long)K);
-    hipError_t e;
-    if (form == FC_FORM_FP64) {
-        if ((e = fcx::launch_scan_fp64(g, K, d, p_idx, dchi2, chi2_min, argmin, chi2_p, stream)) !=
-            hipSuccess)
-            return hip_fail(e, "fc_scan: fp64 launch");
-        return FC_OK;
-    }
-    if (form == FC_FORM_FP32) {
-        unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
-        if ((e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
-            (e = fcx::launch_scan_fp32(g, K, d, p_idx, 0, g->G, keys, chi2_p, stream)) !=
-                hipSuccess ||
-            (e = fcx::launch_finalize(K, p_idx, keys, chi2_min, argmin, chi2_p, dchi2, stream)) !=
-                hipSuccess)
-            return hip_fail(e, "fc_scan: fp32 launch");
-        return FC_OK;
-    }
-    if (form == FC_FORM_SPLIT_BF16 || form == FC_FORM_SPLIT_FP16) {
-        unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
-        if ((e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
-            (e = fcx::launch_scan_split(g, form == FC_FORM_SPLIT_FP16, K, d, p_idx, 0, g->G, keys,
-                                        chi2_p, stream)) != hipSuccess ||
-            (e = fcx::launch_finalize(K, p_idx, keys, chi2_min, argmin, chi2_p, dchi2, stream)) !=
-                hipSuccess)
-            return hip_fail(e, "fc_scan: split launch");
-        return FC_OK;
-    }
-    return fail(FC_ERR_UNSUPPORTED, "fc_scan: form %d not implemented", form);
-}
+}  // extern "C"
 
 namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Scratch memory of one scan call: stream-ordered allocations freed at the
+// end of the call (in stream order), or pieces of a fixed region owned by
+// someone else.
+struct Scratch {
+    hipStream_t st = nullptr;
+    char *base = nullptr;  // fixed region, or nullptr for stream-ordered allocations
+    size_t bytes = 0, used = 0;
+    std::vector<void *> owned;
+
+    hipError_t take(size_t n, void **out)
+    {
+        n = align256(n);
+        if (base) {
+            if (n > bytes - used) return hipErrorOutOfMemory;
+            *out = base + used;
+            used += n;
+            return hipSuccess;
+        }
+        const hipError_t e = hipMallocAsync(out, n, st);
+        if (e == hipSuccess) owned.push_back(*out);
+        return e;
+    }
+    // what is left of a fixed region (nullptr, 0 for stream-ordered scratch)
+    void *rest(size_t *n) const
+    {
+        *n = base ? bytes - used : 0;
+        return base ? base + used : nullptr;
+    }
+    hipError_t release()
+    {
+        hipError_t e = hipSuccess;
+        for (void *p : owned) {
+            const hipError_t ef = hipFreeAsync(p, st);
+            if (e == hipSuccess) e = ef;
+        }
+        owned.clear();
+        return e;
+    }
+};
+
+bool valid_form(int32_t form)
+{
+    return form == FC_FORM_FP64 || form == FC_FORM_FP32 || form == FC_FORM_SPLIT_BF16 ||
+           form == FC_FORM_SPLIT_FP16;
+}
+
+// The scan of fc_scan once the arguments are checked: chi2_min, argmin and
+// chi2_p may be nullptr (the keys and chi2_p then live in scratch).
+int scan_checked(const char *fn, const fc_grid *g, int32_t form, int64_t K, const double *d,
+                 const int64_t *p_idx, double *dchi2, double *chi2_min, int64_t *argmin,
+                 double *chi2_p, hipStream_t stream, Scratch &sc)
+{
+    hipError_t e = hipSuccess;
+    double *cp = chi2_p;
+    if (!cp && (e = sc.take(sizeof(double) * (size_t)K, reinterpret_cast<void **>(&cp))) !=
+                   hipSuccess)
+        goto fail_alloc;
+    if (form == FC_FORM_FP64) {
+        size_t rest = 0;
+        void *r = sc.rest(&rest);
+        if ((e = fcx::launch_scan_fp64(g, K, d, p_idx, dchi2, chi2_min, argmin, cp, stream,
+                                       static_cast<fcx::Fp64Part *>(r), rest)) != hipSuccess) {
+            (void)sc.release();
+            return hip_fail(e, fn);
+        }
+    } else {
+        unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
+        if (!keys && (e = sc.take(sizeof(uint64_t) * (size_t)K,
+                                  reinterpret_cast<void **>(&keys))) != hipSuccess)
+            goto fail_alloc;
+        if ((e = fcx::launch_init_keys(K, keys, cp, stream)) != hipSuccess ||
+            (e = (form == FC_FORM_FP32)
+                     ? fcx::launch_scan_fp32(g, K, d, p_idx, 0, g->G, keys, cp, stream)
+                     : fcx::launch_scan_split(g, form == FC_FORM_SPLIT_FP16, K, d, p_idx, 0,
+                                              g->G, keys, cp, stream)) != hipSuccess ||
+            (e = fcx::launch_finalize(K, p_idx, keys, chi2_min, argmin, cp, dchi2, stream)) !=
+                hipSuccess) {
+            (void)sc.release();
+            return hip_fail(e, fn);
+        }
+    }
+    if ((e = sc.release()) != hipSuccess) return hip_fail(e, fn);
+    return FC_OK;
+fail_alloc:
+    (void)sc.release();
+    if (sc.base)
+        return fail(FC_ERR_INVALID_ARG, "%s: K=%lld needs more than the %zu bytes of scratch", fn,
+                    (long long)K, sc.bytes);
+    return hip_fail(e, fn);
+}
+
+// Argument checks of fc_scan (and its no-allocation variant).
+int check_scan(const char *fn, const fc_grid *g, int32_t form, int64_t K, const double *d,
+               const int64_t *p_idx, const double *dchi2)
+{
+    if (!g) return fail(FC_ERR_INVALID_ARG, "%s: grid is NULL", fn);
+    if (!valid_form(form)) return fail(FC_ERR_INVALID_ARG, "%s: bad form %d", fn, form);
+    if (!(g->forms & (uint32_t)form))
+        return fail(FC_ERR_STATE, "%s: form %d was not built for this grid", fn, form);
+    if (K < 0) return fail(FC_ERR_INVALID_ARG, "%s: K=%lld < 0", fn, (long long)K);
+    if (K > (int64_t(1) << 30))
+        return fail(FC_ERR_INVALID_ARG, "%s: K=%lld > 2^30 universes per call", fn, (long long)K);
+    if (K > 0 && (!d || !p_idx || !dchi2))
+        return fail(FC_ERR_INVALID_ARG, "%s: NULL d, p_idx or dchi2", fn);
+    return FC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d, const int64_t *p_idx,
+            double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p, hipStream_t stream)
+{
+    g_last_error.clear();
+    const int rc = check_scan("fc_scan", g, form, K, d, p_idx, dchi2);
+    if (rc != FC_OK || K == 0) return rc;
+    Scratch sc;
+    sc.st = stream;
+    return scan_checked("fc_scan", g, form, K, d, p_idx, dchi2, chi2_min, argmin, chi2_p, stream,
+                        sc);
+}
+
+namespace {
 
 // Workspace of a points scan over nq grid points: p_idx [K] int64 and, for
 // the FP32 form, the tile prefix [n_pts+1] int64 and the offset table
@@ -399,7 +480,7 @@ int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t 
     if (n_pts == 0) return fail(FC_ERR_INVALID_ARG, "fc_scan_points: K > 0 universes, no points");
     if (K > (int64_t(1) << 30))
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points: K=%lld > 2^30", (long long)K);
-    if (!p || !seg_off || !d || !workspace || !dchi2 || !chi2_min || !argmin || !chi2_p)
+    if (!p || !seg_off || !d || !workspace || !dchi2)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points: NULL device pointer");
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return fail(FC_ERR_INVALID_ARG, "fc_scan_points: workspace not 256-byte aligned");
@@ -411,16 +492,30 @@ int fc_scan_points(const fc_grid *g, int32_t form, int64_t n_pts, const int64_t 
     hipError_t e;
     if ((e = fcx::launch_expand_segments(K, n_pts, seg_off, p, w.p_idx, stream)) != hipSuccess)
         return hip_fail(e, "fc_scan_points: segment expansion");
+    Scratch sc;
+    sc.st = stream;
     if (form != FC_FORM_FP32)
-        return fc_scan(g, form, K, d, w.p_idx, dchi2, chi2_min, argmin, chi2_p, stream);
+        return scan_checked("fc_scan_points", g, form, K, d, w.p_idx, dchi2, chi2_min, argmin,
+                            chi2_p, stream, sc);
+    double *cp = chi2_p;
     unsigned long long *keys = reinterpret_cast<unsigned long long *>(chi2_min);
+    if ((!cp && (e = sc.take(sizeof(double) * (size_t)K, reinterpret_cast<void **>(&cp))) !=
+                    hipSuccess) ||
+        (!keys && (e = sc.take(sizeof(uint64_t) * (size_t)K, reinterpret_cast<void **>(&keys))) !=
+                      hipSuccess)) {
+        (void)sc.release();
+        return hip_fail(e, "fc_scan_points: scratch");
+    }
     if ((e = fcx::launch_offset_table(g, n_pts, p, 0, g->G, w.T, stream)) != hipSuccess ||
-        (e = fcx::launch_init_keys(K, keys, chi2_p, stream)) != hipSuccess ||
+        (e = fcx::launch_init_keys(K, keys, cp, stream)) != hipSuccess ||
         (e = fcx::launch_scan_fp32_points(g, n_pts, p, seg_off, K, d, 0, g->G, w.T, w.tile_start,
-                                          keys, chi2_p, stream)) != hipSuccess ||
-        (e = fcx::launch_finalize(K, w.p_idx, keys, chi2_min, argmin, chi2_p, dchi2, stream)) !=
-            hipSuccess)
+                                          keys, cp, stream)) != hipSuccess ||
+        (e = fcx::launch_finalize(K, w.p_idx, keys, chi2_min, argmin, cp, dchi2, stream)) !=
+            hipSuccess) {
+        (void)sc.release();
         return hip_fail(e, "fc_scan_points: fp32 launch");
+    }
+    if ((e = sc.release()) != hipSuccess) return hip_fail(e, "fc_scan_points: scratch");
     return FC_OK;
 }
 

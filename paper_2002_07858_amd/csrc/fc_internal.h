@@ -239,6 +239,23 @@ struct fc_grid {
 // ---- launchers (defined in the .hip files) ------------------------------
 namespace fcx {
 
+// Record a failure for fc_last_error on the calling thread; returns code.
+int set_last_error(int code, const char *msg);
+
+// Kernel timing (fc_profile_enable): while enabled, brackets the launches made
+// in its scope by HIP events on the launch stream.
+class ProfScope {
+public:
+    ProfScope(hipStream_t st, const char *name);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+
+private:
+    hipStream_t st_;
+    int slot_;
+};
+
 hipError_t launch_offset(const double *S64, int64_t G, int N, double *off, double *dev,
                          hipStream_t st);
 hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *stat, int stat_mode,
@@ -272,7 +289,8 @@ hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const 
 hipError_t launch_init_keys(int64_t K, unsigned long long *keys, double *chi2_p, hipStream_t st,
                             double chi2_p_fill = __builtin_nan(""));
 // p_idx may be nullptr: then every universe's true point is p_uniform.
-// chi2_min may alias keys (decoded in place).  p_limit > 0: a true point
+// chi2_min may alias keys (decoded in place); chi2_min and argmin may be
+// nullptr (not written).  p_limit > 0: a true point
 // outside [0, p_limit) gives dchi2 = NaN (its chi2_p was never written).
 hipError_t launch_finalize(int64_t K, const int64_t *p_idx, const unsigned long long *keys,
                            double *chi2_min, int64_t *argmin, const double *chi2_p, double *dchi2,

@@ -463,7 +463,7 @@ __global__ __launch_bounds__(kPtsTile) __attribute__((amdgpu_waves_per_eu(2))) v
     const uint4 *__restrict__ R32, const double *__restrict__ S64, const double *__restrict__ d,
     int64_t G, int64_t n_pts, const int64_t *__restrict__ p, const int64_t *__restrict__ seg_off,
     const int64_t *__restrict__ tile_start, const float *__restrict__ T, int64_t groups_per_xcd,
-    int64_t q_lo, int64_t q_hi, int64_t q_per_chunk,
+    int64_t q_lo, int64_t q_hi, int64_t q_per_chunk, int64_t K,
     unsigned long long *__restrict__ keys, double *__restrict__ chi2_p)
 {
     constexpr int NS = n_ksteps(N);
@@ -497,7 +497,9 @@ __global__ __launch_bounds__(kPtsTile) __attribute__((amdgpu_waves_per_eu(2))) v
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int64_t u = s0 + kPtsTile * i + tid;
-    const bool act = u < s1;
+    // (the row must also lie in [0, K): offsets that break their contract
+    // read and write nothing outside the arrays)
+    const bool act = u < s1 && u >= 0 && u < K;
 
     Fp32Fast<N> L;
     const double *__restrict__ sp = S64 + pp * N;  // uniform: scalar loads
@@ -542,7 +544,8 @@ __global__ __launch_bounds__(256) void k_init_keys(int64_t K, unsigned long long
 }
 
 // Decode the keys.  chi2_min may be the key buffer itself (decoded in place:
-// each thread reads its key before it writes the same element).  A universe
+// each thread reads its key before it writes the same element); chi2_min and
+// argmin may be nullptr.  A universe
 // with no finite chi2 keeps Algorithm 1's initial state and gets a NaN dchi2,
 // and so does one whose true point is outside [0, p_limit) when p_limit > 0.
 __global__ __launch_bounds__(256) void k_finalize(int64_t K, const int64_t *__restrict__ p_idx,
@@ -571,8 +574,8 @@ __global__ __launch_bounds__(256) void k_finalize(int64_t K, const int64_t *__re
             if (pu < 0 || pu >= p_limit) dc = __builtin_nan("");
         }
     }
-    chi2_min[u] = cmin;
-    argmin[u] = am;
+    if (chi2_min) chi2_min[u] = cmin;
+    if (argmin) argmin[u] = am;
     dchi2[u] = dc;
 }
 
@@ -636,6 +639,7 @@ static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, co
         resident_slots(reinterpret_cast<const void *>(&k_scan_fp32<N>), 64 * kWavesPerBlock);
     const ScanGeometry sg = scan_geometry(K, nq, slots, kFp32UnivPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
+    ProfScope prof(st, "k_scan_fp32");
     hipLaunchKernelGGL((k_scan_fp32<N>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, st,
                        g->R32, d, p_idx, K, q0, q0 + nq, sg.n_utiles, sg.q_per_chunk, keys, chi2_p);
     return hipGetLastError();
@@ -688,9 +692,10 @@ static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64
     const ScanGeometry sg = scan_geometry(max_tiles * kPtsTile, nq, slots, kPtsTile);
     const int64_t blocks = n_tiles * sg.n_qchunks;
     hipLaunchKernelGGL(k_tile_prefix, dim3(1), dim3(1024), 0, st, n_pts, seg_off, tile_start);
+    ProfScope prof(st, "k_scan_fp32_pts");
     hipLaunchKernelGGL((k_scan_fp32_pts<N>), dim3((unsigned)blocks), dim3(kPtsTile), 0,
                        st, g->R32, g->S64, d, g->G, n_pts, p, seg_off, tile_start, T, groups_per_xcd,
-                       q0, q0 + nq, sg.q_per_chunk, keys, chi2_p);
+                       q0, q0 + nq, sg.q_per_chunk, K, keys, chi2_p);
     return hipGetLastError();
 }
 
@@ -790,6 +795,7 @@ static hipError_t launch_offset_table_n(const fc_grid *g, int64_t n_pts, const i
                                         int64_t q0, int64_t nq, float *T, hipStream_t st)
 {
     const int64_t blocks = nq < 65536 ? nq : 65536;
+    ProfScope prof(st, "k_offset_table");
     hipLaunchKernelGGL((k_offset_table<N>), dim3((unsigned)blocks), dim3(256), 0, st, g->R32, g->S64,
                        g->G, q0, nq, n_pts, p, T);
     return hipGetLastError();

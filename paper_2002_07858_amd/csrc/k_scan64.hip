@@ -98,7 +98,7 @@ __device__ __forceinline__ double f64_row_sum(double a, double b)
 }
 
 template <int NB>
-__global__ __launch_bounds__(64 * kF64Waves) __attribute__((amdgpu_waves_per_eu(2))) void
+__global__ __launch_bounds__(64 * kF64Waves) __attribute__((amdgpu_waves_per_eu(3))) void
 k_scan_f64m(const uint4 *__restrict__ R64, const double *__restrict__ d,
             const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t q0, int64_t nq,
             int64_t n_utiles, int64_t q_per_chunk, Fp64Part *__restrict__ part,
@@ -184,9 +184,9 @@ k_scan_f64m(const uint4 *__restrict__ R64, const double *__restrict__ d,
         if (p >= qb && p < qe) chi2_p[u_own] = cp;
         return;
     }
-    chi2_min[u_own] = best;
-    argmin[u_own] = qbest;
-    chi2_p[u_own] = cp;
+    if (chi2_min) chi2_min[u_own] = best;
+    if (argmin) argmin[u_own] = qbest;
+    if (chi2_p) chi2_p[u_own] = cp;
     dchi2[u_own] = cp - best;
 }
 
@@ -198,7 +198,8 @@ k_scan_f64m(const uint4 *__restrict__ R64, const double *__restrict__ d,
 // chunks partition the grid in order, so that is the earlier chunk, and the
 // result is the sequential scan's.  Chunk values are never NaN (a NaN chi2
 // never passes "<"), and a chunk with no finite value reports (+inf, p).  A
-// true point outside [0, G) was owned by no chunk: chi2_p = NaN.
+// true point outside [0, G) was owned by no chunk: chi2_p = NaN.  chi2_min
+// and argmin may be nullptr; chi2_p holds the owners' values on entry.
 __global__ __launch_bounds__(256) void k_fp64_merge(const Fp64Part *__restrict__ part,
                                                    int64_t n_chunks, const int64_t *__restrict__ p_idx,
                                                    int64_t K, int64_t G, double *__restrict__ dchi2,
@@ -230,8 +231,8 @@ __global__ __launch_bounds__(256) void k_fp64_merge(const Fp64Part *__restrict__
     }
     if (lane != 0) return;
     const double cp = (p >= 0 && p < G) ? chi2_p[u] : __builtin_nan("");
-    chi2_min[u] = best;
-    argmin[u] = qbest;
+    if (chi2_min) chi2_min[u] = best;
+    if (argmin) argmin[u] = qbest;
     chi2_p[u] = cp;
     dchi2[u] = cp - best;
 }
@@ -284,9 +285,12 @@ hipError_t launch_f64m_nb(const fc_grid *g, int64_t K, const double *d, const in
     if (part)
         hipLaunchKernelGGL(k_fill_nan, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, K,
                            chi2_p);
-    hipLaunchKernelGGL(k_scan_f64m<NB>, dim3((unsigned)blocks), dim3(64 * kF64Waves), 0, st, g->R64,
-                       d, p_idx, K, g->N, (int64_t)0, G, sg.n_utiles, qpc, part, dchi2, chi2_min,
-                       argmin, chi2_p);
+    {
+        ProfScope prof(st, "k_scan_f64m");
+        hipLaunchKernelGGL(k_scan_f64m<NB>, dim3((unsigned)blocks), dim3(64 * kF64Waves), 0, st,
+                           g->R64, d, p_idx, K, g->N, (int64_t)0, G, sg.n_utiles, qpc, part,
+                           dchi2, chi2_min, argmin, chi2_p);
+    }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && part) {
         hipLaunchKernelGGL(k_fp64_merge, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, st, part,

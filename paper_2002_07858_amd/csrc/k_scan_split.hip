@@ -60,7 +60,11 @@ __device__ __forceinline__ void split8(const float (&x)[8], uint4 &hi, uint4 &lo
 // Per-universe state a wave carries through its range of grid points.
 template <int NK, int NC>
 struct SplitLane {
-    uint4 dhi[NC][NK], dlo[NC][NK];  // B operands: 2^ed (d - o) split hi + lo
+    uint4 dhi[NC][NK], dlo[NC][NK];  // B operands: 2^(ed - eu) (d - o) split hi + lo
+    uint32_t eu_pk;                  // per-universe exponents eu (FP16 range), 8 bits per
+                                     // column block; 0 unless far outside the grid's range
+    int e_own;                       // eu of the universe this lane owns after the reduction
+    bool scaled;                     // some universe of the wave has eu != 0 (wave-uniform)
     int64_t p_own;
     float best;
     uint32_t qbest;
@@ -71,7 +75,7 @@ struct SplitLane {
 // One grid point: contract the record in `cur`, fold chi2 into the running
 // minimum, and (if more) bring the next record into `nxt` (separate LDS
 // objects, see the FP32 form).
-template <int NK, int NB, int NC, bool FP16>
+template <int NK, int NB, int NC, bool FP16, bool SCALED>
 __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *__restrict__ R16,
                                             const uint4 *cur, uint4 *nxt, SplitLane<NK, NC> &L)
 {
@@ -86,7 +90,9 @@ __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *_
     if (more) record_to_lds<REC, THREADS>(R16 + (q + 1) * REC, nxt, tid);
     __builtin_amdgcn_sched_barrier(0);  // issue the copy before the contraction
 
-    // every accumulator starts at -2^(eq+ed) u_q for its rows
+    // every accumulator starts at -2^(eq+ed-eu) u_q for its rows (the record
+    // holds -2^(eq+ed) u_q; eu = 0 unless the wave holds a universe far outside
+    // the grid's range, which only then costs the rescale)
     const float4 *ul = reinterpret_cast<const float4 *>(cur + UU) + grp * 4;
     v4f acc[NC][NB];
 #pragma unroll
@@ -94,6 +100,18 @@ __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *_
         const float4 c0 = ul[b];
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c][b] = v4f{c0.x, c0.y, c0.z, c0.w};
+    }
+    if constexpr (SCALED) {
+        {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int e = (int)((L.eu_pk >> (8 * c)) & 255u);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[c][b][j] = ldexpf(acc[c][b][j], -e);
+            }
+        }
     }
 #pragma unroll
     for (int s = 0; s < NK; ++s) {
@@ -155,7 +173,8 @@ __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *_
                                                           __float_as_uint(kk), false, false);
         kk = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
     }
-    const float chi2 = kk * unscale;
+    float chi2 = kk * unscale;
+    if constexpr (SCALED) chi2 = ldexpf(chi2, 2 * L.e_own);
 
     if (q == L.p_own) {
         L.cp = chi2;
@@ -194,25 +213,48 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
 
     SplitLane<NK, NC> L;
     // the universes, split once: B operand of k-step s for column block c holds
-    // bins 32s + 8*grp + e of universe u0 + 16c + col, as 2^ed (d - o)
+    // bins 32s + 8*grp + e of universe u0 + 16c + col, as 2^(ed - eu) (d - o).
+    // FP16: eu >= 0 is the universe's own power of two keeping its largest
+    // |d - o| 2^(ed - eu) below 2^15 (FP16's largest finite value is just under
+    // 2^16); it is 0 for every universe within 4x the grid's range of S - o
+    // (ed keeps that below 2^13), and then the values are the grid-wide scale's.
+    bool any_scaled = false;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const int64_t u = u0 + 16 * c + col;
+        int eu = 0;
+        if constexpr (FP16) {
+            double m = 0.0;
+            for (int s = 0; s < NK; ++s)
+                for (int e = 0; e < 8; ++e) {
+                    const int k = 32 * s + 8 * grp + e;
+                    if (u < K && k < N) m = fmax(m, fabs(d[u * N + k] - off[k]));
+                }
+            m = ldexp(m, ed);
+            m = fmax(m, __shfl_xor(m, 16));  // the universe's four lane rows
+            m = fmax(m, __shfl_xor(m, 32));
+            if (m >= 32768.0 && m <= 1.0e300) eu = ilogb(m) - 14;
+        }
+        if (c == 0) L.eu_pk = 0;
+        L.eu_pk |= (uint32_t)eu << (8 * c);
+        any_scaled = any_scaled || eu != 0;
 #pragma unroll
         for (int s = 0; s < NK; ++s) {
             float x[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int k = 32 * s + 8 * grp + e;
-                x[e] = (u < K && k < N) ? (float)ldexp(d[u * N + k] - off[k], ed) : 0.0f;
+                x[e] = (u < K && k < N) ? (float)ldexp(d[u * N + k] - off[k], ed - eu) : 0.0f;
             }
             split8<FP16>(x, L.dhi[c][s], L.dlo[c][s]);
         }
     }
+    L.scaled = __any(any_scaled);
     // after the reduction, lane l holds column block cl of universe column col
     const int cl = (NC == 4) ? grp : (grp >> 1);
     const bool owner = (NC == 4) ? true : ((grp & 1) == 0);
     const int64_t u_own = u0 + 16 * cl + col;
+    L.e_own = (int)((L.eu_pk >> (8 * cl)) & 255u);
     L.p_own = (u_own < K) ? (it.p_idx ? it.p_idx[u_own] : it.p) : -1;
     L.best = __builtin_inff();
     L.qbest = 0xffffffffu;
@@ -222,12 +264,22 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
     record_to_lds<REC, THREADS>(R16 + qb * REC, buf0, tid);
     wait_record_loads();
     __syncthreads();
+    // a wave with a universe outside the FP16 range runs the loop that
+    // rescales its accumulators; every other wave runs the plain one
     int64_t q = qb;
-    for (; q + 1 < qe; q += 2) {
-        split_point<NK, NB, NC, FP16>(q, true, R16, buf0, buf1, L);
-        split_point<NK, NB, NC, FP16>(q + 1, q + 2 < qe, R16, buf1, buf0, L);
+    if (FP16 && L.scaled) {
+        for (; q + 1 < qe; q += 2) {
+            split_point<NK, NB, NC, FP16, FP16>(q, true, R16, buf0, buf1, L);
+            split_point<NK, NB, NC, FP16, FP16>(q + 1, q + 2 < qe, R16, buf1, buf0, L);
+        }
+        if (q < qe) split_point<NK, NB, NC, FP16, FP16>(q, false, R16, buf0, buf1, L);
+    } else {
+        for (; q + 1 < qe; q += 2) {
+            split_point<NK, NB, NC, FP16, false>(q, true, R16, buf0, buf1, L);
+            split_point<NK, NB, NC, FP16, false>(q + 1, q + 2 < qe, R16, buf1, buf0, L);
+        }
+        if (q < qe) split_point<NK, NB, NC, FP16, false>(q, false, R16, buf0, buf1, L);
     }
-    if (q < qe) split_point<NK, NB, NC, FP16>(q, false, R16, buf0, buf1, L);
 
     if (owner && u_own < K) {
         if (L.have_cp) it.chi2_p[u_own] = (double)L.cp;
@@ -240,7 +292,7 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
 }
 
 template <int NK, int NB, int NC, bool FP16>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_scan_split(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scan_split(
     const uint4 *__restrict__ R16, const double *__restrict__ d, const double *__restrict__ off,
     int ed, const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t q_lo, int64_t q_hi,
     int64_t n_utiles, int64_t q_per_chunk, unsigned long long *__restrict__ keys,
@@ -312,6 +364,7 @@ static hipError_t launch_split_t(const fc_grid *g, int64_t K, const double *d,
     const ScanGeometry sg = scan_geometry(K, nq, slots, 16 * NC * kWavesPerBlock);
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     const uint4 *R = FP16 ? g->RH16 : g->RB16;
+    ProfScope prof(st, "k_scan_split");
     hipLaunchKernelGGL((k_scan_split<NK, NB, NC, FP16>), dim3((unsigned)blocks), dim3(256), 0, st, R,
                        d, g->off, FP16 ? g->ed16 : 0, p_idx, K, g->N, q0, q0 + nq, sg.n_utiles,
                        sg.q_per_chunk, keys, chi2_p);

@@ -50,7 +50,7 @@ EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_scan_points",
             "fc_grid_inverse_cov", "fc_grid_info",
             "fc_grid_device_bytes", "fc_grid_destroy", "fc_last_error", "fc_server_create", "fc_server_submit",
             "fc_server_submit_drawn", "fc_server_poll",
-            "fc_server_stats", "fc_server_destroy")
+            "fc_server_stats", "fc_server_destroy", "fc_profile_enable", "fc_profile_read")
 
 
 class FCError(RuntimeError):
@@ -110,6 +110,10 @@ def lib():
         L.fc_server_stats.argtypes = [_p, _p, _p, _p, _p]
         L.fc_server_destroy.argtypes = [_p]
         L.fc_server_destroy.restype = None
+        L.fc_profile_enable.argtypes = [_i32]
+        L.fc_profile_enable.restype = ctypes.c_int
+        L.fc_profile_read.argtypes = [ctypes.c_char_p, _p, _p]
+        L.fc_profile_read.restype = ctypes.c_int
         for name in ("fc_server_create", "fc_server_submit", "fc_server_submit_drawn",
                      "fc_server_poll", "fc_server_stats"):
             getattr(L, name).restype = ctypes.c_int
@@ -158,6 +162,22 @@ def _dev(t, dtype_name: str, name: str):
     return _p(t.data_ptr()) if t.numel() else None
 
 
+def _need(t, n: int, name: str):
+    """Size check before a device pointer goes to the library: a tensor that
+    is too short would be read or written past its end by the kernels."""
+    if t is not None and int(t.numel()) < int(n):
+        raise ValueError(f"{name} holds {int(t.numel())} elements, the call needs {int(n)}")
+
+
+def _rows(d, N: int, name: str = "d") -> int:
+    """K of a [K][N] universe tensor (checked against the grid's bin count)."""
+    if d is None:
+        return 0
+    if d.dim() != 2 or int(d.shape[1]) != int(N):
+        raise ValueError(f"{name} must be [K][{N}] for this grid, got {tuple(d.shape)}")
+    return int(d.shape[0])
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -172,6 +192,21 @@ class Grid:
 
     def __init__(self, handle: int):
         self.handle = handle
+        self._shape = None
+
+    @property
+    def N(self) -> int:
+        return self._sizes()[0]
+
+    @property
+    def G(self) -> int:
+        return self._sizes()[1]
+
+    def _sizes(self):
+        if self._shape is None:
+            i = fc_grid_info(self)
+            self._shape = (i["N"], i["G"])
+        return self._shape
 
     @property
     def _h(self):
@@ -227,9 +262,14 @@ def fc_build_covariance(grid: Grid, frac_cov, stat_mode=FC_STAT_PEARSON, stat_di
     return int(bad[0])
 
 
-def fc_scan(grid: Grid, form: int, d, p_idx, dchi2, chi2_min, argmin, chi2_p, stream=None):
-    """Enqueue the scan of K = d.shape[0] universes (all arrays torch CUDA tensors)."""
-    K = int(d.shape[0]) if d is not None else 0
+def fc_scan(grid: Grid, form: int, d, p_idx, dchi2, chi2_min=None, argmin=None, chi2_p=None,
+            stream=None):
+    """Enqueue the scan of K = d.shape[0] universes (all arrays torch CUDA
+    tensors; chi2_min, argmin and chi2_p are optional outputs)."""
+    K = _rows(d, grid.N)
+    for t, n in ((p_idx, "p_idx"), (dchi2, "dchi2"), (chi2_min, "chi2_min"), (argmin, "argmin"),
+                 (chi2_p, "chi2_p")):
+        _need(t, K, n)
     _check(lib().fc_scan(grid._h, int(form), K, _dev(d, "f64", "d"), _dev(p_idx, "i64", "p_idx"),
                          _dev(dchi2, "f64", "dchi2"), _dev(chi2_min, "f64", "chi2_min"),
                          _dev(argmin, "i64", "argmin"), _dev(chi2_p, "f64", "chi2_p"),
@@ -244,14 +284,17 @@ def fc_scan_points_workspace(grid: Grid, form: int, n_pts: int, K: int) -> int:
     return b.value
 
 
-def fc_scan_points(grid: Grid, form: int, p, seg_off, d, dchi2, chi2_min, argmin, chi2_p,
-                   workspace=None, stream=None):
+def fc_scan_points(grid: Grid, form: int, p, seg_off, d, dchi2, chi2_min=None, argmin=None,
+                   chi2_p=None, workspace=None, stream=None):
     """Enqueue the scan of universes grouped by true point: segment i of
     seg_off (n_pts + 1 offsets) holds universes of true point p[i].  The
     workspace (a uint8 CUDA tensor) is allocated here when not given."""
     import torch
-    K = int(d.shape[0])
+    K = _rows(d, grid.N)
     n_pts = int(p.numel())
+    _need(seg_off, n_pts + 1, "seg_off")
+    for t, n in ((dchi2, "dchi2"), (chi2_min, "chi2_min"), (argmin, "argmin"), (chi2_p, "chi2_p")):
+        _need(t, K, n)
     need = fc_scan_points_workspace(grid, form, n_pts, K)
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=d.device)
@@ -268,13 +311,16 @@ def fc_scan_state_init(keys, chi2_p, stream=None):
     """Enqueue keys = none, chi2_p = 0 for a grid-sliced scan.  keys is an
     int64 CUDA tensor holding the uint64 keys bit for bit."""
     K = int(keys.numel())
+    _need(chi2_p, K, "chi2_p")
     _check(lib().fc_scan_state_init(K, _dev(keys, "i64", "keys"), _dev(chi2_p, "f64", "chi2_p"),
                                     _stream(stream)))
 
 
 def fc_scan_slice(grid: Grid, form: int, d, p_idx, q0: int, nq: int, keys, chi2_p, stream=None):
     """Enqueue the scan of grid points [q0, q0 + nq), merged into (keys, chi2_p)."""
-    K = int(d.shape[0])
+    K = _rows(d, grid.N)
+    for t, n in ((p_idx, "p_idx"), (keys, "keys"), (chi2_p, "chi2_p")):
+        _need(t, K, n)
     _check(lib().fc_scan_slice(grid._h, int(form), K, _dev(d, "f64", "d"),
                                _dev(p_idx, "i64", "p_idx"), int(q0), int(nq),
                                _dev(keys, "i64", "keys"), _dev(chi2_p, "f64", "chi2_p"),
@@ -294,8 +340,11 @@ def fc_scan_points_slice(grid: Grid, form: int, p, seg_off, d, q0: int, nq: int,
     """Enqueue the points scan of grid points [q0, q0 + nq), merged into
     (keys, chi2_p).  The workspace is allocated here when not given."""
     import torch
-    K = int(d.shape[0])
+    K = _rows(d, grid.N)
     n_pts = int(p.numel())
+    _need(seg_off, n_pts + 1, "seg_off")
+    for t, n in ((keys, "keys"), (chi2_p, "chi2_p")):
+        _need(t, K, n)
     need = fc_scan_points_slice_workspace(grid, form, n_pts, K, nq)
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=d.device)
@@ -311,6 +360,9 @@ def fc_scan_state_finalize(grid: Grid, p_idx, keys, chi2_p, dchi2, chi2_min, arg
                            stream=None):
     """Enqueue the decoding of a merged sliced-scan state into fc_scan's outputs."""
     K = int(keys.numel())
+    for t, n in ((p_idx, "p_idx"), (chi2_p, "chi2_p"), (dchi2, "dchi2"), (chi2_min, "chi2_min"),
+                 (argmin, "argmin")):
+        _need(t, K, n)
     _check(lib().fc_scan_state_finalize(grid._h, K, _dev(p_idx, "i64", "p_idx"),
                                         _dev(keys, "i64", "keys"), _dev(chi2_p, "f64", "chi2_p"),
                                         _dev(dchi2, "f64", "dchi2"),
@@ -323,6 +375,8 @@ def fc_critical_value(seg_off, dchi2, alpha, crit, n_bins=200, hist_hi=50.0, his
     """Enqueue critical values (and histograms) for n_seg = seg_off.numel()-1 segments."""
     a = _host(np.atleast_1d(alpha), np.float64)
     n_seg = int(seg_off.numel()) - 1
+    _need(crit, max(n_seg, 0) * a.shape[0], "crit")
+    _need(hist, max(n_seg, 0) * (int(n_bins) + 1), "hist")
     _check(lib().fc_critical_value(n_seg, _dev(seg_off, "i64", "seg_off"),
                                    _dev(dchi2, "f64", "dchi2"), int(a.shape[0]), _hp(a),
                                    _dev(crit, "f64", "crit"), int(n_bins), float(hist_hi),
@@ -333,7 +387,10 @@ def fc_scan_fixed_m(grid: Grid, d, p_idx, dchi2, chi2_min, argmin, chi2_p, max_i
                     m_final=None, iters=None, stream=None):
     """One matrix per universe scan (M = Sigma_m^-1, m = p, iterated up to
     max_iter times at the minimiser); synchronous; torch CUDA tensors."""
-    K = int(d.shape[0])
+    K = _rows(d, grid.N)
+    for t, n in ((p_idx, "p_idx"), (dchi2, "dchi2"), (chi2_min, "chi2_min"), (argmin, "argmin"),
+                 (chi2_p, "chi2_p"), (m_final, "m_final"), (iters, "iters")):
+        _need(t, K, n)
     _check(lib().fc_scan_fixed_m(grid._h, K, _dev(d, "f64", "d"), _dev(p_idx, "i64", "p_idx"),
                                  int(max_iter), _dev(dchi2, "f64", "dchi2"),
                                  _dev(chi2_min, "f64", "chi2_min"), _dev(argmin, "i64", "argmin"),
@@ -348,7 +405,11 @@ def fc_generate_universes(grid: Grid, p, seg_off, seed: int, d, p_idx=None, coun
     p, seg_off, u_first: int64 CUDA tensors; d: float64 [K][N]; p_idx int64 [K]
     and counts int32 [K][N] optional outputs.
     """
-    K = int(d.shape[0])
+    K = _rows(d, grid.N)
+    _need(seg_off, int(p.numel()) + 1, "seg_off")
+    _need(u_first, int(p.numel()), "u_first")
+    _need(p_idx, K, "p_idx")
+    _need(counts, K * grid.N, "counts")
     _check(lib().fc_generate_universes(grid._h, int(p.numel()), _dev(p, "i64", "p"),
                                        _dev(seg_off, "i64", "seg_off"),
                                        _dev(u_first, "i64", "u_first"),
@@ -369,6 +430,9 @@ def fc_region(grid: Grid, form: int, dchi2_data, crit, accepted, pts=None, K0=25
     pa = None if pts is None else _host(pts, np.int64)
     n_pts = G if pa is None else int(pa.shape[0])
     a = _host(np.atleast_1d(alpha), np.float64)
+    _need(dchi2_data, G, "dchi2_data")
+    _need(crit, n_pts * a.shape[0], "crit")
+    _need(accepted, n_pts * a.shape[0], "accepted")
     K_used = np.zeros(n_pts, dtype=np.int64)
     rounds = ctypes.c_int32()
     evals = ctypes.c_double()
@@ -387,6 +451,9 @@ def fc_data_scan(grid: Grid, dchi2_data, central=None, stream=None):
     or None for the grid's own.  Returns (chi2_min, argmin).
     """
     c = None if central is None else _host(central, np.float64)
+    if c is not None and c.shape != (grid.N,):
+        raise ValueError(f"central must hold {grid.N} bins")
+    _need(dchi2_data, grid.G, "dchi2_data")
     m = ctypes.c_double()
     a = ctypes.c_int64()
     _check(lib().fc_data_scan(grid._h, _hp(c), _dev(dchi2_data, "f64", "dchi2_data"),
@@ -397,12 +464,16 @@ def fc_data_scan(grid: Grid, dchi2_data, central=None, stream=None):
 def fc_acceptance(grid: Grid, p, crit, dchi2_data, accepted, crit_stride=1, stream=None):
     """Enqueue accepted[k] = dchi2_data[p[k]] <= crit[k * crit_stride] (CUDA tensors)."""
     n = int(p.numel())
+    _need(accepted, n, "accepted")
+    _need(crit, (n - 1) * int(crit_stride) + 1 if n else 0, "crit")
+    _need(dchi2_data, grid.G, "dchi2_data")
     _check(lib().fc_acceptance(grid._h, n, _dev(p, "i64", "p"), _dev(crit, "f64", "crit"),
                                int(crit_stride), _dev(dchi2_data, "f64", "dchi2_data"),
                                _dev(accepted, "u8", "accepted"), _stream(stream)))
 
 
 def fc_grid_inverse_cov(grid: Grid, q0: int, nq: int, out, stream=None):
+    _need(out, int(nq) * grid.N * grid.N, "out")
     _check(lib().fc_grid_inverse_cov(grid._h, int(q0), int(nq), _dev(out, "f64", "out"),
                                      _stream(stream)))
 
@@ -415,6 +486,19 @@ def fc_grid_info(grid: Grid):
     _check(lib().fc_grid_info(grid._h, ctypes.byref(D), ctypes.byref(N), ctypes.byref(G),
                               ctypes.byref(forms)))
     return dict(D=D.value, N=N.value, G=G.value, forms=forms.value)
+
+
+def fc_profile_enable(on: bool = True):
+    """Start (clearing earlier records) or stop kernel timing with HIP events."""
+    _check(lib().fc_profile_enable(1 if on else 0))
+
+
+def fc_profile_read(kernel: str):
+    """(launches, total ms) of one kernel's timed launches since fc_profile_enable(True)."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(lib().fc_profile_read(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def fc_grid_device_bytes(grid: Grid) -> int:

@@ -9,6 +9,14 @@ argmin agreement is counted over universes that are not near-ties:
          oracle's argmin.  tau is twice the form's tolerance: two chi^2
          values within 2 tol of each other can swap order under per-value
          errors <= tol.
+argmin validity covers every compared universe, near-ties included: the
+         oracle evaluates Eq. (1) at the device's argmin q_dev, and q_dev is
+         valid when that value is a minimum up to the form's error,
+             chi2_64(d, q_dev) <= chi2_min_64 + 2 tol max(1, chi2_min_64),
+         and the device's reported minimum is chi2 at q_dev up to it,
+             |chi2_64(d, q_dev) - chi2_min_dev| <= tol max(1, chi2_p_64).
+         (A wrong q packed beside a correct chi^2 fails the second test; a
+         q that is not a minimiser fails the first.)
 """
 from __future__ import annotations
 
@@ -40,9 +48,49 @@ def report(dev: dict, ref: dict, tol: float) -> dict:
     )
 
 
-def check_invariants(dev: dict, G: int):
-    """Properties that hold for any correct scan at any size."""
+def chi2_at(pr, d, q):
+    """The oracle's chi^2 (Eq. (1), FP64) of universes d[k] at grid points q[k]."""
+    import oracle
+    d = np.asarray(d, dtype=np.float64)
+    q = np.asarray(q, dtype=np.int64)
+    out = np.empty(q.shape[0])
+    for qq in np.unique(q):
+        L = oracle.factor_range(pr.S, pr.F, pr.stat_mode, pr.stat_diag, int(qq), 1)[0]
+        for k in np.flatnonzero(q == qq):
+            out[k] = oracle.chi2(L, d[k], pr.S[qq])
+    return out
+
+
+def argmin_validity(pr, dev: dict, d, ref: dict, tol: float) -> dict:
+    """Validity of the device's argmin on every compared universe (see above).
+    Universes whose oracle minimum is not finite (no chi^2 < +inf) are left
+    to the invariants and the NaN tests."""
+    fin = np.isfinite(ref["chi2_min"])
+    am = np.asarray(dev["argmin"])
+    ok_range = (am >= 0) & (am < pr.G)
+    sel = np.flatnonzero(fin & ok_range)
+    c_at = np.full(am.shape[0], np.nan)
+    if sel.size:
+        c_at[sel] = chi2_at(pr, np.asarray(d)[sel], am[sel])
+    cmin = ref["chi2_min"]
+    gap = (c_at - cmin) / np.maximum(1.0, cmin)
+    val_err = np.abs(c_at - dev["chi2_min"]) / np.maximum(1.0, ref["chi2_p"])
+    valid = fin & ok_range & (gap <= 2.0 * tol) & (val_err <= tol)
+    n = int(fin.sum())
+    return dict(argmin_valid=float(valid[fin].mean()) if n else 1.0,
+                argmin_invalid=int(n - valid[fin].sum()),
+                argmin_gap_max=float(np.nanmax(gap[fin])) if n else 0.0,
+                chi2_min_at_argmin_err=float(np.nanmax(val_err[fin])) if n else 0.0)
+
+
+def check_invariants(dev: dict, G: int, all_finite: bool = False):
+    """Properties that hold for any correct scan at any size.  With
+    all_finite, every universe must have a finite Delta chi^2 (inputs with no
+    NaN data and every true point on the grid)."""
     dchi2, cmin, cp, am = dev["dchi2"], dev["chi2_min"], dev["chi2_p"], dev["argmin"]
+    if all_finite:
+        assert np.all(np.isfinite(dchi2)), "non-finite Delta chi^2"
+        assert np.all(np.isfinite(cmin)) and np.all(np.isfinite(cp))
     fin = np.isfinite(cp)
     assert np.all(cmin[fin] >= 0.0)
     assert np.all(dchi2[fin] >= 0.0), "Delta chi^2 < 0"

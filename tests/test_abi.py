@@ -148,3 +148,36 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_binding_checks_sizes_before_the_library(fcmod):
+    """Tensors too short for the call are refused in the binding: the kernels
+    would read or write past their ends."""
+    torch = pytest.importorskip("torch")
+    g = fcmod.Grid(0)
+    g._shape = (57, 100)  # N, G of a grid that is never touched
+    d = torch.zeros((10, 57), dtype=torch.float64)
+    p = torch.zeros(10, dtype=torch.int64)
+    out = torch.zeros(10, dtype=torch.float64)
+    with pytest.raises(ValueError, match=r"\[K\]\[57\]"):
+        fcmod.fc_scan(g, 2, torch.zeros((10, 56), dtype=torch.float64), p, out)
+    with pytest.raises(ValueError, match="p_idx"):
+        fcmod.fc_scan(g, 2, d, p[:9], out)
+    with pytest.raises(ValueError, match="chi2_p"):
+        fcmod.fc_scan(g, 2, d, p, out, chi2_p=out[:5])
+    with pytest.raises(ValueError, match="seg_off"):
+        fcmod.fc_scan_points(g, 2, p[:2], p[:2], d, out)
+    with pytest.raises(ValueError, match="crit"):
+        fcmod.fc_critical_value(p[:3], out, [0.9, 0.95], out[:3])
+    with pytest.raises(ValueError, match="keys"):
+        fcmod.fc_scan_slice(g, 2, d, p, 0, 10, p[:4], out)
+
+
+def test_profile_calls_validate(fcmod):
+    L = fcmod.lib()
+    assert L.fc_profile_read(None, None, None) == fcmod.FC_ERR_INVALID_ARG
+    assert L.fc_profile_enable(0) == fcmod.FC_OK
+    n = ctypes.c_int64(-1)
+    ms = ctypes.c_double(-1.0)
+    assert L.fc_profile_read(b"k_scan_f64m", ctypes.byref(n), ctypes.byref(ms)) == fcmod.FC_OK
+    assert n.value == 0 and ms.value == 0.0

@@ -1,27 +1,43 @@
-"""Full-size configurations on the GPU, checked on sampled universes against
-the FP64 oracle (which computes them one by one) and on properties that hold
-at any size.
+"""Full-size configurations on the GPU, checked against the FP64 oracle's
+values for a sample of universes (written by tests/golden/
+make_full_config_golden.py, which calls only the oracle) and on properties
+that hold at any size, in the launch configuration the benchmark times.
 
-c3: D=3 grid 60^3 (216 000 points), N=57, 64 true points x 4000 universes,
-    FP32 (per-universe and grouped-by-point entries) and split BF16 / FP16
-    forms on the same inputs.
-c5: D=5 grid 16^5 (1 048 576 points), N=57, 16 true points x 10 000
-    universes, FP32 (both entries) and split FP16.
+c2: D=2 100^2 (10 000 points), N=57, 256 true points x 2000 universes: every
+    universe of 4 true points and their full-K critical values.
+c3: D=3 60^3 (216 000 points), N=57, 64 true points x 4000 universes: the
+    first 64 universes of every true point plus all 4000 of 2 true points
+    (full-K critical values).
+c5: D=5 16^5 (1 048 576 points), N=57, 16 true points x 10 000 universes: the
+    first 16 universes of every true point.
+Every form (FP64, FP32 through both entries, split BF16 and FP16) runs on the
+same inputs.  Per form: the invariants on every universe (all finite: no NaN
+data, every true point on the grid), e_rel within the form's tolerance,
+argmin agreement on universes that are not near-ties (100 % for FP64 and
+FP32), the argmin's validity on every sampled universe (near-ties included),
+and the critical values of the full points within the Lipschitz bound of
+the Delta chi^2 error.
 """
 from __future__ import annotations
+
+import os
+import sys
 
 import numpy as np
 import pytest
 
 import fcgen
-import oracle
 import parity
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import make_full_config_golden as golden  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-FORM = {"fp32": 2, "split_bf16": 4, "split_fp16": 8}
+FORM = {"fp64": 1, "fp32": 2, "split_bf16": 4, "split_fp16": 8}
+ALPHA = (0.6827, 0.9, 0.95)
 
 
 @pytest.fixture(scope="module")
@@ -33,109 +49,77 @@ def fc():
     return fc
 
 
-def scan(fc, grid, form, d_t, p_t):
-    K = d_t.shape[0]
-    out = {k: torch.empty(K, dtype=torch.float64, device="cuda")
-           for k in ("dchi2", "chi2_min", "chi2_p")}
-    out["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
-    fc.fc_scan(grid, form, d_t, p_t, out["dchi2"], out["chi2_min"], out["argmin"],
-               out["chi2_p"])
-    torch.cuda.synchronize()
-    return {k: v.cpu().numpy() for k, v in out.items()}
-
-
-def scan_points(fc, grid, pr, d_t):
-    """The FP32 offset form through fc_scan_points, as the benchmark times it."""
-    K = d_t.shape[0]
-    out = {k: torch.empty(K, dtype=torch.float64, device="cuda")
-           for k in ("dchi2", "chi2_min", "chi2_p")}
-    out["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
+def scan_all(fc, pr):
+    """Every form through fc_scan_points (the benchmark's entry) and the FP32
+    form also through fc_scan; critical values of every segment."""
+    grid = fc.fc_build_grid(pr.axes, pr.S)
+    fc.fc_build_covariance(grid, pr.F, pr.stat_mode, pr.stat_diag, forms=1 | 2 | 4 | 8)
+    K = pr.K
+    d_t = torch.as_tensor(pr.d).cuda()
+    p_t = torch.as_tensor(pr.p_idx).cuda()
     pts = torch.as_tensor(pr.p_idx[pr.seg_off[:-1]]).cuda()
     seg = torch.as_tensor(pr.seg_off).cuda()
-    fc.fc_scan_points(grid, 2, pts, seg, d_t, out["dchi2"], out["chi2_min"], out["argmin"],
-                      out["chi2_p"])
-    torch.cuda.synchronize()
-    return {k: v.cpu().numpy() for k, v in out.items()}
+    n_seg = len(pr.seg_off) - 1
+    outs = {}
+    for name in list(FORM) + ["fp32_universes"]:
+        form = FORM[name.replace("_universes", "")]
+        o = {k: torch.empty(K, dtype=torch.float64, device="cuda")
+             for k in ("dchi2", "chi2_min", "chi2_p")}
+        o["argmin"] = torch.empty(K, dtype=torch.int64, device="cuda")
+        if name.endswith("_universes"):
+            fc.fc_scan(grid, form, d_t, p_t, o["dchi2"], o["chi2_min"], o["argmin"],
+                       o["chi2_p"])
+        else:
+            fc.fc_scan_points(grid, form, pts, seg, d_t, o["dchi2"], o["chi2_min"], o["argmin"],
+                              o["chi2_p"])
+        crit = torch.empty((n_seg, len(ALPHA)), dtype=torch.float64, device="cuda")
+        fc.fc_critical_value(seg, o["dchi2"], ALPHA, crit)
+        torch.cuda.synchronize()
+        outs[name] = {k: v.cpu().numpy() for k, v in o.items()}
+        outs[name]["crit"] = crit.cpu().numpy()
+    grid.destroy()
+    return outs
 
 
-def sample_idx(pr, per_point):
-    idx = []
-    for s in range(len(pr.seg_off) - 1):
+@pytest.fixture(scope="module", params=["c2", "c3", "c5"])
+def config(fc, request):
+    name = request.param
+    pr = fcgen.make_problem(name)
+    ref = golden.load(name, pr)
+    print(f"\n[config] {name}: G={pr.G} K={pr.K}, {ref['idx'].shape[0]} sampled universes",
+          flush=True)
+    return name, pr, ref, scan_all(fc, pr)
+
+
+@pytest.mark.parametrize("form", list(FORM) + ["fp32_universes"])
+def test_full_config_parity(config, form):
+    name, pr, ref, outs = config
+    dev = outs[form]
+    tol = parity.TOL[form.replace("_universes", "")]
+    parity.check_invariants(dev, pr.G, all_finite=True)
+    idx = ref["idx"]
+    ds = {k: dev[k][idx] for k in ("dchi2", "chi2_min", "argmin", "chi2_p")}
+    rep = parity.report(ds, ref, tol)
+    rep.update(parity.argmin_validity(pr, ds, pr.d[idx], ref, tol))
+    print(name, form, rep)
+    assert rep["e_rel"] <= tol, rep
+    assert rep["argmin_agree"] >= (1.0 if form in ("fp64", "fp32", "fp32_universes") else 0.99)
+    assert rep["argmin_valid"] == 1.0, rep
+    # full-K critical values of the points whose universes are all sampled
+    # (P10: an order statistic moves by at most the largest value error)
+    for j, s in enumerate(ref["full_points"]):
         lo, hi = int(pr.seg_off[s]), int(pr.seg_off[s + 1])
-        idx += list(range(lo, lo + per_point)) + [hi - 1]
-    return np.array(idx)
+        bound = tol * max(1.0, float(dev["chi2_p"][lo:hi].max()))
+        err = np.abs(dev["crit"][s] - ref["crit"][j])
+        assert np.all(err <= bound), (name, form, int(s), err, bound)
 
 
-@pytest.fixture(scope="module")
-def c3(fc):
-    pr = fcgen.make_problem("c3")
-    grid = fc.fc_build_grid(pr.axes, pr.S)
-    fc.fc_build_covariance(grid, pr.F, forms=2 | 4 | 8)
-    d_t = torch.as_tensor(pr.d).cuda()
-    p_t = torch.as_tensor(pr.p_idx).cuda()
-    outs = {f: scan(fc, grid, FORM[f], d_t, p_t) for f in FORM}
-    outs["fp32_points"] = scan_points(fc, grid, pr, d_t)
-    idx = sample_idx(pr, 1)
-    ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx])
-    yield pr, outs, idx, ref
-    grid.destroy()
-
-
-@pytest.mark.parametrize("form", list(FORM) + ["fp32_points"])
-def test_c3_sampled_parity(c3, form):
-    pr, outs, idx, ref = c3
-    dev = outs[form]
-    tol = parity.TOL[form.replace("_points", "")]
-    parity.check_invariants(dev, pr.G)
-    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, tol)
-    print(form, rep)
-    assert rep["e_rel"] <= tol
-    assert rep["argmin_agree"] >= 0.98
-
-
-def test_c3_forms_agree_on_every_universe(c3):
-    """All 256 000 universes: the split forms and the FP32 offset form against the
-    FP32 residual form on the same inputs."""
-    pr, outs, _, _ = c3
-    base = outs["fp32"]
+def test_forms_agree_on_every_universe(config):
+    """All universes: every form against the FP64 form on the same inputs."""
+    name, pr, ref, outs = config
+    base = outs["fp64"]
     scale = np.maximum(1.0, base["chi2_p"])
-    for form in ("split_bf16", "split_fp16"):
-        e = np.abs(outs[form]["dchi2"] - base["dchi2"]) / scale
-        assert e.max() <= parity.TOL[form] + parity.TOL["fp32"], (form, e.max())
-    # the FP32 offset form (fc_scan_points) against the residual form
-    e = np.abs(outs["fp32_points"]["dchi2"] - base["dchi2"]) / scale
-    assert e.max() <= 2 * parity.TOL["fp32"], e.max()
-    # per-point 90 % critical values agree within the same Lipschitz bound
-    for form in ("split_bf16", "split_fp16"):
-        c_a, _ = oracle.critical_value(base["dchi2"], pr.seg_off, [0.9], with_hist=False)
-        c_b, _ = oracle.critical_value(outs[form]["dchi2"], pr.seg_off, [0.9], with_hist=False)
-        bound = (parity.TOL[form] + parity.TOL["fp32"]) * scale.max()
-        assert np.max(np.abs(c_a - c_b)) <= bound
-
-
-@pytest.fixture(scope="module")
-def c5(fc):
-    pr = fcgen.make_problem("c5")
-    grid = fc.fc_build_grid(pr.axes, pr.S)
-    fc.fc_build_covariance(grid, pr.F, forms=2 | 8)
-    d_t = torch.as_tensor(pr.d).cuda()
-    p_t = torch.as_tensor(pr.p_idx).cuda()
-    outs = {f: scan(fc, grid, FORM[f], d_t, p_t) for f in ("fp32", "split_fp16")}
-    outs["fp32_points"] = scan_points(fc, grid, pr, d_t)
-    idx = sample_idx(pr, 1)
-    ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx])
-    yield pr, outs, idx, ref
-    grid.destroy()
-
-
-@pytest.mark.parametrize("form", ["fp32", "split_fp16", "fp32_points"])
-def test_c5_sampled_parity(c5, form):
-    pr, outs, idx, ref = c5
-    assert pr.G == 16 ** 5
-    dev = outs[form]
-    tol = parity.TOL[form.replace("_points", "")]
-    parity.check_invariants(dev, pr.G)
-    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, tol)
-    print(form, rep)
-    assert rep["e_rel"] <= tol
-    assert rep["argmin_agree"] >= 0.95
+    for form, dev in outs.items():
+        tol = parity.TOL[form.replace("_universes", "")]
+        e = np.abs(dev["dchi2"] - base["dchi2"]) / scale
+        assert e.max() <= tol + parity.TOL["fp64"], (name, form, e.max())

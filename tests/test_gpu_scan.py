@@ -381,3 +381,81 @@ def test_full_size_c2_sampled_parity(fc):
     print(rep)
     assert rep["e_rel"] <= 1e-6
     assert rep["argmin_agree"] >= 0.99
+
+
+# ---------------------------------------------------------------------------
+# optional outputs (NULL pointers through the C ABI)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["fp64", "fp32", "split_bf16", "split_fp16"])
+def test_optional_outputs_are_optional(fc, form):
+    """chi2_min, argmin and chi2_p may be NULL: the library then keeps its keys
+    and chi2_p in scratch, and every output that is given is bit for bit the
+    full call's (fc_scan, and fc_scan_points for the same universes)."""
+    pr = fcgen.make_problem("c1", K=333)
+    g = make_grid(fc, pr, ALL_FORMS)
+    full = run_scan(fc, g, FORM[form], pr.d, pr.p_idx)
+    d_t = to_dev(pr.d, torch.float64)
+    p_t = to_dev(pr.p_idx, torch.int64)
+    pts = to_dev(pr.p_idx[pr.seg_off[:-1]], torch.int64)
+    so = to_dev(pr.seg_off, torch.int64)
+    pts_full = {k: torch.empty(pr.K, dtype=torch.float64, device="cuda")
+                for k in ("dchi2", "chi2_min", "chi2_p")}
+    pts_full["argmin"] = torch.empty(pr.K, dtype=torch.int64, device="cuda")
+    fc.fc_scan_points(g, FORM[form], pts, so, d_t, pts_full["dchi2"], pts_full["chi2_min"],
+                      pts_full["argmin"], pts_full["chi2_p"])
+    torch.cuda.synchronize()
+    pts_full = {k: v.cpu().numpy() for k, v in pts_full.items()}
+    for drop in (("chi2_min",), ("argmin",), ("chi2_p",), ("chi2_min", "argmin", "chi2_p")):
+        for entry, ref in (("scan", full), ("points", pts_full)):
+            out = {k: torch.full((pr.K,), -5.0, dtype=torch.float64, device="cuda")
+                   for k in ("dchi2", "chi2_min", "chi2_p")}
+            out["argmin"] = torch.full((pr.K,), -5, dtype=torch.int64, device="cuda")
+            args = {k: (None if k in drop else v) for k, v in out.items()}
+            if entry == "scan":
+                fc.fc_scan(g, FORM[form], d_t, p_t, args["dchi2"], args["chi2_min"],
+                           args["argmin"], args["chi2_p"])
+            else:
+                fc.fc_scan_points(g, FORM[form], pts, so, d_t, args["dchi2"], args["chi2_min"],
+                                  args["argmin"], args["chi2_p"])
+            torch.cuda.synchronize()
+            for k, v in out.items():
+                got = v.cpu().numpy()
+                if k in drop:
+                    assert np.all(got == -5), (entry, k, "a NULL output's stand-in was written")
+                else:
+                    np.testing.assert_array_equal(got, ref[k], err_msg=f"{entry} {drop} {k}")
+    # the outputs agree with the oracle (the full call is the reference above)
+    ref = oracle.scan(pr.S, pr.F, pr.d, pr.p_idx)
+    rep = parity.report(full, ref, parity.TOL[form])
+    assert rep["e_rel"] <= parity.TOL[form], rep
+
+
+def test_split_fp16_universes_far_outside_the_grid_range(fc):
+    """A finite universe whose |d - o| is far beyond the grid's own spread of
+    S - o would overflow FP16 at the grid-wide scale; it gets its own power of
+    two, so the split FP16 form stays finite and within its tolerance of the
+    oracle, and the ordinary universes around it are unchanged bit for bit."""
+    pr = fcgen.make_problem("c1", K=192)
+    g = make_grid(fc, pr, ALL_FORMS)
+    d = pr.d.copy()
+    base = run_scan(fc, g, FORM["split_fp16"], d, pr.p_idx)
+    far = [5, 70, 71, 130]
+    d[5] = pr.S[pr.p_idx[5]] * 40.0                       # 40x the counts
+    d[70] = pr.S[pr.p_idx[70]] + 3.0e5                    # far above every bin
+    d[71, ::2] = -2.0e5                                   # large negative bins
+    d[130] = pr.S[pr.p_idx[130]] * 1.0e4                  # five orders of magnitude
+    dev = run_scan(fc, g, FORM["split_fp16"], d, pr.p_idx)
+    parity.check_invariants(dev, pr.G, all_finite=True)
+    ref = oracle.scan(pr.S, pr.F, d, pr.p_idx)
+    rep = parity.report(dev, ref, parity.TOL["split_fp16"])
+    rep.update(parity.argmin_validity(pr, dev, d, ref, parity.TOL["split_fp16"]))
+    assert rep["e_rel"] <= parity.TOL["split_fp16"], rep
+    assert rep["argmin_valid"] == 1.0, rep
+    # the chi^2 values of the far universes themselves, relative to their size
+    for k in far:
+        assert abs(dev["chi2_p"][k] - ref["chi2_p"][k]) <= 1e-4 * ref["chi2_p"][k], k
+    # every other universe keeps exponent 0 (scaling by 2^0 is exact), so its
+    # results are bit for bit those without the far universes
+    keep = np.setdiff1d(np.arange(pr.K), far)
+    for k in ("dchi2", "chi2_min", "chi2_p", "argmin"):
+        np.testing.assert_array_equal(dev[k][keep], base[k][keep])

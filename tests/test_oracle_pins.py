@@ -230,10 +230,13 @@ def test_p6_constructed_minimiser():
 # --------------------------------------------------------------------------
 # P7: Wilks -- for a linear model with Gaussian data Delta chi^2 ~ chi^2_D
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("D,n_axis,K", [(1, 161, 20000), (2, 121, 5000)])
-def test_p7_wilks(D, n_axis, K):
+@pytest.mark.parametrize("D,n_axis,h,K", [(1, 161, 0.1, 20000), (2, 201, 0.1, 20000),
+                                           (3, 41, 0.25, 20000)])
+def test_p7_wilks(D, n_axis, h, K):
+    # D = 1, 2: spacing 0.1 sigma over +-8 / +-10 sigma; D = 3: spacing 0.25 sigma
+    # over +-5 sigma (a wider bias band, the same statistic)
     rng = np.random.default_rng(7 + D)
-    N, h = 6, 0.1
+    N = 6
     s0, A, X, S, _ = _linear_model(N, D, h, n_axis, rng)
     F = np.zeros((N, N))
     p = (S.shape[0] - 1) // 2                  # the grid centre, x_p = 0
