@@ -153,6 +153,7 @@ def test_generated_universes_scan_matches_oracle(fc):
     rep = parity.report(dev, ref, parity.TOL["fp32"])
     assert rep["e_rel"] <= parity.TOL["fp32"], rep
     assert rep["argmin_agree"] == 1.0, rep
+    assert parity.argmin_validity(pr, dev, d_o, ref, parity.TOL["fp32"])["argmin_valid"] == 1.0
 
 
 def test_large_universe_count_indexing(fc):

@@ -79,6 +79,7 @@ def test_points_fp32_matches_oracle(fc, name):
     rep = parity.report(dev, ref, parity.TOL["fp32"])
     assert rep["e_rel"] <= parity.TOL["fp32"], rep
     assert rep["argmin_agree"] == 1.0, rep
+    assert parity.argmin_validity(pr, dev, d, ref, parity.TOL["fp32"])["argmin_valid"] == 1.0
 
 
 @pytest.mark.parametrize("form_name", ["fp64", "split_bf16", "split_fp16"])
@@ -184,8 +185,11 @@ def test_points_full_size_c2_sampled(fc):
     rows = np.concatenate([pr.seg_off[:-1] + k for k in (0, 1, 999, 1999)])
     rows = np.concatenate([rows, np.arange(1990, 2070)])
     ref = oracle.scan(pr.S, pr.F, pr.d[rows], pr.p_idx[rows])
-    rep = parity.report({k: v[rows] for k, v in dev.items()}, ref, parity.TOL["fp32"])
+    ds = {k: v[rows] for k, v in dev.items()}
+    rep = parity.report(ds, ref, parity.TOL["fp32"])
     assert rep["e_rel"] <= parity.TOL["fp32"], rep
+    assert rep["argmin_agree"] == 1.0, rep
+    assert parity.argmin_validity(pr, ds, pr.d[rows], ref, parity.TOL["fp32"])["argmin_valid"] == 1.0
 
 
 def test_points_many_segments_and_long_ones(fc):
@@ -211,6 +215,7 @@ def test_points_many_segments_and_long_ones(fc):
     rep = parity.report(dev, ref, parity.TOL["fp32"])
     assert rep["e_rel"] <= parity.TOL["fp32"], rep
     assert rep["argmin_agree"] == 1.0, rep
+    assert parity.argmin_validity(pr, dev, d, ref, parity.TOL["fp32"])["argmin_valid"] == 1.0
 
 
 def test_points_empty_inputs(fc):

@@ -102,9 +102,11 @@ def test_scan_parity_c1(fc, form):
     dev = run_scan(fc, g, FORM[form], pr.d, pr.p_idx)
     parity.check_invariants(dev, pr.G)
     rep = parity.report(dev, ref, parity.TOL[form])
+    rep.update(parity.argmin_validity(pr, dev, pr.d, ref, parity.TOL[form]))
     print(form, rep)
     assert rep["e_rel"] <= parity.TOL[form]
     assert rep["argmin_agree"] >= (1.0 if form in ("fp64", "fp32") else 0.99)
+    assert rep["argmin_valid"] == 1.0, rep
 
 
 @pytest.fixture(scope="module")
@@ -121,9 +123,11 @@ def test_scan_parity_ragged_multi_tile(fc, c2_ragged, form):
     dev = run_scan(fc, g, FORM[form], pr.d, pr.p_idx)
     parity.check_invariants(dev, pr.G)
     rep = parity.report(dev, ref, parity.TOL[form])
+    rep.update(parity.argmin_validity(pr, dev, pr.d, ref, parity.TOL[form]))
     print(form, rep)
     assert rep["e_rel"] <= parity.TOL[form]
-    assert rep["argmin_agree"] >= 0.99
+    assert rep["argmin_agree"] >= (1.0 if form == "fp32" else 0.99)
+    assert rep["argmin_valid"] == 1.0, rep
 
 
 @pytest.mark.parametrize("N", [1, 3, 4, 5, 16, 17, 32, 33, 48, 49, 57, 64])
@@ -151,12 +155,15 @@ def test_scan_parity_bin_counts(fc, N):
         assert rep["argmin_agree"] == 1.0, (form, rep)
 
 
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
 @pytest.mark.parametrize("N", list(range(1, 65)))
-def test_fp32_every_bin_count(fc, N):
-    """The FP32 kernel is compiled once per bin count (the padding shift, the
-    skipped slices and the signal-chunk boundaries are constants of each
-    instantiation): every N against the oracle, with an odd grid (a grid point
-    left over after the pairs), two universe tiles and a ragged second one."""
+def test_every_bin_count(fc, N, form):
+    """The FP32 and FP64 kernels are compiled per bin count (FP32: the padding
+    shift, the skipped slices and the signal-chunk boundaries; FP64: the
+    number of 4-bin blocks): every N against the oracle, with an odd grid (a
+    grid point left over after the pairs), two universe tiles and a ragged
+    second one."""
+    import types
     rng = np.random.default_rng(1000 + N)
     G, K = 23, 300
     S = rng.uniform(20, 800, size=(G, N))
@@ -168,13 +175,16 @@ def test_fp32_every_bin_count(fc, N):
     d = S[p] + rng.normal(0, 1, size=(K, N)) * np.sqrt(S[p])
     ref = oracle.scan(S, F, d, p)
     g = fc.fc_build_grid([np.arange(float(G))], S)
-    fc.fc_build_covariance(g, F, forms=FORM["fp32"])
-    dev = run_scan(fc, g, FORM["fp32"], d, p)
+    fc.fc_build_covariance(g, F, forms=FORM[form])
+    dev = run_scan(fc, g, FORM[form], d, p)
     g.destroy()
-    parity.check_invariants(dev, G)
-    rep = parity.report(dev, ref, parity.TOL["fp32"])
-    assert rep["e_rel"] <= parity.TOL["fp32"], rep
+    parity.check_invariants(dev, G, all_finite=True)
+    rep = parity.report(dev, ref, parity.TOL[form])
+    pr = types.SimpleNamespace(S=S, F=F, stat_mode=0, stat_diag=None, G=G)
+    rep.update(parity.argmin_validity(pr, dev, d, ref, parity.TOL[form]))
+    assert rep["e_rel"] <= parity.TOL[form], rep
     assert rep["argmin_agree"] == 1.0, rep
+    assert rep["argmin_valid"] == 1.0, rep
 
 
 # ---------------------------------------------------------------------------
@@ -377,10 +387,13 @@ def test_full_size_c2_sampled_parity(fc):
     parity.check_invariants(dev, pr.G)
     idx = _sample_idx(pr, 1)
     ref = oracle.scan(pr.S, pr.F, pr.d[idx], pr.p_idx[idx])
-    rep = parity.report({k: v[idx] for k, v in dev.items()}, ref, 1e-6)
+    ds = {k: v[idx] for k, v in dev.items()}
+    rep = parity.report(ds, ref, 1e-6)
+    rep.update(parity.argmin_validity(pr, ds, pr.d[idx], ref, 1e-6))
     print(rep)
     assert rep["e_rel"] <= 1e-6
-    assert rep["argmin_agree"] >= 0.99
+    assert rep["argmin_agree"] == 1.0
+    assert rep["argmin_valid"] == 1.0, rep
 
 
 # ---------------------------------------------------------------------------

@@ -123,19 +123,41 @@ def test_mix_equals_alone(fc, grids, form_name, policy):
         assert res[i]["latency"] > 0.0
 
 
-def test_served_results_match_oracle(fc, grids):
-    server = fc.Server([g for _, g in grids], form=fc.FC_FORM_FP32, hbm_budget=256 << 20,
-                       host_budget=256 << 20, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI)
-    reqs = make_requests(grids, 3, 200, 400, seed=2)
-    ids = [server.submit(gi, p, d) for gi, p, d in reqs]
+@pytest.mark.parametrize("form_name", ["fp32", "split_fp16"])
+def test_served_results_match_oracle(fc, grids, form_name):
+    """24 requests of 300..3000 universes served in a mix, each checked against
+    the oracle on sampled universes (its first 16 and its last): Delta chi^2
+    within the form's tolerance, argmin agreement and validity; and the served
+    critical values and histogram equal the oracle's quantile of the served
+    Delta chi^2 values (all K of them)."""
+    form = {"fp32": fc.FC_FORM_FP32, "split_fp16": fc.FC_FORM_SPLIT_FP16}[form_name]
+    tol = parity.TOL[form_name]
+    server = fc.Server([g for _, g in grids], form=form, hbm_budget=256 << 20,
+                       host_budget=256 << 20, alpha=ALPHA, n_bins=N_BINS, hist_hi=HIST_HI,
+                       launch_evals=2e7)
+    reqs = make_requests(grids, 24, 300, 3000, seed=2)
+    ids = []
+    for k, (gi, p, d) in enumerate(reqs):
+        ids.append(server.submit(gi, p, d))
+        if k % 4 == 3:
+            time.sleep(0.002)
     res = wait_all(server, ids)
     server.destroy()
+    assert len(res) == 24
     for i, (gi, p, d) in zip(ids, reqs):
         pr = grids[gi][0]
-        ref = oracle.scan(pr.S, pr.F, d, np.full(d.shape[0], p))
-        rep = parity.report(res[i], ref, parity.TOL["fp32"])
-        assert rep["e_rel"] <= parity.TOL["fp32"], rep
-        c_ref, h_ref = oracle.critical_value(res[i]["dchi2"], [0, d.shape[0]], ALPHA,
+        K = d.shape[0]
+        rows = np.r_[0:16, K - 1]
+        ref = oracle.scan(pr.S, pr.F, d[rows], np.full(rows.shape[0], p))
+        dev = {k: res[i][k][rows] for k in ("dchi2", "chi2_min", "argmin", "chi2_p")}
+        rep = parity.report(dev, ref, tol)
+        rep.update(parity.argmin_validity(pr, dev, d[rows], ref, tol))
+        assert rep["e_rel"] <= tol, rep
+        assert rep["argmin_agree"] >= (1.0 if form_name == "fp32" else 0.99), rep
+        assert rep["argmin_valid"] == 1.0, rep
+        parity.check_invariants({k: res[i][k] for k in ("dchi2", "chi2_min", "argmin",
+                                                        "chi2_p")}, pr.G, all_finite=True)
+        c_ref, h_ref = oracle.critical_value(res[i]["dchi2"], [0, K], ALPHA,
                                              n_bins=N_BINS, hist_hi=HIST_HI)
         np.testing.assert_array_equal(res[i]["crit"], c_ref[0])
         np.testing.assert_array_equal(res[i]["hist"], h_ref[0])
@@ -223,6 +245,7 @@ def test_drawn_request_matches_oracle(fc, grids):
     rep = parity.report(r, ref, parity.TOL["fp32"])
     assert rep["e_rel"] <= parity.TOL["fp32"], rep
     assert rep["argmin_agree"] == 1.0, rep
+    assert parity.argmin_validity(pr, r, d_o, ref, parity.TOL["fp32"])["argmin_valid"] == 1.0
 
 
 def test_drawn_request_needs_a_factor(fc):

@@ -158,6 +158,7 @@ def test_sliced_scan_matches_oracle(fc):
     rep = parity.report(dev, ref, parity.TOL["fp32"])
     assert rep["e_rel"] <= parity.TOL["fp32"], rep
     assert rep["argmin_agree"] == 1.0, rep
+    assert parity.argmin_validity(pr, dev, d, ref, parity.TOL["fp32"])["argmin_valid"] == 1.0
 
 
 def test_state_init_and_untouched_universes(fc):
