@@ -161,6 +161,29 @@ int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d,
             double *chi2_p, hipStream_t stream);
 
 /*
+ * fc_scan_no_alloc -- fc_scan for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, checks and results as fc_scan (bit for bit),
+ * but the call allocates nothing: every scratch buffer the scan needs is
+ * carved from a static device array of FC_NO_ALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on (from the first call on that
+ * device until the process ends).  The FP32 and split forms need scratch
+ * only for NULL outputs (8 K bytes for the keys when chi2_min is NULL, 8 K
+ * when chi2_p is NULL); the FP64 form also keeps its chunk minima there,
+ * with fewer grid chunks when they would not fit (the results do not depend
+ * on the chunk count).  A call whose K needs more than the array holds
+ * returns FC_ERR_INVALID_ARG before any device work.  Every call on one
+ * device shares that device's array: calls that overlap in time on one
+ * device (several streams or threads) race and must be serialised by the
+ * caller; nothing is carried over between calls (what must start at zero is
+ * cleared by each call's own kernels).
+ */
+#define FC_NO_ALLOC_SCRATCH_BYTES (32u << 20)
+int fc_scan_no_alloc(const fc_grid *g, int32_t form, int64_t K, const double *d,
+                     const int64_t *p_idx, double *dchi2, double *chi2_min, int64_t *argmin,
+                     double *chi2_p, hipStream_t stream);
+
+/*
  * fc_critical_value -- per-true-point critical values and histogram of
  * Delta chi2 (asynchronous).  Section 1 / Figure 1: the critical value for a
  * fraction alpha is the value left of which that fraction of the

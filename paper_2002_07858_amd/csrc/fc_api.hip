@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "fc_internal.h"
@@ -395,9 +396,55 @@ int check_scan(const char *fn, const fc_grid *g, int32_t form, int64_t K, const 
     return FC_OK;
 }
 
+// Static scratch of fc_scan_no_alloc: one array per device (each device that
+// loads the library holds its own copy until the process ends).  In host code
+// `scratch` names a host-side stand-in, never the device memory: the device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is passed to kernels.
+__device__ __align__(256) unsigned char scratch[FC_NO_ALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+hipError_t static_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = a;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
+
+int fc_scan_no_alloc(const fc_grid *g, int32_t form, int64_t K, const double *d,
+                     const int64_t *p_idx, double *dchi2, double *chi2_min, int64_t *argmin,
+                     double *chi2_p, hipStream_t stream)
+{
+    g_last_error.clear();
+    const int rc = check_scan("fc_scan_no_alloc", g, form, K, d, p_idx, dchi2);
+    if (rc != FC_OK || K == 0) return rc;
+    void *base = nullptr;
+    const hipError_t e = static_scratch(&base);
+    if (e != hipSuccess) return hip_fail(e, "fc_scan_no_alloc: static scratch address");
+    Scratch sc;
+    sc.st = stream;
+    sc.base = static_cast<char *>(base);
+    sc.bytes = FC_NO_ALLOC_SCRATCH_BYTES;
+    return scan_checked("fc_scan_no_alloc", g, form, K, d, p_idx, dchi2, chi2_min, argmin, chi2_p,
+                        stream, sc);
+}
 
 int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d, const int64_t *p_idx,
             double *dchi2, double *chi2_min, int64_t *argmin, double *chi2_p, hipStream_t stream)

@@ -32,6 +32,7 @@ FC_STAT_PEARSON = 0
 FC_STAT_FIXED = 1
 
 FC_MAX_BINS = 64
+FC_NO_ALLOC_SCRATCH_BYTES = 32 << 20
 
 FC_SCHED_FAIR = 0
 FC_SCHED_FIFO = 1
@@ -50,7 +51,8 @@ EXPORTED = ("fc_build_grid", "fc_build_covariance", "fc_scan", "fc_scan_points",
             "fc_grid_inverse_cov", "fc_grid_info",
             "fc_grid_device_bytes", "fc_grid_destroy", "fc_last_error", "fc_server_create", "fc_server_submit",
             "fc_server_submit_drawn", "fc_server_poll",
-            "fc_server_stats", "fc_server_destroy", "fc_profile_enable", "fc_profile_read")
+            "fc_server_stats", "fc_server_destroy", "fc_profile_enable", "fc_profile_read",
+            "fc_scan_no_alloc")
 
 
 class FCError(RuntimeError):
@@ -77,6 +79,8 @@ def lib():
         L.fc_build_grid.argtypes = [ctypes.POINTER(_p), _i32, _p, _p, _i32, _p, _p, _p]
         L.fc_build_covariance.argtypes = [_p, _p, _i32, _p, _u32, _p, _p]
         L.fc_scan.argtypes = [_p, _i32, _i64, _p, _p, _p, _p, _p, _p, _p]
+        L.fc_scan_no_alloc.argtypes = [_p, _i32, _i64, _p, _p, _p, _p, _p, _p, _p]
+        L.fc_scan_no_alloc.restype = ctypes.c_int
         L.fc_scan_points.argtypes = [_p, _i32, _i64, _p, _p, _i64, _p, _p, ctypes.c_size_t, _p,
                                      _p, _p, _p, _p]
         L.fc_scan_points_workspace.argtypes = [_p, _i32, _i64, _i64, _p]
@@ -274,6 +278,21 @@ def fc_scan(grid: Grid, form: int, d, p_idx, dchi2, chi2_min=None, argmin=None, 
                          _dev(dchi2, "f64", "dchi2"), _dev(chi2_min, "f64", "chi2_min"),
                          _dev(argmin, "i64", "argmin"), _dev(chi2_p, "f64", "chi2_p"),
                          _stream(stream)))
+
+
+def fc_scan_no_alloc(grid: Grid, form: int, d, p_idx, dchi2, chi2_min=None, argmin=None,
+                     chi2_p=None, stream=None):
+    """fc_scan without any device allocation in the call: its scratch lives in
+    the library's static per-device array (calls on one device must not
+    overlap in time)."""
+    K = _rows(d, grid.N)
+    for t, n in ((p_idx, "p_idx"), (dchi2, "dchi2"), (chi2_min, "chi2_min"), (argmin, "argmin"),
+                 (chi2_p, "chi2_p")):
+        _need(t, K, n)
+    _check(lib().fc_scan_no_alloc(grid._h, int(form), K, _dev(d, "f64", "d"),
+                                  _dev(p_idx, "i64", "p_idx"), _dev(dchi2, "f64", "dchi2"),
+                                  _dev(chi2_min, "f64", "chi2_min"), _dev(argmin, "i64", "argmin"),
+                                  _dev(chi2_p, "f64", "chi2_p"), _stream(stream)))
 
 
 def fc_scan_points_workspace(grid: Grid, form: int, n_pts: int, K: int) -> int:
