@@ -71,7 +71,7 @@ size_t grid_bytes(const fc_grid *g)
     size_t b = 0;
     b += sizeof(double) * (size_t)g->G * g->N;  // S64
     if (g->W64) b += sizeof(double) * (size_t)g->G * ((size_t)g->N * (g->N + 1) / 2);
-    if (g->R64) b += sizeof(uint4) * (size_t)g->G * fcx::f64_rec_units(fcx::f64_nb(g->N));
+    if (g->R64) b += sizeof(uint4) * (size_t)g->G * fcx::f64_rec_units(g->N);
     b += sizeof(double) * 128;                  // off, dev
     if (g->R32) b += sizeof(uint4) * (size_t)g->G * fcx::rec_units(g->ns);
     if (g->RB16) b += (size_t)g->G * split_record_bytes(g);
@@ -212,7 +212,7 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
          (e = hipMalloc(&W64, sizeof(double) * (size_t)g->G * nt)) != hipSuccess) ||
         ((forms & FC_FORM_FP64) &&
          (e = hipMalloc(&R64, sizeof(uint4) * (size_t)g->G *
-                                  fcx::f64_rec_units(fcx::f64_nb(N)))) != hipSuccess) ||
+                                  fcx::f64_rec_units(N))) != hipSuccess) ||
         ((forms & FC_FORM_FP32) &&
          (e = hipMalloc(&R32, sizeof(uint4) * (size_t)g->G * fcx::rec_units(g->ns))) !=
              hipSuccess) ||

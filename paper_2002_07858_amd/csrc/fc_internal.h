@@ -129,41 +129,59 @@ __host__ __device__ constexpr int split_rec_units(int nk, int nb)
 // the A operand of every block).  Bins and rows are padded to NP = 4 nb with
 // nb = ceil(N / 4) blocks of four, real bins / rows at padded positions
 // P .. NP-1 (P = NP - N): W'[r'][k'] = W_q[r' - P][k' - P] for P <= k' <= r',
-// else 0.  Tiles (kb, r) with kb <= r (rows 4r .. 4r+3, bins 4kb .. 4kb+3)
-// run kb outer, r inner: nb (nb + 1) / 2 tiles.  Tile t's element
-// A[i][k] = W'[4r + i][4kb + k] is stored at position 4k + i of the tile;
-// tiles are stored in pairs, [pair][position][tile 2 pair + {0, 1}] doubles
-// (an odd last pair padded with zeros), so that one 16-byte LDS read at
-// pair * 256 + (4 (lane / 16) + lane % 4) * 16 gives a lane the A operands of
-// two consecutive tiles.  The signal follows in the order the residual needs
-// it: Sp[g][kb] = S_q[4kb + g - P] (0 for padding), g = 0..3, kb < nbe =
-// nb rounded up to even, so that a lane reads its nb values (g = lane / 16)
-// with 16-byte loads.  N = 57: nb = 15, 120 tiles, 15.5 KB per grid point.
+// else 0.  The first bin block holds only L = 4 - P real bins; when L <= 2
+// (N = 57: one) its products are cheaper on the vector ALUs than as nb tiles
+// that are mostly zero, so the record carries those L columns apart ("lead"
+// columns) and the tiles start at bin block k0 = 1; otherwise k0 = 0.  Tiles
+// (kb, r) with k0 <= kb <= r (rows 4r .. 4r+3, bins 4kb .. 4kb+3) run kb outer,
+// r inner.  Tile t's element A[i][k] = W'[4r + i][4kb + k] is stored at
+// position 4k + i of the tile; tiles are stored in pairs,
+// [pair][position][tile 2 pair + {0, 1}] doubles (an odd last pair padded
+// with zeros), so that one 16-byte LDS read at pair * 256 +
+// (4 (lane / 16) + lane % 4) * 16 gives a lane the A operands of two
+// consecutive tiles.  Then, in the order a lane reads them (g = lane / 16,
+// nbe = nb rounded up to even, 16-byte loads):
+//     signal  Sp[g][r]    = S_q[4r + g - P]           (0 for padding)
+//     lead    Wl[c][g][r] = W'[4r + g][P + c]  c < L  (lead columns only)
+// N = 57: nb = 15, 105 tiles + 1 lead column, 14.3 KB per grid point.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int f64_nb(int N) { return (N + 3) / 4; }
-__host__ __device__ constexpr int f64_nbe(int nb) { return (nb + 1) & ~1; }
-__host__ __device__ constexpr int f64_ntile(int nb) { return nb * (nb + 1) / 2; }
-__host__ __device__ constexpr int f64_npair(int nb) { return (f64_ntile(nb) + 1) / 2; }
-__host__ __device__ constexpr int f64_sig_double(int nb) { return 32 * f64_npair(nb); }
-__host__ __device__ constexpr int f64_rec_doubles(int nb)
+__host__ __device__ constexpr int f64_pad(int N) { return 4 * f64_nb(N) - N; }
+__host__ __device__ constexpr int f64_lead(int N)
 {
-    return f64_sig_double(nb) + 4 * f64_nbe(nb);
+    return (4 - f64_pad(N) <= 2) ? 4 - f64_pad(N) : 0;
 }
-__host__ __device__ constexpr int f64_rec_units(int nb) { return f64_rec_doubles(nb) / 2; }
-__host__ __device__ constexpr int f64_tile_kb(int nb, int t)
+__host__ __device__ constexpr int f64_k0(int N) { return f64_lead(N) ? 1 : 0; }
+__host__ __device__ constexpr int f64_nbe(int N) { return (f64_nb(N) + 1) & ~1; }
+__host__ __device__ constexpr int f64_ntile(int N)
 {
-    int kb = 0;
-    while (t >= nb - kb) {
-        t -= nb - kb;
+    return (f64_nb(N) - f64_k0(N)) * (f64_nb(N) - f64_k0(N) + 1) / 2;
+}
+__host__ __device__ constexpr int f64_npair(int N) { return (f64_ntile(N) + 1) / 2; }
+__host__ __device__ constexpr int f64_sig_double(int N) { return 32 * f64_npair(N); }
+__host__ __device__ constexpr int f64_lead_double(int N)
+{
+    return f64_sig_double(N) + 4 * f64_nbe(N);
+}
+__host__ __device__ constexpr int f64_rec_doubles(int N)
+{
+    return f64_lead_double(N) + 4 * f64_nbe(N) * f64_lead(N);
+}
+__host__ __device__ constexpr int f64_rec_units(int N) { return f64_rec_doubles(N) / 2; }
+__host__ __device__ constexpr int f64_tile_kb(int N, int t)
+{
+    int kb = f64_k0(N);
+    while (t >= f64_nb(N) - kb) {
+        t -= f64_nb(N) - kb;
         ++kb;
     }
     return kb;
 }
-__host__ __device__ constexpr int f64_tile_r(int nb, int t)
+__host__ __device__ constexpr int f64_tile_r(int N, int t)
 {
-    int kb = 0;
-    while (t >= nb - kb) {
-        t -= nb - kb;
+    int kb = f64_k0(N);
+    while (t >= f64_nb(N) - kb) {
+        t -= f64_nb(N) - kb;
         ++kb;
     }
     return kb + t;

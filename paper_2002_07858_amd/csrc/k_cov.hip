@@ -208,23 +208,29 @@ __global__ __launch_bounds__(64) void k_cov_build(
         }
         if (forms & FC_FORM_FP64) {
             // tile records of the FP64 MFMA form: element e of the record is
-            // (pair, position, tile of the pair), then the signal in residual order
-            const int nb = f64_nb(N), nt = f64_ntile(nb), P = 4 * nb - N;
-            const int sig = f64_sig_double(nb), nbe = f64_nbe(nb);
-            double *rq = reinterpret_cast<double *>(R64 + q * (int64_t)f64_rec_units(nb));
+            // (pair, position, tile of the pair), then the signal and the lead
+            // columns in the order the scan's lanes read them
+            const int nb = f64_nb(N), nt = f64_ntile(N), P = f64_pad(N), nbe = f64_nbe(N);
+            const int sig = f64_sig_double(N), lead = f64_lead_double(N), nl = f64_lead(N);
+            double *rq = reinterpret_cast<double *>(R64 + q * (int64_t)f64_rec_units(N));
             for (int e = i; e < sig; e += 64) {
                 const int t = 2 * (e >> 5) + (e & 1), pos = (e >> 1) & 15;
                 double val = 0.0;
                 if (t < nt) {
-                    const int rr = 4 * f64_tile_r(nb, t) + (pos & 3) - P;
-                    const int cc = 4 * f64_tile_kb(nb, t) + (pos >> 2) - P;
+                    const int rr = 4 * f64_tile_r(N, t) + (pos & 3) - P;
+                    const int cc = 4 * f64_tile_kb(N, t) + (pos >> 2) - P;
                     if (rr >= 0 && rr < N && cc >= 0 && cc <= rr) val = wget(A, ld, rr, cc);
                 }
                 rq[e] = val;
             }
             for (int e = i; e < 4 * nbe; e += 64) {
-                const int g = e / nbe, kb = e % nbe, k = 4 * kb + g - P;
+                const int g = e / nbe, r = e % nbe, k = 4 * r + g - P;
                 rq[sig + e] = (k >= 0 && k < N) ? Sq[k] : 0.0;
+            }
+            for (int e = i; e < 4 * nbe * nl; e += 64) {
+                const int c = e / (4 * nbe), g = (e / nbe) % 4, r = e % nbe;
+                const int rr = 4 * r + g - P;
+                rq[lead + e] = (r < nb && rr >= c && rr < N) ? wget(A, ld, rr, c) : 0.0;
             }
         }
         if (forms & FC_FORM_FP32) {

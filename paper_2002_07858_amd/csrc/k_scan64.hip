@@ -37,20 +37,23 @@ constexpr int kF64Waves = 4;                       // waves per block
 constexpr int kF64Sets = 2;                        // sets of 16 universes per wave
 constexpr int kF64Univ = 16 * kF64Sets * kF64Waves;  // universes per block (128)
 
-template <int NB>
+template <int N>
 struct F64Acc {
+    static constexpr int NB = f64_nb(N), NBE = f64_nbe(N), L = f64_lead(N);
     double d[kF64Sets][NB];    // universes: bin 4 kb + lane/16 - P of universe lane%16
-    double sig[f64_nbe(NB)];   // S_q at the same bins (one grid point)
+    double dl[kF64Sets][L > 0 ? L : 1];  // the lead bins 0 .. L-1 of universe lane%16
+    double sig[NBE];           // S_q at the lane's bins (one grid point)
     double r[kF64Sets][NB];    // residuals of the current bin block
     double acc[kF64Sets][NB];  // y rows 4 r + lane/16 of universe lane%16
 };
 
-// MFMA of tile t for both sets; the first tile of a bin block forms its
-// residuals, the first bin block starts the accumulators from zero.
-template <int NB, int t>
-__device__ __forceinline__ void f64_tile(F64Acc<NB> &s, double a)
+// MFMA of tile t for both sets.  The first tile of a bin block forms its
+// residuals; the first bin block starts the accumulators from zero, or from
+// the lead columns' products when those are on the vector ALUs.
+template <int N, int t>
+__device__ __forceinline__ void f64_tile(F64Acc<N> &s, double a)
 {
-    constexpr int kb = f64_tile_kb(NB, t), r = f64_tile_r(NB, t);
+    constexpr int kb = f64_tile_kb(N, t), r = f64_tile_r(N, t);
     if constexpr (r == kb) {
 #pragma unroll
         for (int c = 0; c < kF64Sets; ++c) s.r[c][kb] = s.d[c][kb] - s.sig[kb];
@@ -64,16 +67,16 @@ __device__ __forceinline__ void f64_tile(F64Acc<NB> &s, double a)
     }
 }
 
-template <int NB, int... p>
-__device__ __forceinline__ void f64_tiles(F64Acc<NB> &s, const double2 *__restrict__ rec, int pos,
+template <int N, int... p>
+__device__ __forceinline__ void f64_tiles(F64Acc<N> &s, const double2 *__restrict__ rec, int pos,
                                           std::integer_sequence<int, p...>)
 {
-    constexpr int nt = f64_ntile(NB);
+    constexpr int nt = f64_ntile(N);
     (
         [&] {
             const double2 a = rec[p * 16 + pos];
-            f64_tile<NB, 2 * p>(s, a.x);
-            if constexpr (2 * p + 1 < nt) f64_tile<NB, 2 * p + 1>(s, a.y);
+            f64_tile<N, 2 * p>(s, a.x);
+            if constexpr (2 * p + 1 < nt) f64_tile<N, 2 * p + 1>(s, a.y);
         }(),
         ...);
 }
@@ -97,17 +100,16 @@ __device__ __forceinline__ double f64_row_sum(double a, double b)
     return c2 + d2;
 }
 
-template <int NB>
+template <int N>
 __global__ __launch_bounds__(64 * kF64Waves) __attribute__((amdgpu_waves_per_eu(3))) void
 k_scan_f64m(const uint4 *__restrict__ R64, const double *__restrict__ d,
-            const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t q0, int64_t nq,
+            const int64_t *__restrict__ p_idx, int64_t K, int64_t q0, int64_t nq,
             int64_t n_utiles, int64_t q_per_chunk, Fp64Part *__restrict__ part,
             double *__restrict__ dchi2, double *__restrict__ chi2_min,
             int64_t *__restrict__ argmin, double *__restrict__ chi2_p)
 {
-    constexpr int NP = 4 * NB;
-    constexpr int REC = f64_rec_units(NB);  // 16-byte units per record
-    constexpr int NBE = f64_nbe(NB);
+    constexpr int NB = f64_nb(N), P = f64_pad(N), NBE = f64_nbe(N), L = f64_lead(N);
+    constexpr int REC = f64_rec_units(N);  // 16-byte units per record
     __shared__ uint4 lds[2][REC];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -115,24 +117,26 @@ k_scan_f64m(const uint4 *__restrict__ R64, const double *__restrict__ d,
     const int64_t qb = q0 + chunk * q_per_chunk;
     const int64_t qe = (qb + q_per_chunk < q0 + nq) ? qb + q_per_chunk : q0 + nq;
     const int64_t ubase = utile * kF64Univ + (int64_t)wave * 16 * kF64Sets;
-    const int P = NP - N;
 
     if (qb < qe) record_to_lds<REC, 64 * kF64Waves>(R64 + qb * (int64_t)REC, lds[0], tid);
 
-    // stage d for both sets: bin 4 kb + lane/16 - P of universe lane%16 (loads
-    // from clamped, in-bounds addresses; padding bins and idle lanes select 0)
-    F64Acc<NB> s;
+    // stage d for both sets: bin 4 kb + lane/16 - P of universe lane%16, and
+    // the lead bins of the same universe (loads from clamped, in-bounds
+    // addresses; padding bins and idle lanes select 0)
+    F64Acc<N> s;
 #pragma unroll
     for (int c = 0; c < kF64Sets; ++c) {
         const int64_t u = ubase + 16 * c + (lane & 15);
         const bool act = u < K;
         const double *du = d + (act ? u : K - 1) * N;
 #pragma unroll
-        for (int kb = 0; kb < NB; ++kb) {
+        for (int kb = f64_k0(N); kb < NB; ++kb) {
             const int j = 4 * kb + (lane >> 4) - P;
             const double v = du[j < 0 ? 0 : j];
             s.d[c][kb] = (act && j >= 0) ? v : 0.0;
         }
+#pragma unroll
+        for (int b = 0; b < L; ++b) s.dl[c][b] = act ? du[b] : 0.0;
     }
     // the universe this lane tracks after the row butterfly
     const int64_t u_own = ubase + 16 * (lane >> 5) + (lane & 15);
@@ -149,10 +153,11 @@ k_scan_f64m(const uint4 *__restrict__ R64, const double *__restrict__ d,
         __syncthreads();  // record q is in lds[buf]; every wave is done with lds[buf ^ 1]
         if (q + 1 < qe)
             record_to_lds<REC, 64 * kF64Waves>(R64 + (q + 1) * (int64_t)REC, lds[buf ^ 1], tid);
+        const double *rec = reinterpret_cast<const double *>(lds[buf]);
         {
-            // this lane's signal bins (g = lane / 16), then every tile
-            const double2 *sg = reinterpret_cast<const double2 *>(lds[buf]) +
-                                (f64_sig_double(NB) + (lane >> 4) * NBE) / 2;
+            // this lane's signal bins (g = lane / 16)
+            const double2 *sg =
+                reinterpret_cast<const double2 *>(rec + f64_sig_double(N) + (lane >> 4) * NBE);
 #pragma unroll
             for (int k = 0; k < NBE / 2; ++k) {
                 const double2 v = sg[k];
@@ -160,8 +165,38 @@ k_scan_f64m(const uint4 *__restrict__ R64, const double *__restrict__ d,
                 s.sig[2 * k + 1] = v.y;
             }
         }
-        f64_tiles<NB>(s, reinterpret_cast<const double2 *>(lds[buf]), pos,
-                      std::make_integer_sequence<int, f64_npair(NB)>{});
+        if constexpr (L > 0) {
+            // lead columns on the vector ALUs: every accumulator starts at
+            // sum_b W'[row][P + b] (d_b - S_q[b]) for the lane's own universe
+            double rl[kF64Sets][L];
+#pragma unroll
+            for (int b = 0; b < L; ++b) {
+                const double sb = rec[f64_sig_double(N) + (P + b) * NBE];  // S_q[b]: kb 0, g = P + b
+#pragma unroll
+                for (int c = 0; c < kF64Sets; ++c) rl[c][b] = s.dl[c][b] - sb;
+            }
+#pragma unroll
+            for (int b = 0; b < L; ++b) {
+                const double2 *wl = reinterpret_cast<const double2 *>(
+                    rec + f64_lead_double(N) + (b * 4 + (lane >> 4)) * NBE);
+#pragma unroll
+                for (int k = 0; k < NBE / 2; ++k) {
+                    const double2 w = wl[k];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int r = 2 * k + h;
+                        if (r < NB) {
+                            const double wv = h ? w.y : w.x;
+#pragma unroll
+                            for (int c = 0; c < kF64Sets; ++c)
+                                s.acc[c][r] = b ? fma(wv, rl[c][b], s.acc[c][r]) : wv * rl[c][b];
+                        }
+                    }
+                }
+            }
+        }
+        f64_tiles<N>(s, reinterpret_cast<const double2 *>(rec), pos,
+                     std::make_integer_sequence<int, f64_npair(N)>{});
         double sq[kF64Sets];
 #pragma unroll
         for (int c = 0; c < kF64Sets; ++c) {
@@ -247,13 +282,13 @@ __global__ __launch_bounds__(256) void k_fill_nan(int64_t K, double *__restrict_
 
 namespace {
 
-template <int NB>
-hipError_t launch_f64m_nb(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
+template <int N>
+hipError_t launch_f64m_n(const fc_grid *g, int64_t K, const double *d, const int64_t *p_idx,
                           Fp64Part *scratch, size_t scratch_bytes, double *dchi2,
                           double *chi2_min, int64_t *argmin, double *chi2_p, hipStream_t st)
 {
     static const int slots =
-        resident_slots(reinterpret_cast<const void *>(&k_scan_f64m<NB>), 64 * kF64Waves);
+        resident_slots(reinterpret_cast<const void *>(&k_scan_f64m<N>), 64 * kF64Waves);
     const int64_t G = g->G;
     // chunks: the fewest that fill the resident slots with a small tail
     ScanGeometry sg = scan_geometry(K, G, slots, kF64Univ);
@@ -287,9 +322,9 @@ hipError_t launch_f64m_nb(const fc_grid *g, int64_t K, const double *d, const in
                            chi2_p);
     {
         ProfScope prof(st, "k_scan_f64m");
-        hipLaunchKernelGGL(k_scan_f64m<NB>, dim3((unsigned)blocks), dim3(64 * kF64Waves), 0, st,
-                           g->R64, d, p_idx, K, g->N, (int64_t)0, G, sg.n_utiles, qpc, part,
-                           dchi2, chi2_min, argmin, chi2_p);
+        hipLaunchKernelGGL(k_scan_f64m<N>, dim3((unsigned)blocks), dim3(64 * kF64Waves), 0, st,
+                           g->R64, d, p_idx, K, (int64_t)0, G, sg.n_utiles, qpc, part, dchi2,
+                           chi2_min, argmin, chi2_p);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && part) {
@@ -311,14 +346,16 @@ hipError_t launch_scan_fp64(const fc_grid *g, int64_t K, const double *d, const 
                             hipStream_t st, Fp64Part *scratch, size_t scratch_bytes)
 {
     if (K <= 0) return hipSuccess;
-    switch (f64_nb(g->N)) {
-#define FC_CASE(nb)                                                                               \
-    case nb:                                                                                      \
-        return launch_f64m_nb<nb>(g, K, d, p_idx, scratch, scratch_bytes, dchi2, chi2_min, argmin, \
-                                  chi2_p, st);
-        FC_CASE(1) FC_CASE(2) FC_CASE(3) FC_CASE(4) FC_CASE(5) FC_CASE(6) FC_CASE(7) FC_CASE(8)
-        FC_CASE(9) FC_CASE(10) FC_CASE(11) FC_CASE(12) FC_CASE(13) FC_CASE(14) FC_CASE(15)
-        FC_CASE(16)
+    switch (g->N) {
+#define FC_CASE(n)                                                                                \
+    case n:                                                                                       \
+        return launch_f64m_n<n>(g, K, d, p_idx, scratch, scratch_bytes, dchi2, chi2_min, argmin,  \
+                                chi2_p, st);
+#define FC_CASE8(b) FC_CASE(b + 1) FC_CASE(b + 2) FC_CASE(b + 3) FC_CASE(b + 4) \
+                    FC_CASE(b + 5) FC_CASE(b + 6) FC_CASE(b + 7) FC_CASE(b + 8)
+        FC_CASE8(0) FC_CASE8(8) FC_CASE8(16) FC_CASE8(24) FC_CASE8(32) FC_CASE8(40) FC_CASE8(48)
+        FC_CASE8(56)
+#undef FC_CASE8
 #undef FC_CASE
     default: return hipErrorInvalidValue;
     }
