@@ -93,19 +93,23 @@ WORKLOADS = {
 FP32_SOURCES = ("paper_2002_07858_amd/csrc/k_scan.hip", "paper_2002_07858_amd/csrc/fc_internal.h")
 SPLIT_SOURCES = ("paper_2002_07858_amd/csrc/k_scan_split.hip",
                  "paper_2002_07858_amd/csrc/fc_internal.h")
+FP64_SOURCES = ("paper_2002_07858_amd/csrc/k_scan64.hip",
+                "paper_2002_07858_amd/csrc/fc_internal.h")
+# FETCH_SIZE (KiB x 1024 x 2.0000) + WRITE_SIZE (KiB x 1024 x 1.0000) of one launch
 TRAFFIC = {
-    ("c2", "fp32", "points"): {"bytes_per_launch": 7840127441, "source_hash": "882a26365d74f708",
-                               "sources": FP32_SOURCES,
-                               "profile": "profiles/k_scan_fp32_pts_c2_counters.md"},
-    ("c2", "fp32", "universes"): {"bytes_per_launch": 13630857981, "source_hash": "882a26365d74f708",
-                                  "sources": FP32_SOURCES,
-                                  "profile": "profiles/k_scan_fp32_pts_c2_counters.md"},
-    ("c2", "split_fp16", "universes"): {"bytes_per_launch": 10702034065,
-                                        "source_hash": "6352771ae54f8989", "sources": SPLIT_SOURCES,
-                                        "profile": "profiles/k_scan_split_fp16_c2.md"},
+    ("c5", "fp64", "points"): {"bytes_per_launch": 3902496378 * 2048 + 56250 * 1024,
+                               "source_hash": "df1add898ca146e3", "sources": FP64_SOURCES,
+                               "profile": "profiles/k_scan_f64m_c5.md"},
+    ("c5", "fp32", "points"): {"bytes_per_launch": 1901555571 * 2048 + 15000 * 1024,
+                               "source_hash": "2ba159aaaafa1750", "sources": FP32_SOURCES,
+                               "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
+    ("c5", "split_fp16", "points"): {"bytes_per_launch": 2430768542 * 2048 + 56250 * 1024,
+                                     "source_hash": "11c02535c8c34f6d", "sources": SPLIT_SOURCES,
+                                     "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
+    ("c5", "split_bf16", "points"): {"bytes_per_launch": 399826305 * 2048 + 15000 * 1024,
+                                     "source_hash": "11c02535c8c34f6d", "sources": SPLIT_SOURCES,
+                                     "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
 }
-# the split forms scan through the same kernel under either entry
-TRAFFIC[("c2", "split_fp16", "points")] = TRAFFIC[("c2", "split_fp16", "universes")]
 
 
 def kernel_source_hash(sources) -> str:
@@ -553,8 +557,14 @@ def forms_leg(fc, grid, pr, forms, pts_t, so_t, d_t, ref64, sample, steps=2):
         t = float(np.mean(ms)) * 1e-3
         dev = {k: v.cpu().numpy() for k, v in o.items()}
         e_all = np.abs(dev["dchi2"] - ref64["dchi2"]) / scale
+        rl = roofline_of(name, "points", N, float(K) * G, ks if ks else t)
+        tr = TRAFFIC.get((pr.name, name, "points"))
+        if tr is not None and tr["source_hash"] == kernel_source_hash(tr["sources"]):
+            rl["traffic"] = tr["bytes_per_launch"]
+            rl["traffic_GBps"] = tr["bytes_per_launch"] / (rl["kernel_ms"] * 1e-3) / 1e9
+            rl["traffic_source"] = tr["profile"]
         r = {"scan_ms": t * 1e3, "covariance_ms": cov_ms, "evals_per_s": K * G / t,
-             "roofline": roofline_of(name, "points", N, float(K) * G, ks if ks else t),
+             "roofline": rl,
              "vs_fp64_all_universes": {"n": K, "e_rel": float(e_all.max()),
                                        "e_abs": float(np.abs(dev["dchi2"] - ref64["dchi2"]).max()),
                                        "argmin_equal_frac": float((dev["argmin"] ==
