@@ -90,8 +90,10 @@ def test_region_subset_fp32_and_invariants(fc):
 
 def test_region_errors(fc):
     pr, g, dd = setup(fc, "c1", (6, 6), fc.FC_FORM_FP32, 3, 40002)
-    crit = torch.empty((pr.G, 2), dtype=torch.float64, device="cuda")
-    acc = torch.empty((pr.G, 2), dtype=torch.uint8, device="cuda")
+    # outputs large enough for every alpha list below, so that each call
+    # reaches the library's own argument checks
+    crit = torch.empty((pr.G, 5), dtype=torch.float64, device="cuda")
+    acc = torch.empty((pr.G, 5), dtype=torch.uint8, device="cuda")
     for kw in (dict(K0=0), dict(K0=64, K_max=32), dict(z=-1.0), dict(pts=[pr.G]),
                dict(alpha=(0.1, 0.2, 0.3, 0.4, 0.5))):
         args = dict(K0=16, K_max=64, z=2.0)
