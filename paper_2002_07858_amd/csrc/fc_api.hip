@@ -204,6 +204,16 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
         if (dbad) (void)hipFree(dbad);
     };
     const size_t nt = (size_t)N * (N + 1) / 2;
+    // gather maps of the record writers (depend on N only)
+    std::vector<int16_t> hmaps(fcx::cov_maps_size(N, g->ns));
+    fcx::cov_maps_fill(N, g->ns, hmaps.data());
+    int16_t *dmaps = nullptr;
+    if ((e = hipMalloc(&dmaps, sizeof(int16_t) * hmaps.size())) != hipSuccess)
+        return hip_fail(e, "fc_build_covariance: hipMalloc");
+    struct MapsGuard {
+        int16_t *p;
+        ~MapsGuard() { if (p) (void)hipFree(p); }
+    } maps_guard{dmaps};
     if ((e = hipMalloc(&dF, sizeof(double) * N * N)) != hipSuccess ||
         (e = hipMalloc(&dLF, sizeof(double) * N * N)) != hipSuccess ||
         (e = hipMalloc(&dstat, sizeof(double) * N)) != hipSuccess ||
@@ -230,15 +240,17 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
     }
     const unsigned long long none = ~0ull;
     unsigned long long hbad = none, hlf = 0;
-    if ((e = hipMemcpyAsync(dF, frac_cov, sizeof(double) * N * N, hipMemcpyHostToDevice,
+    if ((e = hipMemcpyAsync(dmaps, hmaps.data(), sizeof(int16_t) * hmaps.size(),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(dF, frac_cov, sizeof(double) * N * N, hipMemcpyHostToDevice,
                             stream)) != hipSuccess ||
         (stat_mode == FC_STAT_FIXED &&
          (e = hipMemcpyAsync(dstat, stat_diag, sizeof(double) * N, hipMemcpyHostToDevice,
                              stream)) != hipSuccess) ||
         (e = hipMemcpyAsync(dbad, &none, sizeof(none), hipMemcpyHostToDevice, stream)) !=
             hipSuccess ||
-        (e = fcx::launch_cov_build(g, dF, dstat, stat_mode, forms, W64, R64, R32, RB16, RH16,
-                                   dbad, stream)) !=
+        (e = fcx::launch_cov_build(g, dF, dstat, stat_mode, forms, dmaps, W64, R64, R32, RB16,
+                                   RH16, dbad, stream)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(&hbad, dbad, sizeof(hbad), hipMemcpyDeviceToHost, stream)) !=
             hipSuccess ||

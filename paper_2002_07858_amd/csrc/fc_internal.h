@@ -223,6 +223,92 @@ __device__ __forceinline__ void wait_record_loads()
 // Packed lower-triangle index for the FP64 factor.
 __host__ __device__ inline int64_t tri_index(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
 
+// ---------------------------------------------------------------------------
+// Gather maps of the covariance build's record writers.  After the
+// factorisation the build holds W_q in LDS as packed rows (W_q[r][c] at
+// r (r + 1) / 2 + c) and S_q beside it; every record element is then one
+// gather, whose source depends only on N (and ns) and is tabulated once per
+// build: kMapZero -> 0, below kMapSig -> the packed W_q index, from kMapSig ->
+// S_q[m - kMapSig].
+// ---------------------------------------------------------------------------
+constexpr int16_t kMapZero = -1;
+constexpr int16_t kMapSig = 0x4000;
+
+__host__ __device__ constexpr int16_t map_w(int N, int rr, int cc)
+{
+    return (rr >= 0 && rr < N && cc >= 0 && cc <= rr) ? (int16_t)(rr * (rr + 1) / 2 + cc)
+                                                       : kMapZero;
+}
+
+// FP64 tile record: one entry per double (2 f64_rec_units(N) entries).
+inline void cov_map_fp64(int N, int16_t *m)
+{
+    const int n = 2 * f64_rec_units(N), nt = f64_ntile(N), P = f64_pad(N), nbe = f64_nbe(N);
+    const int nb = f64_nb(N), sig = f64_sig_double(N), lead = f64_lead_double(N);
+    const int nl = f64_lead(N);
+    for (int e = 0; e < n; ++e) {
+        int16_t v = kMapZero;
+        if (e < sig) {
+            const int t = 2 * (e >> 5) + (e & 1), pos = (e >> 1) & 15;
+            if (t < nt)
+                v = map_w(N, 4 * f64_tile_r(N, t) + (pos & 3) - P,
+                          4 * f64_tile_kb(N, t) + (pos >> 2) - P);
+        } else if (e < lead) {
+            const int g = (e - sig) / nbe, r = (e - sig) % nbe, k = 4 * r + g - P;
+            if (k >= 0 && k < N) v = (int16_t)(kMapSig + k);
+        } else if (e < lead + 4 * nbe * nl) {
+            const int x = e - lead, c = x / (4 * nbe), g = (x / nbe) % 4, r = x % nbe;
+            if (r < nb) v = map_w(N, 4 * r + g - P, c);
+        }
+        m[e] = v;
+    }
+}
+
+// FP32 record, its W_q part: one entry per float (4 rec_w_units(ns) entries),
+// A[v/4][lane][v%4] with lane 4 X + m holding pair t = 16 v + X.
+inline void cov_map_fp32(int ns, int N, int16_t *m)
+{
+    const int P = fp32_pad(ns, N), np = fp32_npairs(ns);
+    for (int v = 0; v < 4 * n_groups_from_ns(ns); ++v)
+        for (int lane = 0; lane < 64; ++lane) {
+            const int t = 16 * v + (lane >> 2), mm = lane & 3;
+            int16_t x = kMapZero;
+            if (t < np)
+                x = map_w(N, 4 * fp32_pair_b(ns, t) + mm - P, fp32_pair_kp(ns, t) - P);
+            m[((v >> 2) * 64 + lane) * 4 + (v & 3)] = x;
+        }
+}
+
+// Split records, their fragments: eight entries per (pair, lane), entry
+// ((t 64 + lane) 8 + e) for element e of lane `lane`'s hi (and lo) fragment.
+inline void cov_map_split(int N, int16_t *m)
+{
+    const int nk = split_nk(N), nb = split_nb(N);
+    for (int s = 0; s < nk; ++s)
+        for (int b = 2 * s; b < nb; ++b) {
+            const int t = split_pair_index(nk, nb, s, b);
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e)
+                    m[(t * 64 + lane) * 8 + e] =
+                        map_w(N, 16 * b + (lane & 15), 32 * s + 8 * (lane >> 4) + e);
+        }
+}
+
+// The maps of all three record forms, in the order FP64 | FP32 | split.
+inline size_t cov_maps_size(int N, int ns)
+{
+    return (size_t)2 * f64_rec_units(N) + (size_t)4 * rec_w_units(ns) +
+           (size_t)split_npairs(split_nk(N), split_nb(N)) * 64 * 8;
+}
+inline void cov_maps_fill(int N, int ns, int16_t *m)
+{
+    cov_map_fp64(N, m);
+    m += 2 * f64_rec_units(N);
+    cov_map_fp32(ns, N, m);
+    m += 4 * rec_w_units(ns);
+    cov_map_split(N, m);
+}
+
 // Key of the running minimum: FP32 chi^2 bits (non-negative, so ordered as
 // unsigned) above the grid index; the integer minimum over keys is the
 // smallest chi^2 with ties broken by the lowest q.
@@ -276,9 +362,11 @@ private:
 
 hipError_t launch_offset(const double *S64, int64_t G, int N, double *off, double *dev,
                          hipStream_t st);
+// maps: a device copy of cov_maps_fill's table (cov_maps_size entries).
 hipError_t launch_cov_build(const fc_grid *g, const double *F, const double *stat, int stat_mode,
-                            uint32_t forms, double *W64, uint4 *R64, uint4 *R32, uint4 *RB16,
-                            uint4 *RH16, unsigned long long *bad_q, hipStream_t st);
+                            uint32_t forms, const int16_t *maps, double *W64, uint4 *R64,
+                            uint4 *R32, uint4 *RB16, uint4 *RH16, unsigned long long *bad_q,
+                            hipStream_t st);
 // The keyed scans cover the grid points [q0, q0 + nq) (nq = G: the whole grid)
 // and merge into keys / chi2_p (see launch_init_keys).
 hipError_t launch_scan_split(const fc_grid *g, bool fp16, int64_t K, const double *d,

@@ -1,0 +1,20 @@
+// k_cov_np_36_48.hip -- the covariance build for padded bin counts 36, 40, 44, 48
+// (split over several files to compile in parallel).
+#include "k_cov_impl.h"
+
+namespace fcx {
+
+template hipError_t launch_cov_np<36>(const fc_grid *, const double *, const double *, int,
+                                       uint32_t, const int16_t *, double *, uint4 *, uint4 *,
+                                       uint4 *, uint4 *, unsigned long long *, hipStream_t);
+template hipError_t launch_cov_np<40>(const fc_grid *, const double *, const double *, int,
+                                       uint32_t, const int16_t *, double *, uint4 *, uint4 *,
+                                       uint4 *, uint4 *, unsigned long long *, hipStream_t);
+template hipError_t launch_cov_np<44>(const fc_grid *, const double *, const double *, int,
+                                       uint32_t, const int16_t *, double *, uint4 *, uint4 *,
+                                       uint4 *, uint4 *, unsigned long long *, hipStream_t);
+template hipError_t launch_cov_np<48>(const fc_grid *, const double *, const double *, int,
+                                       uint32_t, const int16_t *, double *, uint4 *, uint4 *,
+                                       uint4 *, uint4 *, unsigned long long *, hipStream_t);
+
+}  // namespace fcx

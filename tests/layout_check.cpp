@@ -4,7 +4,12 @@
 // factor exactly once (rows 4b + m - P, bins k' - P, pairs with k' < P
 // skipped), never reach outside the padded tile, are numbered 0..npair-1 in
 // enumeration order, and fp32_pair_kp / fp32_pair_b invert the numbering.
+// Then the covariance build's gather maps: in the FP64, FP32 and split
+// records every entry of the lower triangle of W_q appears exactly once (the
+// FP64 record: in its tiles or its lead columns), the FP64 record carries
+// every signal bin once, and nothing else is gathered.
 // Prints "ok" or the first failure.
+#include <cstdint>
 #include <cstdio>
 #include <vector>
 
@@ -50,6 +55,30 @@ int main()
                     printf("N=%d entry (%d,%d) covered %d times\n", N, r, c, hits[r * N + c]);
                     return 1;
                 }
+    }
+    for (int N = 1; N <= 64; ++N) {
+        const int ns = n_ksteps(N), T = N * (N + 1) / 2;
+        std::vector<int16_t> m(cov_maps_size(N, ns));
+        cov_maps_fill(N, ns, m.data());
+        const int n64 = 2 * f64_rec_units(N), n32 = 4 * rec_w_units(ns);
+        const int n16 = (int)m.size() - n64 - n32;
+        const int16_t *parts[3] = {m.data(), m.data() + n64, m.data() + n64 + n32};
+        const int lens[3] = {n64, n32, n16};
+        for (int f = 0; f < 3; ++f) {
+            std::vector<int> w(T, 0), sg(N, 0);
+            for (int e = 0; e < lens[f]; ++e) {
+                const int v = parts[f][e];
+                if (v == kMapZero) continue;
+                if (v >= 0 && v < T) ++w[v];
+                else if (f == 0 && v >= kMapSig && v < kMapSig + N) ++sg[v - kMapSig];
+                else { printf("N=%d map %d entry %d out of range (%d)\n", N, f, e, v); return 1; }
+            }
+            for (int x = 0; x < T; ++x)
+                if (w[x] != 1) { printf("N=%d map %d: W entry %d gathered %d times\n", N, f, x, w[x]); return 1; }
+            for (int k = 0; k < N; ++k)
+                if (f == 0 && sg[k] != 1) { printf("N=%d FP64 map: signal bin %d %d times\n", N, k, sg[k]); return 1; }
+        }
+        if (n16 != split_npairs(split_nk(N), split_nb(N)) * 64 * 8) { printf("N=%d split map size\n", N); return 1; }
     }
     printf("issued pairs N=57: %d, N=38: %d, N=64: %d\n",
            fp32_npairs(n_ksteps(57)) - fp32_pad(n_ksteps(57), 57) * n_ksteps(57),
