@@ -252,8 +252,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 bad |= (piv > 0.0) ? 0 : 1;
                 asm volatile("" : "+v"(bad));  // folded now, not as NP masks at the end
                 const double pv = (piv > 0.0) ? piv : 1.0;
-                if (i == 0) rlv[j] = 1.0 / sqrt(pv);
-                return (i > j) ? a[j] / pv : 0.0;
+                // 1 / sqrt(pv): the hardware estimate and two Newton steps,
+                // y <- y (3/2 - (pv/2) y^2) (a short chain; every step waits
+                // on it), and 1 / pv as its square
+                const double h = 0.5 * pv;
+                double y = __builtin_amdgcn_rsq(pv);
+                y = y * fma(-h * y, y, 1.5);
+                y = y * fma(-h * y, y, 1.5);
+                if (i == 0) rlv[j] = y;
+                return (i > j) ? a[j] * (y * y) : 0.0;
             });
         });
         if (bad) {  // uniform
