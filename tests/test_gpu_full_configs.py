@@ -4,7 +4,8 @@ make_full_config_golden.py, which calls only the oracle) and on properties
 that hold at any size, in the launch configuration the benchmark times.
 
 c2: D=2 100^2 (10 000 points), N=57, 256 true points x 2000 universes: every
-    universe of 4 true points and their full-K critical values.
+    universe of 4 true points, and the full-K critical values and histograms
+    of all 256 true points (the oracle ran on every universe).
 c3: D=3 60^3 (216 000 points), N=57, 64 true points x 4000 universes: the
     first 64 universes of every true point plus all 4000 of 2 true points
     (full-K critical values).
@@ -112,6 +113,13 @@ def test_full_config_parity(config, form):
         bound = tol * max(1.0, float(dev["chi2_p"][lo:hi].max()))
         err = np.abs(dev["crit"][s] - ref["crit"][j])
         assert np.all(err <= bound), (name, form, int(s), err, bound)
+    if "crit_all" in ref:
+        # every true point's critical values (the oracle's full run)
+        for s in range(len(pr.seg_off) - 1):
+            lo, hi = int(pr.seg_off[s]), int(pr.seg_off[s + 1])
+            bound = tol * max(1.0, float(dev["chi2_p"][lo:hi].max()))
+            err = np.abs(dev["crit"][s] - ref["crit_all"][s])
+            assert np.all(err <= bound), (name, form, s, err, bound)
 
 
 def test_forms_agree_on_every_universe(config):
