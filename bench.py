@@ -96,18 +96,19 @@ SPLIT_SOURCES = ("paper_2002_07858_amd/csrc/k_scan_split.hip",
 FP64_SOURCES = ("paper_2002_07858_amd/csrc/k_scan64.hip",
                 "paper_2002_07858_amd/csrc/fc_internal.h")
 # FETCH_SIZE (KiB x 1024 x 2.0000) + WRITE_SIZE (KiB x 1024 x 1.0000) of one launch
+# (the FP32 and split forms: mean of the three launches of one run)
 TRAFFIC = {
-    ("c5", "fp64", "points"): {"bytes_per_launch": 3902496378 * 2048 + 56250 * 1024,
-                               "source_hash": "df1add898ca146e3", "sources": FP64_SOURCES,
+    ("c5", "fp64", "points"): {"bytes_per_launch": 4032393833 * 2048 + 56250 * 1024,
+                               "source_hash": "e900e519f807e0a5", "sources": FP64_SOURCES,
                                "profile": "profiles/k_scan_f64m_c5.md"},
-    ("c5", "fp32", "points"): {"bytes_per_launch": 1901555571 * 2048 + 15000 * 1024,
-                               "source_hash": "2ba159aaaafa1750", "sources": FP32_SOURCES,
+    ("c5", "fp32", "points"): {"bytes_per_launch": 1874227550 * 2048 + 15000 * 1024,
+                               "source_hash": "8cc3e7c80069f94b", "sources": FP32_SOURCES,
                                "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
-    ("c5", "split_fp16", "points"): {"bytes_per_launch": 2430768542 * 2048 + 56250 * 1024,
-                                     "source_hash": "11c02535c8c34f6d", "sources": SPLIT_SOURCES,
+    ("c5", "split_fp16", "points"): {"bytes_per_launch": 2452923570 * 2048 + 56250 * 1024,
+                                     "source_hash": "0c91618335a8fce3", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
-    ("c5", "split_bf16", "points"): {"bytes_per_launch": 399826305 * 2048 + 15000 * 1024,
-                                     "source_hash": "11c02535c8c34f6d", "sources": SPLIT_SOURCES,
+    ("c5", "split_bf16", "points"): {"bytes_per_launch": 435069427 * 2048 + 15000 * 1024,
+                                     "source_hash": "0c91618335a8fce3", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
 }
 
