@@ -214,10 +214,13 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
     SplitLane<NK, NC> L;
     // the universes, split once: B operand of k-step s for column block c holds
     // bins 32s + 8*grp + e of universe u0 + 16c + col, as 2^(ed - eu) (d - o).
-    // FP16: eu >= 0 is the universe's own power of two keeping its largest
-    // |d - o| 2^(ed - eu) below 2^15 (FP16's largest finite value is just under
-    // 2^16); it is 0 for every universe within 4x the grid's range of S - o
-    // (ed keeps that below 2^13), and then the values are the grid-wide scale's.
+    // FP16: eu >= 0 is the universe's own power of two, 0 while its largest
+    // |d - o| 2^ed is below 65504 (FP16's largest finite value: hi rounds to at
+    // most that, lo is its small rest), i.e. for every universe within 8x the
+    // grid's range of S - o (ed keeps that below 2^13), and the values are then
+    // the grid-wide scale's; beyond, |d - o| 2^(ed - eu) lands in [2^14, 2^15).
+    // eu is kept to 8 bits: a universe beyond 2^269 (whose chi^2 overflows FP32
+    // anyway) saturates.
     bool any_scaled = false;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -233,7 +236,7 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
             m = ldexp(m, ed);
             m = fmax(m, __shfl_xor(m, 16));  // the universe's four lane rows
             m = fmax(m, __shfl_xor(m, 32));
-            if (m >= 32768.0 && m <= 1.0e300) eu = ilogb(m) - 14;
+            if (m >= 65504.0 && m <= 1.0e300) eu = min(ilogb(m) - 14, 255);
         }
         if (c == 0) L.eu_pk = 0;
         L.eu_pk |= (uint32_t)eu << (8 * c);

@@ -443,6 +443,36 @@ def test_optional_outputs_are_optional(fc, form):
     assert rep["e_rel"] <= parity.TOL[form], rep
 
 
+def test_split_fp16_universes_near_the_fp16_limit(fc):
+    """Universes up to 8x the grid's spread of S - o stay at the grid-wide
+    scale (their largest |d - o| 2^ed is below FP16's largest finite value,
+    65504) and remain within the form's tolerance of the oracle; the others
+    are unchanged bit for bit."""
+    pr = fcgen.make_problem("c1", K=192)
+    g = make_grid(fc, pr, ALL_FORMS)
+    o = pr.S.mean(axis=0)
+    spread = np.abs(pr.S - o).max()        # the grid scale keeps spread 2^ed in [2^12, 2^13)
+    d = pr.d.copy()
+    base = run_scan(fc, g, FORM["split_fp16"], d, pr.p_idx)
+    near = [10, 11, 12]
+    k = int(np.argmax(np.abs(pr.S - o).max(axis=0)))
+    d[10, k] = o[k] + 7.5 * spread          # 2^ed |d - o| in [30720, 61440)
+    d[11, k] = o[k] - 7.5 * spread
+    d[12] = o + 7.0 * spread * np.sign(pr.S[pr.p_idx[12]] - o + 1e-300)
+    dev = run_scan(fc, g, FORM["split_fp16"], d, pr.p_idx)
+    parity.check_invariants(dev, pr.G, all_finite=True)
+    ref = oracle.scan(pr.S, pr.F, d, pr.p_idx)
+    rep = parity.report(dev, ref, parity.TOL["split_fp16"])
+    rep.update(parity.argmin_validity(pr, dev, d, ref, parity.TOL["split_fp16"]))
+    assert rep["e_rel"] <= parity.TOL["split_fp16"], rep
+    assert rep["argmin_valid"] == 1.0, rep
+    for u in near:
+        assert abs(dev["chi2_p"][u] - ref["chi2_p"][u]) <= 1e-4 * ref["chi2_p"][u], u
+    keep = np.setdiff1d(np.arange(pr.K), near)
+    for key in ("dchi2", "chi2_min", "chi2_p", "argmin"):
+        np.testing.assert_array_equal(dev[key][keep], base[key][keep])
+
+
 def test_split_fp16_universes_far_outside_the_grid_range(fc):
     """A finite universe whose |d - o| is far beyond the grid's own spread of
     S - o would overflow FP16 at the grid-wide scale; it gets its own power of
