@@ -104,11 +104,11 @@ TRAFFIC = {
     ("c5", "fp32", "points"): {"bytes_per_launch": 1874227550 * 2048 + 15000 * 1024,
                                "source_hash": "8cc3e7c80069f94b", "sources": FP32_SOURCES,
                                "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
-    ("c5", "split_fp16", "points"): {"bytes_per_launch": 2452923570 * 2048 + 56250 * 1024,
-                                     "source_hash": "0c91618335a8fce3", "sources": SPLIT_SOURCES,
+    ("c5", "split_fp16", "points"): {"bytes_per_launch": 1750514823 * 2048 + 56250 * 1024,
+                                     "source_hash": "99a7fb7257e3ebb2", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
-    ("c5", "split_bf16", "points"): {"bytes_per_launch": 435069427 * 2048 + 15000 * 1024,
-                                     "source_hash": "0c91618335a8fce3", "sources": SPLIT_SOURCES,
+    ("c5", "split_bf16", "points"): {"bytes_per_launch": 321774645 * 2048 + 15000 * 1024,
+                                     "source_hash": "99a7fb7257e3ebb2", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
 }
 
