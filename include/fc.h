@@ -154,7 +154,12 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
  * released with hipFreeAsync on `stream` (FC_ERR_NOMEM or FC_ERR_DEVICE if
  * that fails).
  * Universes with NaN/inf data get chi2_min = +inf, argmin = p, dchi2 = NaN;
- * other universes are unaffected.
+ * other universes are unaffected.  The FP32 and split forms hold chi2 in
+ * FP32: a chi2 value beyond FP32's range (about 3.4e38, residuals of order
+ * 1e18) becomes +inf.  The split FP16 form keeps the universes at one
+ * grid-wide power-of-two scale while their largest |d - o| (o the grid mean
+ * of S) stays within 8x the grid's own spread of S - o, and gives a universe
+ * beyond that its own power of two, so its FP16 operands stay finite.
  */
 int fc_scan(const fc_grid *g, int32_t form, int64_t K, const double *d,
             const int64_t *p_idx, double *dchi2, double *chi2_min, int64_t *argmin,
