@@ -24,8 +24,10 @@
 //   * Inversion, lane i = column i of W (L w = e_i): forward substitution in
 //     axpy form over the same stored columns, w_j = s_j / L[j][j], then
 //     s_r -= L[r][j] w_j for r > j, one FMA per register.
-// Every column read is a wave-wide broadcast used by one FMA per lane, so the
-// build is bound by the LDS reads (NP^2 / 2 doubles per point and pass).  W_q
+// Every column read is a wave-wide broadcast used by one FMA per lane: the LDS
+// reads (NP^2 / 2 doubles per point and pass) and the FP64 FMAs are of the same
+// order, and with about two waves per SIMD the per-step chain (store,
+// broadcast, pivot) is what the waves mostly wait on.  W_q
 // then goes to HBM straight from the registers (packed rows: lanes write
 // consecutive addresses) and, as packed rows, into LDS, from where each
 // requested record form is written as gathers through a per-N map
