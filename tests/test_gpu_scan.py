@@ -71,6 +71,35 @@ def test_inverse_covariance_matches_lapack(fc, name):
         assert err <= 1e-12 * kappa, (q, err, kappa)
 
 
+@pytest.mark.parametrize("N", [5, 33, 61, 64])
+def test_inverse_covariance_fixed_stat_every_padding(fc, N):
+    """The register-resident factorisation at bin counts with every padding
+    (N mod 4 = 1, 1, 1, 0; the largest, 64) and a fixed statistical vector:
+    W^T W against LAPACK's inverse of the oracle's covariance."""
+    rng = np.random.default_rng(N)
+    G = 40
+    S = rng.uniform(50.0, 2000.0, size=(G, N))
+    A = rng.standard_normal((N, 2 * N))
+    C = A @ A.T
+    sd = np.sqrt(np.diag(C))
+    sig = rng.uniform(0.05, 0.2, size=N)
+    F = (C / np.outer(sd, sd)) * np.outer(sig, sig)
+    F = 0.5 * (F + F.T)
+    stat = rng.uniform(20.0, 500.0, size=N)
+    g = fc.fc_build_grid([np.arange(float(G))], S)
+    fc.fc_build_covariance(g, F, fc.FC_STAT_FIXED, stat, forms=1 | 2 | 4 | 8)
+    out = torch.empty((G, N, N), dtype=torch.float64, device="cuda")
+    fc.fc_grid_inverse_cov(g, 0, G, out)
+    torch.cuda.synchronize()
+    M = out.cpu().numpy()
+    for q in range(G):
+        Sig = oracle.covariance(S[q], F, oracle.STAT_FIXED, stat)
+        ref = np.linalg.inv(Sig)
+        err = np.linalg.norm(M[q] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-12 * np.linalg.cond(Sig), (N, q, err)
+    g.destroy()
+
+
 def test_not_positive_definite_reports_first_bad_point(fc):
     N = 4
     S = np.full((6, N), 100.0)
