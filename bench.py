@@ -83,7 +83,7 @@ WORKLOADS = {
     "c3": dict(desc="c3: D=3 grid 60^3 (G=216000), N=57, 64 true points x 4000 universes",
                steps=3, warmup=1, cpu_per_point=8, serving=0),
     "c5": dict(desc="c5: D=5 grid 16^5 (G=1048576), N=57, 16 true points x 10000 universes",
-               steps=2, warmup=1, cpu_per_point=16, serving=200),
+               steps=3, warmup=1, cpu_per_point=16, serving=200),
 }
 
 # HBM traffic of the scan kernel per launch, from rocprofv3 FETCH_SIZE and
