@@ -462,7 +462,8 @@ const char *fc_last_error(void);
  * Kernel timing for measurement tools (no paper passage: instrumentation).
  * fc_profile_enable(1) clears earlier records and starts bracketing every
  * launch of the scan kernels (k_scan_f64m, k_scan_fp32, k_scan_fp32_pts,
- * k_offset_table, k_scan_split) with two HIP events recorded on the stream the
+ * k_offset_table, k_scan_split) and of the covariance build (k_cov_build)
+ * with two HIP events recorded on the stream the
  * kernel is launched on; fc_profile_enable(0) stops (records are kept).
  * fc_profile_read waits for the recorded launches of one kernel and returns
  * their count and summed duration in milliseconds.  Thread-safe; profiling
