@@ -98,8 +98,8 @@ FP64_SOURCES = ("paper_2002_07858_amd/csrc/k_scan64.hip",
 # FETCH_SIZE (KiB x 1024 x 2.0000) + WRITE_SIZE (KiB x 1024 x 1.0000) of one launch
 # (the FP32 and split forms: mean of the three launches of one run)
 TRAFFIC = {
-    ("c5", "fp64", "points"): {"bytes_per_launch": 4032393833 * 2048 + 56250 * 1024,
-                               "source_hash": "e900e519f807e0a5", "sources": FP64_SOURCES,
+    ("c5", "fp64", "points"): {"bytes_per_launch": 4109908336 * 2048 + 28750 * 1024,
+                               "source_hash": "e630d11ce573129b", "sources": FP64_SOURCES,
                                "profile": "profiles/k_scan_f64m_c5.md"},
     ("c5", "fp32", "points"): {"bytes_per_launch": 1874227550 * 2048 + 15000 * 1024,
                                "source_hash": "8cc3e7c80069f94b", "sources": FP32_SOURCES,

@@ -83,7 +83,9 @@ __device__ __forceinline__ void f64_tiles(F64Acc<N> &s, const double2 *__restric
 
 // Sum of x over the lanes l, l ^ 16, l ^ 32, l ^ 48 for two values a (set 0)
 // and b (set 1): lanes < 32 get set 0's sum, lanes >= 32 set 1's.  The upper
-// half of a is swapped with the lower half of b, then 16-lane rows pair up.
+// half of a is swapped with the lower half of b, then 16-lane rows pair up
+// through a swizzle (lane l reads lane l ^ 16), which runs on the LDS unit
+// and so takes no vector-ALU time from the FP64 MFMAs.
 __device__ __forceinline__ double f64_row_sum(double a, double b)
 {
     const uint2 ua = __builtin_bit_cast(uint2, a), ub = __builtin_bit_cast(uint2, b);
@@ -93,11 +95,10 @@ __device__ __forceinline__ double f64_row_sum(double a, double b)
     const double b2 = __builtin_bit_cast(double, make_uint2(lo[1], hi[1]));
     const double h = a2 + b2;  // lane l < 32: a_l + a_{l+32}; lane l >= 32: b_{l-32} + b_l
     const uint2 uh = __builtin_bit_cast(uint2, h);
-    const auto lo2 = __builtin_amdgcn_permlane16_swap(uh.x, uh.x, false, false);
-    const auto hi2 = __builtin_amdgcn_permlane16_swap(uh.y, uh.y, false, false);
-    const double c2 = __builtin_bit_cast(double, make_uint2(lo2[0], hi2[0]));
-    const double d2 = __builtin_bit_cast(double, make_uint2(lo2[1], hi2[1]));
-    return c2 + d2;
+    // bit-mode swizzle: and 0x1f, or 0, xor 0x10 within each 32-lane half
+    const uint32_t sx = (uint32_t)__builtin_amdgcn_ds_swizzle((int)uh.x, 0x401F);
+    const uint32_t sy = (uint32_t)__builtin_amdgcn_ds_swizzle((int)uh.y, 0x401F);
+    return h + __builtin_bit_cast(double, make_uint2(sx, sy));
 }
 
 template <int N>
