@@ -98,17 +98,17 @@ FP64_SOURCES = ("paper_2002_07858_amd/csrc/k_scan64.hip",
 # FETCH_SIZE (KiB x 1024 x 2.0000) + WRITE_SIZE (KiB x 1024 x 1.0000) of one launch
 # (the FP32 and split forms: mean of the three launches of one run)
 TRAFFIC = {
-    ("c5", "fp64", "points"): {"bytes_per_launch": 4109908336 * 2048 + 28750 * 1024,
-                               "source_hash": "e630d11ce573129b", "sources": FP64_SOURCES,
+    ("c5", "fp64", "points"): {"bytes_per_launch": 4030085096 * 2048 + 28750 * 1024,
+                               "source_hash": "94700be90b106c3e", "sources": FP64_SOURCES,
                                "profile": "profiles/k_scan_f64m_c5.md"},
-    ("c5", "fp32", "points"): {"bytes_per_launch": 1874227550 * 2048 + 15000 * 1024,
-                               "source_hash": "8cc3e7c80069f94b", "sources": FP32_SOURCES,
+    ("c5", "fp32", "points"): {"bytes_per_launch": 1878591182 * 2048 + 15000 * 1024,
+                               "source_hash": "3a43f67f3a6367f6", "sources": FP32_SOURCES,
                                "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
-    ("c5", "split_fp16", "points"): {"bytes_per_launch": 1750514823 * 2048 + 56250 * 1024,
-                                     "source_hash": "99a7fb7257e3ebb2", "sources": SPLIT_SOURCES,
+    ("c5", "split_fp16", "points"): {"bytes_per_launch": 2168687946 * 2048 + 2561250 * 1024,
+                                     "source_hash": "8b6ffbb410a4eb8e", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
-    ("c5", "split_bf16", "points"): {"bytes_per_launch": 321774645 * 2048 + 15000 * 1024,
-                                     "source_hash": "99a7fb7257e3ebb2", "sources": SPLIT_SOURCES,
+    ("c5", "split_bf16", "points"): {"bytes_per_launch": 583341770 * 2048 + 6721251 * 1024,
+                                     "source_hash": "8b6ffbb410a4eb8e", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
 }
 

@@ -63,7 +63,7 @@ void free_forms(fc_grid *g)
 
 size_t split_record_bytes(const fc_grid *g)
 {
-    return sizeof(uint4) * (size_t)fcx::split_rec_units(fcx::split_nk(g->N), fcx::split_nb(g->N));
+    return sizeof(uint4) * (size_t)fcx::split_rec_units(g->N);
 }
 
 size_t grid_bytes(const fc_grid *g)

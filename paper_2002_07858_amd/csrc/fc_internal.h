@@ -82,47 +82,96 @@ __host__ __device__ constexpr int fp32_pair_b(int ns, int t)
 
 // ---------------------------------------------------------------------------
 // Split-form layout (hi+lo BF16 or FP16 operands, FP32 accumulation) for
-// v_mfma_f32_16x16x32_{bf16,f16}: A = 16x32 tiles of the factor, B = 32x16
-// tiles of the universes.  The split forms use linearity,
+// v_mfma_f32_16x16x32_{bf16,f16}: A = 16x32 fragments of the factor, B = 32x16
+// fragments of the universes.  The split forms use linearity,
 //     z = W_q (d - S_q) = W_q (d - o) - W_q (S_q - o),
 // so that the universes are split once (registers, for the whole scan) and
 // u_q = W_q (S_q - o) is computed per grid point in FP64 when the form is
-// built; o is a per-bin offset (the grid mean of S).  Bins are taken 32 at a
-// time (nk = ceil(N/32) k-steps), rows 16 at a time (nb = ceil(N/16)); row
-// block b needs the first cnt(b) = min(nk, b/2 + 1) k-steps.  Pairs (s, b)
-// run s outer, b = 2s .. nb-1 inner.  Lane l of pair (s, b) holds the eight
-// A-operand values W_q[16b + l%16][32s + 8(l/16) + e], e = 0..7, scaled by
-// 2^eq (FP16 form) and split hi + lo.  Record of one grid point (16 B units):
-//     [pair][hi | lo][lane]           npair * 128 units
-//     c[g][b][j] FP32, -2^(eq+ed) * u_q[16b + 4g + j]           16 units
-//     {2^-2(eq+ed), 0, 0, 0}                                       1 unit
-// c is the initial accumulator of every row block, so that the MFMA chain
-// ends at 2^(eq+ed) z and chi^2 = 2^-2(eq+ed) sum z'^2.  eq is chosen per grid
-// point so that max |W_q| 2^eq lies in [2^13, 2^14); ed per grid so that
-// max |S - o| 2^ed is below 2^13 (both 0 for BF16, whose range is FP32's).
+// built; o is a per-bin offset (the grid mean of S).
+//
+// The three products hi*hi + hi*lo + lo*hi of a bin sit next to each other
+// along k: position p = 3 j + t holds bin j, with (A, B) = (W_hi, d_hi) for
+// t = 0, (W_hi, d_lo) for t = 1 and (W_lo, d_hi) for t = 2, so a row needing
+// bins 0..r needs the first 3 (r + 1) positions and no product is padded to
+// a 32-position step on its own.  Rows go in nb = ceil(N/16) groups of at
+// most 16, every group but the first full (group g holds rows
+// row0(g) .. row0(g+1)-1, row0(0) = 0, row0(g) = N - 16 (nb - g)), which
+// keeps each group's last row, and so its step count
+// steps(g) = ceil(3 row0(g+1) / 32), as small as 16-row groups allow (N = 57:
+// rows 0-8 | 9-24 | 25-40 | 41-56, 1 + 3 + 4 + 6 = 14 steps of 32 positions,
+// where a separate 32-bin padding of each product takes 18).
+//
+// Fragment f = (g, s), numbered group by group, holds in lane l the eight A
+// values at positions 32 s + 8 (l/16) + e, e = 0..7, of row row0(g) + l%16
+// (zero past the group's last row or the row's last bin), W_q scaled by 2^eq
+// (FP16 form).  Record of one grid point (16 B units):
+//     [fragment][lane]                                  nfrag * 64 units
+//     c[l/16][g][j] FP32, -2^(eq+ed) u_q[row0(g) + 4 (l/16) + j]   16 units
+//     {2^-2(eq+ed), 0, 0, 0}                                        1 unit
+// c is the initial accumulator of every row group (zero on padding rows), so
+// that the MFMA chain ends at 2^(eq+ed) z and chi^2 = 2^-2(eq+ed) sum z'^2.
+// eq is chosen per grid point so that max |W_q| 2^eq lies in [2^13, 2^14); ed
+// per grid so that max |S - o| 2^ed is below 2^13 (both 0 for BF16, whose
+// range is FP32's).  The step counts of the groups, four bits each, name the
+// kernel that scans the form (`split_code`).
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int split_nk(int N) { return ceil_div(N, 32); }
 __host__ __device__ constexpr int split_nb(int N) { return ceil_div(N, 16); }
-__host__ __device__ constexpr int split_cnt(int nk, int b) { return (b / 2 + 1 < nk) ? b / 2 + 1 : nk; }
-__host__ __device__ constexpr int split_npairs(int nk, int nb)
+__host__ __device__ constexpr int split_row0(int N, int g)
 {
-    int t = 0;
-    for (int b = 0; b < nb; ++b) t += split_cnt(nk, b);
+    return g <= 0 ? 0 : (g >= split_nb(N) ? N : N - 16 * (split_nb(N) - g));
+}
+__host__ __device__ constexpr int split_steps(int N, int g)
+{
+    return g < split_nb(N) ? ceil_div(3 * split_row0(N, g + 1), 32) : 0;
+}
+__host__ __device__ constexpr int split_code(int N)
+{
+    return split_steps(N, 0) | split_steps(N, 1) << 4 | split_steps(N, 2) << 8 |
+           split_steps(N, 3) << 12;
+}
+// the same figures from a code
+__host__ __device__ constexpr int code_steps(int code, int g) { return (code >> (4 * g)) & 15; }
+__host__ __device__ constexpr int code_nb(int code)
+{
+    return (code_steps(code, 0) != 0) + (code_steps(code, 1) != 0) + (code_steps(code, 2) != 0) +
+           (code_steps(code, 3) != 0);
+}
+__host__ __device__ constexpr int code_smax(int code)
+{
+    int m = 0;
+    for (int g = 0; g < 4; ++g) m = code_steps(code, g) > m ? code_steps(code, g) : m;
+    return m;
+}
+__host__ __device__ constexpr int code_nfrag(int code)
+{
+    return code_steps(code, 0) + code_steps(code, 1) + code_steps(code, 2) + code_steps(code, 3);
+}
+__host__ __device__ constexpr int code_frag(int code, int g, int s)
+{
+    int t = s;
+    for (int g2 = 0; g2 < g; ++g2) t += code_steps(code, g2);
     return t;
 }
-__host__ __device__ constexpr int split_pair_index(int nk, int nb, int s, int b)
+// The i-th fragment in the scan's issue order (steps outer, groups inner):
+// its step and its group.
+__host__ __device__ constexpr int code_issue_s(int code, int i)
 {
-    int t = 0;
-    for (int s2 = 0; s2 < s; ++s2) t += nb - 2 * s2;
-    (void)nk;
-    return t + (b - 2 * s);
+    for (int s = 0; s < 16; ++s)
+        for (int g = 0; g < 4; ++g)
+            if (s < code_steps(code, g) && i-- == 0) return s;
+    return -1;
 }
-__host__ __device__ constexpr int split_u_unit(int nk, int nb) { return split_npairs(nk, nb) * 128; }
-__host__ __device__ constexpr int split_scale_unit(int nk, int nb) { return split_u_unit(nk, nb) + 16; }
-__host__ __device__ constexpr int split_rec_units(int nk, int nb)
+__host__ __device__ constexpr int code_issue_g(int code, int i)
 {
-    return split_scale_unit(nk, nb) + 1;
+    for (int s = 0; s < 16; ++s)
+        for (int g = 0; g < 4; ++g)
+            if (s < code_steps(code, g) && i-- == 0) return g;
+    return -1;
 }
+__host__ __device__ constexpr int code_u_unit(int code) { return code_nfrag(code) * 64; }
+__host__ __device__ constexpr int code_scale_unit(int code) { return code_u_unit(code) + 16; }
+__host__ __device__ constexpr int code_rec_units(int code) { return code_scale_unit(code) + 1; }
+__host__ __device__ constexpr int split_rec_units(int N) { return code_rec_units(split_code(N)); }
 
 // ---------------------------------------------------------------------------
 // FP64 tile form for v_mfma_f64_4x4x4f64 (four 4x4x4 blocks; the tile of W is
@@ -279,18 +328,25 @@ inline void cov_map_fp32(int ns, int N, int16_t *m)
         }
 }
 
-// Split records, their fragments: eight entries per (pair, lane), entry
-// ((t 64 + lane) 8 + e) for element e of lane `lane`'s hi (and lo) fragment.
+// Split records, their fragments: eight entries per (fragment, lane), entry
+// (f 64 + lane) 8 + e for element e of lane `lane`'s fragment f; kMapLo marks
+// the low half of the split value (position 3 j + 2 of bin j).
+constexpr int16_t kMapLo = 0x2000;
 inline void cov_map_split(int N, int16_t *m)
 {
-    const int nk = split_nk(N), nb = split_nb(N);
-    for (int s = 0; s < nk; ++s)
-        for (int b = 2 * s; b < nb; ++b) {
-            const int t = split_pair_index(nk, nb, s, b);
-            for (int lane = 0; lane < 64; ++lane)
-                for (int e = 0; e < 8; ++e)
-                    m[(t * 64 + lane) * 8 + e] =
-                        map_w(N, 16 * b + (lane & 15), 32 * s + 8 * (lane >> 4) + e);
+    const int code = split_code(N);
+    for (int g = 0; g < code_nb(code); ++g)
+        for (int s = 0; s < code_steps(code, g); ++s) {
+            const int f = code_frag(code, g, s);
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = split_row0(N, g) + (lane & 15);
+                for (int e = 0; e < 8; ++e) {
+                    const int p = 32 * s + 8 * (lane >> 4) + e, j = p / 3;
+                    int16_t v = row < split_row0(N, g + 1) ? map_w(N, row, j) : kMapZero;
+                    if (v != kMapZero && p % 3 == 2) v = (int16_t)(v | kMapLo);
+                    m[(f * 64 + lane) * 8 + e] = v;
+                }
+            }
         }
 }
 
@@ -298,7 +354,7 @@ inline void cov_map_split(int N, int16_t *m)
 inline size_t cov_maps_size(int N, int ns)
 {
     return (size_t)2 * f64_rec_units(N) + (size_t)4 * rec_w_units(ns) +
-           (size_t)split_npairs(split_nk(N), split_nb(N)) * 64 * 8;
+           (size_t)code_nfrag(split_code(N)) * 64 * 8;
 }
 inline void cov_maps_fill(int N, int ns, int16_t *m)
 {
@@ -427,12 +483,12 @@ struct ScanItem {
 
 hipError_t launch_serve_fp32(int N, const ScanItem *items, int n_items, int *counter, int blocks,
                              hipStream_t st);
-hipError_t launch_serve_split(int nk, int nb, bool fp16, const ScanItem *items, int n_items,
+hipError_t launch_serve_split(int code, bool fp16, const ScanItem *items, int n_items,
                               int *counter, int blocks, hipStream_t st);
 int serve_fp32_univ_per_item();
 int serve_split_univ_per_item();
 int serve_slots_fp32(int N);
-int serve_slots_split(int nk, int nb, bool fp16);
+int serve_slots_split(int code, bool fp16);
 
 hipError_t launch_crit_gapped(int64_t n_seg, const int64_t *seg_lo, const int64_t *seg_hi,
                               const double *x, int n_alpha, const double *alpha, double *crit,

@@ -132,7 +132,7 @@ struct Req {
 };
 
 struct Cls {
-    int ns = 0, nk = 0, nb = 0, N = 0;
+    int ns = 0, code = 0, N = 0;  // code: the split layout (split_code)
     hipStream_t lst[2] = {nullptr, nullptr};   // stream of each launch slot
     hipEvent_t ev_admit[2] = {nullptr, nullptr};  // after the latest admission on lst[k]
     bool admit_wait[2] = {false, false};  // slot k must wait for ev_admit[k ^ 1]
@@ -370,7 +370,7 @@ bool fc_server::launch(Cls &c)
         (e = hipMemsetAsync(c.d_counter[slot], 0, sizeof(int), st)) != hipSuccess ||
         (e = (form == FC_FORM_FP32)
                  ? fcx::launch_serve_fp32(c.N, c.d_items[slot], n, c.d_counter[slot], blocks, st)
-                 : fcx::launch_serve_split(c.nk, c.nb, form == FC_FORM_SPLIT_FP16,
+                 : fcx::launch_serve_split(c.code, form == FC_FORM_SPLIT_FP16,
                                            c.d_items[slot], n, c.d_counter[slot], blocks,
                                            st)) != hipSuccess) {
         std::lock_guard<std::mutex> lk(mu);
@@ -566,15 +566,14 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
             const Cls &cl = s->classes[c];
             const bool same = (form == FC_FORM_FP32)
                                   ? cl.N == N
-                                  : (cl.nk == fcx::split_nk(N) && cl.nb == fcx::split_nb(N));
+                                  : cl.code == fcx::split_code(N);
             if (same) found = (int)c;
         }
         if (found < 0) {
             Cls cl;
             cl.N = N;
             cl.ns = fcx::n_ksteps(N);
-            cl.nk = fcx::split_nk(N);
-            cl.nb = fcx::split_nb(N);
+            cl.code = fcx::split_code(N);
             s->classes.push_back(cl);
             found = (int)s->classes.size() - 1;
         }
@@ -622,7 +621,7 @@ int fc_server_create(fc_server **out, const fc_grid *const *grids, int32_t n_gri
             c.slots = fcx::serve_slots_fp32(c.N);
             c.upi = fcx::serve_fp32_univ_per_item();
         } else {
-            c.slots = fcx::serve_slots_split(c.nk, c.nb, s->form == FC_FORM_SPLIT_FP16);
+            c.slots = fcx::serve_slots_split(c.code, s->form == FC_FORM_SPLIT_FP16);
             c.upi = fcx::serve_split_univ_per_item();
         }
     }

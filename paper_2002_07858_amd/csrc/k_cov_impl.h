@@ -151,40 +151,52 @@ __device__ __forceinline__ double cov_gather(int m, const double *Wl, const doub
 }
 
 // One split-form record (see fc_internal.h) from W_q's packed rows in LDS;
-// wmax = max |W_q| (FP16 range).
+// wmax = max |W_q| (FP16 range).  Each fragment element is one gathered W_q
+// entry, scaled, rounded to the 16-bit type (hi) or, marked kMapLo, the rest
+// of that rounding (lo).
 template <bool FP16>
 __device__ void write_split_record(const double *Wl, const double *sdo, const int16_t *map, int N,
                                    int ed, double wmax, uint4 *rq, int i)
 {
-    const int nk = split_nk(N), nb = split_nb(N);
+    const int code = split_code(N);
     const int eq = (FP16 && wmax > 0.0) ? 13 - ilogb(wmax) : 0;
-    const int np = split_npairs(nk, nb);
-    for (int u = i; u < np * 64; u += 64) {
+    const int nf = code_nfrag(code);
+    for (int u = i; u < nf * 64; u += 64) {
         const int16_t *mu = map + 8 * u;
         float x[8];
+        bool lo[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int m = mu[e];
-            x[e] = (m < 0) ? 0.0f : (float)ldexp(Wl[m], eq);
+            lo[e] = m >= 0 && (m & kMapLo) != 0;
+            x[e] = (m < 0) ? 0.0f : (float)ldexp(Wl[m & (kMapLo - 1)], eq);
         }
-        uint4 hi, lo;
-        split8<FP16>(x, hi, lo);
-        rq[(u >> 6) * 128 + (u & 63)] = hi;
-        rq[(u >> 6) * 128 + 64 + (u & 63)] = lo;
+        uint4 hi, lw;
+        split8<FP16>(x, hi, lw);
+        const uint32_t *ph = reinterpret_cast<const uint32_t *>(&hi);
+        const uint32_t *pl = reinterpret_cast<const uint32_t *>(&lw);
+        uint32_t w[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t m0 = lo[2 * h] ? 0x0000ffffu : 0u;
+            const uint32_t m1 = lo[2 * h + 1] ? 0xffff0000u : 0u;
+            w[h] = (ph[h] & ~(m0 | m1)) | (pl[h] & (m0 | m1));
+        }
+        rq[u] = make_uint4(w[0], w[1], w[2], w[3]);
     }
-    // u_q = W_q (S_q - o) in FP64, in the accumulator's row order [g][b][j]
+    // u_q = W_q (S_q - o) in FP64, in the accumulator's row order [l/16][g][j]
     {
-        const int g = i >> 4, b = (i >> 2) & 3, j = i & 3;
-        const int row = 16 * b + 4 * g + j;
+        const int gl = i >> 4, g = (i >> 2) & 3, j = i & 3;
+        const int row = split_row0(N, g) + 4 * gl + j;
         double u = 0.0;
-        if (row < N) {
+        if (g < split_nb(N) && row < split_row0(N, g + 1)) {
             const double *wr = Wl + row * (row + 1) / 2;
 #pragma unroll 4
             for (int k = 0; k <= row; ++k) u += wr[k] * sdo[k];
         }
-        reinterpret_cast<float *>(rq + split_u_unit(nk, nb))[i] = (float)ldexp(-u, eq + ed);
+        reinterpret_cast<float *>(rq + code_u_unit(code))[i] = (float)ldexp(-u, eq + ed);
     }
-    const int su = split_scale_unit(nk, nb), ru = split_rec_units(nk, nb);
+    const int su = code_scale_unit(code), ru = code_rec_units(code);
     if (i == 0) rq[su] = make_uint4(__float_as_uint(ldexpf(1.0f, -2 * (eq + ed))), 0u, 0u, 0u);
     for (int u = su + 1 + i; u < ru; u += 64) rq[u] = make_uint4(0u, 0u, 0u, 0u);
 }
@@ -332,7 +344,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         }
         if (forms & (FC_FORM_SPLIT_BF16 | FC_FORM_SPLIT_FP16)) {
             for (int m = 32; m > 0; m >>= 1) wmax = fmax(wmax, __shfl_xor(wmax, m));
-            const int64_t sru = split_rec_units(split_nk(N), split_nb(N));
+            const int64_t sru = split_rec_units(N);
             if (forms & FC_FORM_SPLIT_BF16)
                 write_split_record<false>(Lc, sdo, map16, N, 0, wmax, RB16 + q * sru, i);
             if (forms & FC_FORM_SPLIT_FP16)

@@ -9,7 +9,10 @@
 // vector -2^(eq+ed) u_q, u_q = W_q (S_q - o), comes precomputed (FP64) with
 // the record as the accumulators' initial value, so the loop over grid points
 // does no per-universe residual work: MFMAs, then one square per z value and
-// one power-of-two rescale per universe.
+// one power-of-two rescale per universe.  The three products of a bin are
+// adjacent positions of one k sequence (layout in fc_internal.h), so the B
+// fragments hold d_hi, d_lo, d_hi, d_hi, d_lo, ... and each row group issues
+// ceil(3 (last row + 1) / 32) MFMAs per column block.
 //
 // Work decomposition as in the FP32 form: a 256-thread block owns 4 waves x
 // 16*NC universes and walks a chunk of grid points, double-buffering one
@@ -57,14 +60,34 @@ __device__ __forceinline__ void split8(const float (&x)[8], uint4 &hi, uint4 &lo
     }
 }
 
+// The k-sequence entry of position p = 3 j + t: the low half of bin j's split
+// for t = 1, the high half otherwise; each 16-bit half of a 32-bit word picked
+// by its own flag.
+__device__ __forceinline__ uint4 pick_lo(const uint4 &hi, const uint4 &lo, uint32_t lomask)
+{
+    uint32_t w[4];
+    const uint32_t *ph = reinterpret_cast<const uint32_t *>(&hi);
+    const uint32_t *pl = reinterpret_cast<const uint32_t *>(&lo);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        const uint32_t m = ((lomask >> (2 * h)) & 1u ? 0x0000ffffu : 0u) |
+                           ((lomask >> (2 * h + 1)) & 1u ? 0xffff0000u : 0u);
+        w[h] = (ph[h] & ~m) | (pl[h] & m);
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// LDS fragment reads kept in flight ahead of the MFMAs that use them.
+constexpr int kFragAhead = 2;
+
 // Per-universe state a wave carries through its range of grid points.
-template <int NK, int NC>
+template <int SM, int NC>
 struct SplitLane {
-    uint4 dhi[NC][NK], dlo[NC][NK];  // B operands: 2^(ed - eu) (d - o) split hi + lo
-    uint32_t eu_pk;                  // per-universe exponents eu (FP16 range), 8 bits per
-                                     // column block; 0 unless far outside the grid's range
-    int e_own;                       // eu of the universe this lane owns after the reduction
-    bool scaled;                     // some universe of the wave has eu != 0 (wave-uniform)
+    uint4 dx[NC][SM];   // B operands: the k sequence of 2^(ed - eu) (d - o), split
+    uint32_t eu_pk;     // per-universe exponents eu (FP16 range), 8 bits per
+                        // column block; 0 unless far outside the grid's range
+    int e_own;          // eu of the universe this lane owns after the reduction
+    bool scaled;        // some universe of the wave has eu != 0 (wave-uniform)
     int64_t p_own;
     float best;
     uint32_t qbest;
@@ -75,13 +98,16 @@ struct SplitLane {
 // One grid point: contract the record in `cur`, fold chi2 into the running
 // minimum, and (if more) bring the next record into `nxt` (separate LDS
 // objects, see the FP32 form).
-template <int NK, int NB, int NC, bool FP16, bool SCALED>
+template <int CODE, int NC, bool FP16, bool SCALED>
 __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *__restrict__ R16,
-                                            const uint4 *cur, uint4 *nxt, SplitLane<NK, NC> &L)
+                                            const uint4 *cur, uint4 *nxt,
+                                            SplitLane<code_smax(CODE), NC> &L)
 {
-    constexpr int REC = split_rec_units(NK, NB);
-    constexpr int UU = split_u_unit(NK, NB);
-    constexpr int SU = split_scale_unit(NK, NB);
+    constexpr int NB = code_nb(CODE);
+    constexpr int SM = code_smax(CODE);
+    constexpr int REC = code_rec_units(CODE);
+    constexpr int UU = code_u_unit(CODE);
+    constexpr int SU = code_scale_unit(CODE);
     constexpr int THREADS = 64 * kWavesPerBlock;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -113,20 +139,24 @@ __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *_
             }
         }
     }
+    // fragments in issue order, each read kFragAhead fragments before its
+    // MFMAs (a fence per fragment keeps the reads from all being hoisted, which
+    // would hold every fragment of the record in registers at once)
+    constexpr int NF = code_nfrag(CODE);
+    uint4 w[NF];
 #pragma unroll
-    for (int s = 0; s < NK; ++s) {
+    for (int i = 0; i < kFragAhead && i < NF; ++i)
+        w[i] = cur[code_frag(CODE, code_issue_g(CODE, i), code_issue_s(CODE, i)) * 64 + lane];
 #pragma unroll
-        for (int b = 2 * s; b < NB; ++b) {
-            const int t = split_pair_index(NK, NB, s, b);
-            const uint4 wh = cur[t * 128 + lane];
-            const uint4 wl = cur[t * 128 + 64 + lane];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                acc[c][b] = mfma16x16x32<FP16>(wh, L.dhi[c][s], acc[c][b]);
-                acc[c][b] = mfma16x16x32<FP16>(wh, L.dlo[c][s], acc[c][b]);
-                acc[c][b] = mfma16x16x32<FP16>(wl, L.dhi[c][s], acc[c][b]);
-            }
+    for (int i = 0; i < NF; ++i) {
+        if (i + kFragAhead < NF) {
+            const int ia = i + kFragAhead;
+            w[ia] = cur[code_frag(CODE, code_issue_g(CODE, ia), code_issue_s(CODE, ia)) * 64 + lane];
         }
+        const int s = code_issue_s(CODE, i), b = code_issue_g(CODE, i);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c][b] = mfma16x16x32<FP16>(w[i], L.dx[c][s], acc[c][b]);
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     // acc = 2^(eq+ed) z: squared and summed per universe column
@@ -188,14 +218,15 @@ __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *_
     __syncthreads();
 }
 
-template <int NK, int NB, int NC, bool FP16>
+template <int CODE, int NC, bool FP16>
 __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint4 *buf1)
 {
     static_assert(NC == 2 || NC == 4, "two or four 16-universe column blocks per wave");
+    constexpr int SM = code_smax(CODE);
     constexpr int UW = 16 * NC;
-    constexpr int REC = split_rec_units(NK, NB);
+    constexpr int REC = code_rec_units(CODE);
     constexpr int THREADS = 64 * kWavesPerBlock;
-    static_assert(REC <= 4 * THREADS, "records of at most four 4 KB pieces");
+    static_assert(REC <= 5 * THREADS, "records of at most five 4 KB pieces");
 
     const uint4 *__restrict__ R16 = it.R;
     const double *__restrict__ d = it.d;
@@ -208,12 +239,13 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
     const int wave = tid >> 6;
     const int64_t u0 = it.u0 + wave * UW;
     const int64_t qb = it.qb, qe = it.qe;
-    if (qb >= qe) return;  // uniform per block
+    if (qb >= qe || K <= 0) return;  // uniform per block
     const int grp = lane >> 4, col = lane & 15;
 
-    SplitLane<NK, NC> L;
+    SplitLane<SM, NC> L;
     // the universes, split once: B operand of k-step s for column block c holds
-    // bins 32s + 8*grp + e of universe u0 + 16c + col, as 2^(ed - eu) (d - o).
+    // positions p = 32s + 8*grp + e of universe u0 + 16c + col's k sequence,
+    // i.e. bin j = p / 3 of 2^(ed - eu) (d - o), its low half where p % 3 = 1.
     // FP16: eu >= 0 is the universe's own power of two, 0 while its largest
     // |d - o| 2^ed is below 65504 (FP16's largest finite value: hi rounds to at
     // most that, lo is its small rest), i.e. for every universe within 8x the
@@ -222,35 +254,61 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
     // eu is kept to 8 bits: a universe beyond 2^269 (whose chi^2 overflows FP32
     // anyway) saturates.
     bool any_scaled = false;
+    L.eu_pk = 0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const int64_t u = u0 + 16 * c + col;
         int eu = 0;
         if constexpr (FP16) {
             double m = 0.0;
-            for (int s = 0; s < NK; ++s)
-                for (int e = 0; e < 8; ++e) {
-                    const int k = 32 * s + 8 * grp + e;
-                    if (u < K && k < N) m = fmax(m, fabs(d[u * N + k] - off[k]));
-                }
+            for (int k = 8 * grp; k < N; k += 32)
+                for (int e = 0; e < 8; ++e)
+                    if (u < K && k + e < N) m = fmax(m, fabs(d[u * N + k + e] - off[k + e]));
             m = ldexp(m, ed);
             m = fmax(m, __shfl_xor(m, 16));  // the universe's four lane rows
             m = fmax(m, __shfl_xor(m, 32));
             if (m >= 65504.0 && m <= 1.0e300) eu = min(ilogb(m) - 14, 255);
         }
-        if (c == 0) L.eu_pk = 0;
         L.eu_pk |= (uint32_t)eu << (8 * c);
         any_scaled = any_scaled || eu != 0;
+    }
+    // a fragment's eight positions 32s + 8*grp + e cover at most four bins
+    // from j0 = (32s + 8*grp) / 3: those are loaded (from clamped, in-range
+    // addresses, the values then masked) and spread; one step at a time for
+    // all column blocks, so that only that step's loads are in flight
 #pragma unroll
-        for (int s = 0; s < NK; ++s) {
+    for (int s = 0; s < SM; ++s) {
+        const int p0 = 32 * s + 8 * grp, j0 = p0 / 3, r0 = p0 - 3 * j0;
+        double o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = off[j0 + i < N ? j0 + i : N - 1];
+        uint32_t lomask = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) lomask |= ((r0 + e) % 3 == 1 ? 1u : 0u) << e;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int64_t u = u0 + 16 * c + col;
+            const bool uin = u < K;
+            const double *__restrict__ du = d + (uin ? u : K - 1) * (int64_t)N;
+            const int sc = ed - (int)((L.eu_pk >> (8 * c)) & 255u);
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = j0 + i;
+                const double dv = du[k < N ? k : N - 1] - o[i];
+                v[i] = (uin && k < N) ? (float)ldexp(dv, sc) : 0.0f;
+            }
             float x[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int k = 32 * s + 8 * grp + e;
-                x[e] = (u < K && k < N) ? (float)ldexp(d[u * N + k] - off[k], ed - eu) : 0.0f;
+                const int i = (r0 + e) / 3;  // 0..3
+                x[e] = i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
             }
-            split8<FP16>(x, L.dhi[c][s], L.dlo[c][s]);
+            uint4 hi, lo;
+            split8<FP16>(x, hi, lo);
+            L.dx[c][s] = pick_lo(hi, lo, lomask);
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
     L.scaled = __any(any_scaled);
     // after the reduction, lane l holds column block cl of universe column col
@@ -272,16 +330,16 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
     int64_t q = qb;
     if (FP16 && L.scaled) {
         for (; q + 1 < qe; q += 2) {
-            split_point<NK, NB, NC, FP16, FP16>(q, true, R16, buf0, buf1, L);
-            split_point<NK, NB, NC, FP16, FP16>(q + 1, q + 2 < qe, R16, buf1, buf0, L);
+            split_point<CODE, NC, FP16, FP16>(q, true, R16, buf0, buf1, L);
+            split_point<CODE, NC, FP16, FP16>(q + 1, q + 2 < qe, R16, buf1, buf0, L);
         }
-        if (q < qe) split_point<NK, NB, NC, FP16, FP16>(q, false, R16, buf0, buf1, L);
+        if (q < qe) split_point<CODE, NC, FP16, FP16>(q, false, R16, buf0, buf1, L);
     } else {
         for (; q + 1 < qe; q += 2) {
-            split_point<NK, NB, NC, FP16, false>(q, true, R16, buf0, buf1, L);
-            split_point<NK, NB, NC, FP16, false>(q + 1, q + 2 < qe, R16, buf1, buf0, L);
+            split_point<CODE, NC, FP16, false>(q, true, R16, buf0, buf1, L);
+            split_point<CODE, NC, FP16, false>(q + 1, q + 2 < qe, R16, buf1, buf0, L);
         }
-        if (q < qe) split_point<NK, NB, NC, FP16, false>(q, false, R16, buf0, buf1, L);
+        if (q < qe) split_point<CODE, NC, FP16, false>(q, false, R16, buf0, buf1, L);
     }
 
     if (owner && u_own < K) {
@@ -294,14 +352,24 @@ __device__ __forceinline__ void split_item(const ScanItem &it, uint4 *buf0, uint
     }
 }
 
-template <int NK, int NB, int NC, bool FP16>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scan_split(
-    const uint4 *__restrict__ R16, const double *__restrict__ d, const double *__restrict__ off,
-    int ed, const int64_t *__restrict__ p_idx, int64_t K, int N, int64_t q_lo, int64_t q_hi,
-    int64_t n_utiles, int64_t q_per_chunk, unsigned long long *__restrict__ keys,
-    double *__restrict__ chi2_p)
+// Waves per SIMD the kernel is built for: three while the B fragments and
+// the accumulators (4 NC (smax + nb) VGPRs) leave room for the rest in a
+// third of the register file, else two.
+template <int CODE, int NC>
+constexpr int split_waves()
 {
-    __shared__ uint4 buf0[split_rec_units(NK, NB)], buf1[split_rec_units(NK, NB)];
+    return 4 * NC * (code_smax(CODE) + code_nb(CODE)) + 40 <= 168 ? 3 : 2;
+}
+
+template <int CODE, int NC, bool FP16>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(split_waves<CODE, NC>())))
+void k_scan_split(const uint4 *__restrict__ R16, const double *__restrict__ d,
+                  const double *__restrict__ off, int ed, const int64_t *__restrict__ p_idx,
+                  int64_t K, int N, int64_t q_lo, int64_t q_hi, int64_t n_utiles,
+                  int64_t q_per_chunk, unsigned long long *__restrict__ keys,
+                  double *__restrict__ chi2_p)
+{
+    __shared__ uint4 buf0[code_rec_units(CODE)], buf1[code_rec_units(CODE)];
     ScanItem it;
     it.R = R16;
     it.d = d;
@@ -318,16 +386,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     it.u0 = utile * (int64_t)(16 * NC * kWavesPerBlock);
     it.qb = q_lo + qchunk * q_per_chunk;
     it.qe = (it.qb + q_per_chunk < q_hi) ? it.qb + q_per_chunk : q_hi;
-    split_item<NK, NB, NC, FP16>(it, buf0, buf1);
+    split_item<CODE, NC, FP16>(it, buf0, buf1);
 }
 
 // Serving: persistent-style launch over a finite table of items (see the
 // FP32 form).
-template <int NK, int NB, int NC, bool FP16>
+template <int CODE, int NC, bool FP16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_serve_split(
     const ScanItem *__restrict__ items, int n_items, int *__restrict__ counter)
 {
-    __shared__ uint4 buf0[split_rec_units(NK, NB)], buf1[split_rec_units(NK, NB)];
+    __shared__ uint4 buf0[code_rec_units(CODE)], buf1[code_rec_units(CODE)];
     __shared__ int cur;
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
@@ -335,7 +403,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int i = cur;
         __syncthreads();
         if (i >= n_items) break;
-        split_item<NK, NB, NC, FP16>(items[i], buf0, buf1);
+        split_item<CODE, NC, FP16>(items[i], buf0, buf1);
         __syncthreads();
     }
 }
@@ -354,8 +422,32 @@ static int resident_slots_split(const void *kernel)
 }
 
 constexpr int kSplitColBlocks = 4;  // 64 universes per wave
+// Grid points per block at most.  The blocks that share a chunk read the
+// same records in the same order, and the L2 serves the later readers only
+// while the blocks stay within a few hundred points of each other; short
+// chunks restart them together often (c5, 2048 instead of 25 600 points:
+// split FP16 7.6 -> 5.6 TB fetched, 1.82 -> 1.66 s; BF16 3.3 -> 1.2 TB).
+constexpr int64_t kSplitChunkMax = 2048;
 
-template <int NK, int NB, bool FP16>
+// Every layout split_code gives for N = 1..64 (step counts of the row groups).
+#define FC_SPLIT_CODES(X)                                                                   \
+    X(0x0001) X(0x0002) X(0x0021) X(0x0031) X(0x0032) X(0x0421) X(0x0431) X(0x0532)        \
+        X(0x5421) X(0x6431) X(0x6532)
+
+constexpr bool split_code_known(int code)
+{
+#define FC_K(c) if (code == (c)) return true;
+    FC_SPLIT_CODES(FC_K)
+#undef FC_K
+    return false;
+}
+constexpr bool split_codes_cover(int n)
+{
+    return n > 64 || (split_code_known(split_code(n)) && split_codes_cover(n + 1));
+}
+static_assert(split_codes_cover(1), "a bin count without a split-form kernel");
+
+template <int CODE, bool FP16>
 static hipError_t launch_split_t(const fc_grid *g, int64_t K, const double *d,
                                  const int64_t *p_idx, int64_t q0, int64_t nq,
                                  unsigned long long *keys, double *chi2_p, hipStream_t st)
@@ -363,80 +455,71 @@ static hipError_t launch_split_t(const fc_grid *g, int64_t K, const double *d,
     constexpr int NC = kSplitColBlocks;
     // resident block slots: queried once per instantiation (thread-safe)
     static const int slots =
-        resident_slots_split(reinterpret_cast<const void *>(&k_scan_split<NK, NB, NC, FP16>));
-    const ScanGeometry sg = scan_geometry(K, nq, slots, 16 * NC * kWavesPerBlock);
+        resident_slots_split(reinterpret_cast<const void *>(&k_scan_split<CODE, NC, FP16>));
+    ScanGeometry sg = scan_geometry(K, nq, slots, 16 * NC * kWavesPerBlock);
+    if (sg.q_per_chunk > kSplitChunkMax) {
+        sg.q_per_chunk = kSplitChunkMax;
+        sg.n_qchunks = (nq + kSplitChunkMax - 1) / kSplitChunkMax;
+    }
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     const uint4 *R = FP16 ? g->RH16 : g->RB16;
     ProfScope prof(st, "k_scan_split");
-    hipLaunchKernelGGL((k_scan_split<NK, NB, NC, FP16>), dim3((unsigned)blocks), dim3(256), 0, st, R,
-                       d, g->off, FP16 ? g->ed16 : 0, p_idx, K, g->N, q0, q0 + nq, sg.n_utiles,
-                       sg.q_per_chunk, keys, chi2_p);
+    hipLaunchKernelGGL((k_scan_split<CODE, NC, FP16>), dim3((unsigned)blocks), dim3(256), 0, st,
+                       R, d, g->off, FP16 ? g->ed16 : 0, p_idx, K, g->N, q0, q0 + nq,
+                       sg.n_utiles, sg.q_per_chunk, keys, chi2_p);
     return hipGetLastError();
 }
 
-template <bool FP16>
-static hipError_t launch_split_f(const fc_grid *g, int64_t K, const double *d,
-                                 const int64_t *p_idx, int64_t q0, int64_t nq,
-                                 unsigned long long *keys, double *chi2_p, hipStream_t st)
-{
-    const int nk = split_nk(g->N), nb = split_nb(g->N);
-#define FC_T(a, b) launch_split_t<a, b, FP16>(g, K, d, p_idx, q0, nq, keys, chi2_p, st)
-    if (nk == 1 && nb == 1) return FC_T(1, 1);
-    if (nk == 1 && nb == 2) return FC_T(1, 2);
-    if (nk == 2 && nb == 3) return FC_T(2, 3);
-    if (nk == 2 && nb == 4) return FC_T(2, 4);
-#undef FC_T
-    return hipErrorInvalidValue;
-}
-
-template <int NK, int NB, bool FP16>
+template <int CODE, bool FP16>
 static int serve_slots_split_t()
 {
     // resident block slots: queried once per instantiation (thread-safe)
-    static const int slots =
-        resident_slots_split(reinterpret_cast<const void *>(
-            &k_serve_split<NK, NB, kSplitColBlocks, FP16>));
+    static const int slots = resident_slots_split(
+        reinterpret_cast<const void *>(&k_serve_split<CODE, kSplitColBlocks, FP16>));
     return slots;
 }
 
-template <int NK, int NB, bool FP16>
+template <int CODE, bool FP16>
 static hipError_t launch_serve_split_t(const ScanItem *items, int n_items, int *counter,
                                        int blocks, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_serve_split<NK, NB, kSplitColBlocks, FP16>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((k_serve_split<CODE, kSplitColBlocks, FP16>), dim3((unsigned)blocks),
                        dim3(256), 0, st, items, n_items, counter);
     return hipGetLastError();
 }
 
 int serve_split_univ_per_item() { return 16 * kSplitColBlocks * kWavesPerBlock; }
 
-#define FC_SPLIT_DISPATCH(EXPR_T)                                   \
-    if (fp16) {                                                     \
-        if (nk == 1 && nb == 1) return EXPR_T(1, 1, true);          \
-        if (nk == 1 && nb == 2) return EXPR_T(1, 2, true);          \
-        if (nk == 2 && nb == 3) return EXPR_T(2, 3, true);          \
-        if (nk == 2 && nb == 4) return EXPR_T(2, 4, true);          \
-    } else {                                                        \
-        if (nk == 1 && nb == 1) return EXPR_T(1, 1, false);         \
-        if (nk == 1 && nb == 2) return EXPR_T(1, 2, false);         \
-        if (nk == 2 && nb == 3) return EXPR_T(2, 3, false);         \
-        if (nk == 2 && nb == 4) return EXPR_T(2, 4, false);         \
-    }
-
-hipError_t launch_serve_split(int nk, int nb, bool fp16, const ScanItem *items, int n_items,
+hipError_t launch_serve_split(int code, bool fp16, const ScanItem *items, int n_items,
                               int *counter, int blocks, hipStream_t st)
 {
-#define FC_T(a, b, c) launch_serve_split_t<a, b, c>(items, n_items, counter, blocks, st)
-    FC_SPLIT_DISPATCH(FC_T)
-#undef FC_T
+#define FC_CASE_T(c) \
+    case c: return launch_serve_split_t<c, true>(items, n_items, counter, blocks, st);
+#define FC_CASE_F(c) \
+    case c: return launch_serve_split_t<c, false>(items, n_items, counter, blocks, st);
+    if (fp16) {
+        switch (code) { FC_SPLIT_CODES(FC_CASE_T) }
+    } else {
+        switch (code) { FC_SPLIT_CODES(FC_CASE_F) }
+    }
+#undef FC_CASE_T
+#undef FC_CASE_F
     return hipErrorInvalidValue;
 }
 
-int serve_slots_split(int nk, int nb, bool fp16)
+int serve_slots_split(int code, bool fp16)
 {
-#define FC_T(a, b, c) serve_slots_split_t<a, b, c>()
-    FC_SPLIT_DISPATCH(FC_T)
-#undef FC_T
+#define FC_CASE_T(c) \
+    case c: return serve_slots_split_t<c, true>();
+#define FC_CASE_F(c) \
+    case c: return serve_slots_split_t<c, false>();
+    if (fp16) {
+        switch (code) { FC_SPLIT_CODES(FC_CASE_T) }
+    } else {
+        switch (code) { FC_SPLIT_CODES(FC_CASE_F) }
+    }
+#undef FC_CASE_T
+#undef FC_CASE_F
     return 512;
 }
 
@@ -444,8 +527,19 @@ hipError_t launch_scan_split(const fc_grid *g, bool fp16, int64_t K, const doubl
                              const int64_t *p_idx, int64_t q0, int64_t nq,
                              unsigned long long *keys, double *chi2_p, hipStream_t st)
 {
-    return fp16 ? launch_split_f<true>(g, K, d, p_idx, q0, nq, keys, chi2_p, st)
-                : launch_split_f<false>(g, K, d, p_idx, q0, nq, keys, chi2_p, st);
+    const int code = split_code(g->N);
+#define FC_CASE_T(c) \
+    case c: return launch_split_t<c, true>(g, K, d, p_idx, q0, nq, keys, chi2_p, st);
+#define FC_CASE_F(c) \
+    case c: return launch_split_t<c, false>(g, K, d, p_idx, q0, nq, keys, chi2_p, st);
+    if (fp16) {
+        switch (code) { FC_SPLIT_CODES(FC_CASE_T) }
+    } else {
+        switch (code) { FC_SPLIT_CODES(FC_CASE_F) }
+    }
+#undef FC_CASE_T
+#undef FC_CASE_F
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fcx
