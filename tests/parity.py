@@ -25,6 +25,27 @@ import numpy as np
 TOL = {"fp64": 1e-11, "fp32": 1e-6, "split_bf16": 1e-4, "split_fp16": 1e-4}
 
 
+def split_bf16_tol(S, d, p) -> float:
+    """The split-BF16 form's error bound on a given input.
+
+    The split forms contract z = W_q (d - o) - W_q (S_q - o) with o the grid's
+    mean signal per bin, so their products see d - o, not d - S_q.  A BF16
+    hi + lo pair carries x to 2^-18 |x|, and each of the three products
+    hi*hi + hi*lo + lo*hi of W_ij x_j is off by at most about 3 * 2^-18
+    |W_ij x_j|; with R = max_j |d_j - o_j| / sqrt(S_p,j), the universe's
+    reach from the offset in its own standard deviations, a row of z is off
+    by a few 2^-18 R, and chi^2 = |z|^2 by about 2^-14 R relative to
+    max(1, chi^2_p) (a few 2^-16 R sqrt(N) absolute against chi^2 ~ N).
+    The 1e-4 target holds while R stays within about 15 (the c1-c5
+    configurations: R <= 25 and N >= 38, measured 2e-5); few bins on a wide
+    grid reach 1e-4 to 4e-4 (FP16, with 5 more bits in each half, stays
+    below 1e-5 on the same inputs)."""
+    S = np.asarray(S, dtype=np.float64)
+    o = S.mean(axis=0)
+    R = float(np.max(np.abs(np.asarray(d) - o) / np.sqrt(S[np.asarray(p)])))
+    return max(TOL["split_bf16"], 2.0 ** -14 * R)
+
+
 def report(dev: dict, ref: dict, tol: float) -> dict:
     scale = np.maximum(1.0, ref["chi2_p"])
     e_abs = np.abs(dev["dchi2"] - ref["dchi2"])

@@ -184,14 +184,16 @@ def test_scan_parity_bin_counts(fc, N):
         assert rep["argmin_agree"] == 1.0, (form, rep)
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp64"])
+@pytest.mark.parametrize("form", ["fp32", "fp64", "split_bf16", "split_fp16"])
 @pytest.mark.parametrize("N", list(range(1, 65)))
 def test_every_bin_count(fc, N, form):
-    """The FP32 and FP64 kernels are compiled per bin count (FP32: the padding
-    shift, the skipped slices and the signal-chunk boundaries; FP64: the
-    number of 4-bin blocks): every N against the oracle, with an odd grid (a
-    grid point left over after the pairs), two universe tiles and a ragged
-    second one."""
+    """The kernels are compiled per bin count or per layout of it (FP32: the
+    padding shift, the skipped slices and the signal-chunk boundaries; FP64:
+    the number of 4-bin blocks; split: the row groups and their k-step counts,
+    eleven layouts over N = 1..64, each group's last row at a different place
+    in its last step): every N against the oracle, with an odd grid (a grid
+    point left over after the pairs), two universe tiles and a ragged second
+    one."""
     import types
     rng = np.random.default_rng(1000 + N)
     G, K = 23, 300
@@ -208,12 +210,15 @@ def test_every_bin_count(fc, N, form):
     dev = run_scan(fc, g, FORM[form], d, p)
     g.destroy()
     parity.check_invariants(dev, G, all_finite=True)
-    rep = parity.report(dev, ref, parity.TOL[form])
+    # this grid spans up to ~100 standard deviations: the split-BF16 form is
+    # held to its derived bound there (the other forms to their targets)
+    tol = parity.split_bf16_tol(S, d, p) if form == "split_bf16" else parity.TOL[form]
+    rep = parity.report(dev, ref, tol)
     pr = types.SimpleNamespace(S=S, F=F, stat_mode=0, stat_diag=None, G=G)
-    rep.update(parity.argmin_validity(pr, dev, d, ref, parity.TOL[form]))
-    assert rep["e_rel"] <= parity.TOL[form], rep
+    rep.update(parity.argmin_validity(pr, dev, d, ref, tol))
+    assert rep["e_rel"] <= tol, (tol, rep)
     assert rep["argmin_agree"] == 1.0, rep
-    assert rep["argmin_valid"] == 1.0, rep
+    assert rep["argmin_valid"] == 1.0, (tol, rep)
 
 
 # ---------------------------------------------------------------------------
