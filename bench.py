@@ -96,7 +96,7 @@ SPLIT_SOURCES = ("paper_2002_07858_amd/csrc/k_scan_split.hip",
 FP64_SOURCES = ("paper_2002_07858_amd/csrc/k_scan64.hip",
                 "paper_2002_07858_amd/csrc/fc_internal.h")
 # FETCH_SIZE (KiB x 1024 x 2.0000) + WRITE_SIZE (KiB x 1024 x 1.0000) of one launch
-# (the FP32 and split forms: mean of the three launches of one run)
+# (a leg's: mean of the three launches of one run)
 TRAFFIC = {
     ("c5", "fp64", "points"): {"bytes_per_launch": 4030085096 * 2048 + 28750 * 1024,
                                "source_hash": "94700be90b106c3e", "sources": FP64_SOURCES,
@@ -104,11 +104,11 @@ TRAFFIC = {
     ("c5", "fp32", "points"): {"bytes_per_launch": 1878591182 * 2048 + 15000 * 1024,
                                "source_hash": "3a43f67f3a6367f6", "sources": FP32_SOURCES,
                                "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
-    ("c5", "split_fp16", "points"): {"bytes_per_launch": 2168687946 * 2048 + 2561250 * 1024,
-                                     "source_hash": "8b6ffbb410a4eb8e", "sources": SPLIT_SOURCES,
+    ("c5", "split_fp16", "points"): {"bytes_per_launch": 2194617926 * 2048 + 2561250 * 1024,
+                                     "source_hash": "426698537f46a4cf", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
-    ("c5", "split_bf16", "points"): {"bytes_per_launch": 583341770 * 2048 + 6721251 * 1024,
-                                     "source_hash": "8b6ffbb410a4eb8e", "sources": SPLIT_SOURCES,
+    ("c5", "split_bf16", "points"): {"bytes_per_launch": 568374400 * 2048 + 6721251 * 1024,
+                                     "source_hash": "426698537f46a4cf", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
 }
 

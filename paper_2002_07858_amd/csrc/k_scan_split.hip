@@ -77,8 +77,11 @@ __device__ __forceinline__ uint4 pick_lo(const uint4 &hi, const uint4 &lo, uint3
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// LDS fragment reads kept in flight ahead of the MFMAs that use them.
-constexpr int kFragAhead = 2;
+// LDS fragment reads kept in flight ahead of the MFMAs that use them (c5:
+// FP16 1.59 s with one against 1.63 s with two, BF16 1.53 s either way
+// within 0.4 %; three is slower for both).
+template <bool FP16>
+constexpr int kFragAhead = FP16 ? 1 : 2;
 
 // Per-universe state a wave carries through its range of grid points.
 template <int SM, int NC>
@@ -139,18 +142,18 @@ __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *_
             }
         }
     }
-    // fragments in issue order, each read kFragAhead fragments before its
+    // fragments in issue order, each read kFragAhead<FP16> fragments before its
     // MFMAs (a fence per fragment keeps the reads from all being hoisted, which
     // would hold every fragment of the record in registers at once)
     constexpr int NF = code_nfrag(CODE);
     uint4 w[NF];
 #pragma unroll
-    for (int i = 0; i < kFragAhead && i < NF; ++i)
+    for (int i = 0; i < kFragAhead<FP16> && i < NF; ++i)
         w[i] = cur[code_frag(CODE, code_issue_g(CODE, i), code_issue_s(CODE, i)) * 64 + lane];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-        if (i + kFragAhead < NF) {
-            const int ia = i + kFragAhead;
+        if (i + kFragAhead<FP16> < NF) {
+            const int ia = i + kFragAhead<FP16>;
             w[ia] = cur[code_frag(CODE, code_issue_g(CODE, ia), code_issue_s(CODE, ia)) * 64 + lane];
         }
         const int s = code_issue_s(CODE, i), b = code_issue_g(CODE, i);
@@ -458,8 +461,15 @@ static hipError_t launch_split_t(const fc_grid *g, int64_t K, const double *d,
         resident_slots_split(reinterpret_cast<const void *>(&k_scan_split<CODE, NC, FP16>));
     ScanGeometry sg = scan_geometry(K, nq, slots, 16 * NC * kWavesPerBlock);
     if (sg.q_per_chunk > kSplitChunkMax) {
-        sg.q_per_chunk = kSplitChunkMax;
-        sg.n_qchunks = (nq + kSplitChunkMax - 1) / kSplitChunkMax;
+        // shorter chunks, as many as keep blocks x 256 work-items within the
+        // 32-bit dispatch size (the general geometry's bound)
+        const int64_t cap = (int64_t(1) << 23) / (sg.n_utiles > 0 ? sg.n_utiles : 1);
+        int64_t nc = (nq + kSplitChunkMax - 1) / kSplitChunkMax;
+        if (nc > cap) nc = cap;
+        if (nc > sg.n_qchunks) {
+            sg.q_per_chunk = (nq + nc - 1) / nc;
+            sg.n_qchunks = (nq + sg.q_per_chunk - 1) / sg.q_per_chunk;
+        }
     }
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     const uint4 *R = FP16 ? g->RH16 : g->RB16;
