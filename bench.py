@@ -98,8 +98,8 @@ FP64_SOURCES = ("paper_2002_07858_amd/csrc/k_scan64.hip",
 # FETCH_SIZE (KiB x 1024 x 2.0000) + WRITE_SIZE (KiB x 1024 x 1.0000) of one launch
 # (a leg's: mean of the three launches of one run)
 TRAFFIC = {
-    ("c5", "fp64", "points"): {"bytes_per_launch": 4030085096 * 2048 + 28750 * 1024,
-                               "source_hash": "94700be90b106c3e", "sources": FP64_SOURCES,
+    ("c5", "fp64", "points"): {"bytes_per_launch": 985414308 * 2048 + 1281250 * 1024,
+                               "source_hash": "7c799a98aa98fe16", "sources": FP64_SOURCES,
                                "profile": "profiles/k_scan_f64m_c5.md"},
     ("c5", "fp32", "points"): {"bytes_per_launch": 1878591182 * 2048 + 15000 * 1024,
                                "source_hash": "3a43f67f3a6367f6", "sources": FP32_SOURCES,
