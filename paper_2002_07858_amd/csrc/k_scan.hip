@@ -689,7 +689,21 @@ static hipError_t launch_fp32_pts_n(const fc_grid *g, int64_t n_pts, const int64
     const int64_t max_tiles = K / kPtsTile + n_pts;  // bound on the dense tile count
     const int64_t groups_per_xcd = (max_tiles + 63) / 64;
     const int64_t n_tiles = 64 * groups_per_xcd;    // blocks per grid chunk
-    const ScanGeometry sg = scan_geometry(max_tiles * kPtsTile, nq, slots, kPtsTile);
+    ScanGeometry sg = scan_geometry(max_tiles * kPtsTile, nq, slots, kPtsTile);
+    // then shorter chunks, of at most kPtsChunkMax points, as far as the
+    // dispatch size allows: the tiles that share a chunk start together and
+    // stay close, so the L2 serves the later readers of each record (c5:
+    // 4.65 s against 4.81 s for the whole call, the same results bit for bit)
+    constexpr int64_t kPtsChunkMax = 2048;
+    if (sg.q_per_chunk > kPtsChunkMax) {
+        const int64_t cap = (int64_t(1) << 23) / n_tiles;
+        int64_t nc = (nq + kPtsChunkMax - 1) / kPtsChunkMax;
+        if (nc > cap) nc = cap;
+        if (nc > sg.n_qchunks) {
+            sg.q_per_chunk = (nq + nc - 1) / nc;
+            sg.n_qchunks = (nq + sg.q_per_chunk - 1) / sg.q_per_chunk;
+        }
+    }
     const int64_t blocks = n_tiles * sg.n_qchunks;
     hipLaunchKernelGGL(k_tile_prefix, dim3(1), dim3(1024), 0, st, n_pts, seg_off, tile_start);
     ProfScope prof(st, "k_scan_fp32_pts");
