@@ -150,7 +150,8 @@ int fc_build_covariance(fc_grid *g, const double *frac_cov, int32_t stat_mode,
  * takes another 8 K bytes.  The FP64 form splits the grid into chunks when K
  * alone would leave CUs idle and merges their minima in grid order (the
  * same result); the chunk minima take a stream-ordered scratch of 16 bytes
- * per (chunk, universe).  Scratch is allocated with hipMallocAsync and
+ * per (chunk, universe), at most 2 GiB (chunks of 2048 grid points, longer
+ * where that bound or the dispatch size would be passed).  Scratch is allocated with hipMallocAsync and
  * released with hipFreeAsync on `stream` (FC_ERR_NOMEM or FC_ERR_DEVICE if
  * that fails).
  * Universes with NaN/inf data get chi2_min = +inf, argmin = p, dchi2 = NaN;
