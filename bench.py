@@ -101,8 +101,8 @@ TRAFFIC = {
     ("c5", "fp64", "points"): {"bytes_per_launch": 985414308 * 2048 + 1281250 * 1024,
                                "source_hash": "7c799a98aa98fe16", "sources": FP64_SOURCES,
                                "profile": "profiles/k_scan_f64m_c5.md"},
-    ("c5", "fp32", "points"): {"bytes_per_launch": 209318518 * 2048 + 641250 * 1024,
-                               "source_hash": "6e1a9cd2954eb47d", "sources": FP32_SOURCES,
+    ("c5", "fp32", "points"): {"bytes_per_launch": 227249134 * 2048 + 641250 * 1024,
+                               "source_hash": "37a4a054150dd848", "sources": FP32_SOURCES,
                                "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
     ("c5", "split_fp16", "points"): {"bytes_per_launch": 2194617926 * 2048 + 2561250 * 1024,
                                      "source_hash": "426698537f46a4cf", "sources": SPLIT_SOURCES,

@@ -637,7 +637,20 @@ static hipError_t launch_fp32_n(const fc_grid *g, int64_t K, const double *d, co
     // resident block slots: queried once per instantiation (thread-safe)
     static const int slots =
         resident_slots(reinterpret_cast<const void *>(&k_scan_fp32<N>), 64 * kWavesPerBlock);
-    const ScanGeometry sg = scan_geometry(K, nq, slots, kFp32UnivPerBlock);
+    ScanGeometry sg = scan_geometry(K, nq, slots, kFp32UnivPerBlock);
+    // then chunks of at most kFp32ChunkMax points, as far as the dispatch size
+    // allows, as in the points form (c3: 1.59 s against 1.68 s, c5 0.5 %
+    // faster; the same results bit for bit)
+    constexpr int64_t kFp32ChunkMax = 2048;
+    if (sg.q_per_chunk > kFp32ChunkMax) {
+        const int64_t cap = (int64_t(1) << 23) / (sg.n_utiles > 0 ? sg.n_utiles : 1);
+        int64_t nc = (nq + kFp32ChunkMax - 1) / kFp32ChunkMax;
+        if (nc > cap) nc = cap;
+        if (nc > sg.n_qchunks) {
+            sg.q_per_chunk = (nq + nc - 1) / nc;
+            sg.n_qchunks = (nq + sg.q_per_chunk - 1) / sg.q_per_chunk;
+        }
+    }
     const int64_t blocks = sg.n_utiles * sg.n_qchunks;
     ProfScope prof(st, "k_scan_fp32");
     hipLaunchKernelGGL((k_scan_fp32<N>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, st,
