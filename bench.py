@@ -105,10 +105,10 @@ TRAFFIC = {
                                "source_hash": "37a4a054150dd848", "sources": FP32_SOURCES,
                                "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
     ("c5", "split_fp16", "points"): {"bytes_per_launch": 2194617926 * 2048 + 2561250 * 1024,
-                                     "source_hash": "426698537f46a4cf", "sources": SPLIT_SOURCES,
+                                     "source_hash": "98549ac6fbe21dfe", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
     ("c5", "split_bf16", "points"): {"bytes_per_launch": 568374400 * 2048 + 6721251 * 1024,
-                                     "source_hash": "426698537f46a4cf", "sources": SPLIT_SOURCES,
+                                     "source_hash": "98549ac6fbe21dfe", "sources": SPLIT_SOURCES,
                                      "profile": "profiles/k_scan_c5_fp32_split_counters.md"},
 }
 

@@ -107,7 +107,6 @@ __device__ __forceinline__ void split_point(int64_t q, bool more, const uint4 *_
                                             SplitLane<code_smax(CODE), NC> &L)
 {
     constexpr int NB = code_nb(CODE);
-    constexpr int SM = code_smax(CODE);
     constexpr int REC = code_rec_units(CODE);
     constexpr int UU = code_u_unit(CODE);
     constexpr int SU = code_scale_unit(CODE);
