@@ -41,6 +41,19 @@ def run_scan(fc, grid, form, d, p):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
+def run_points(fc, grid, form, d, pts, seg):
+    """fc_scan_points over segments seg of d with true points pts."""
+    K = d.shape[0]
+    out = {k: torch.full((K,), -7.0, dtype=torch.float64, device="cuda")
+           for k in ("dchi2", "chi2_min", "chi2_p")}
+    out["argmin"] = torch.full((K,), -7, dtype=torch.int64, device="cuda")
+    fc.fc_scan_points(grid, form, to_dev(pts, torch.int64), to_dev(seg, torch.int64),
+                      to_dev(d, torch.float64), out["dchi2"], out["chi2_min"], out["argmin"],
+                      out["chi2_p"])
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
 def make_grid(fc, pr, forms):
     g = fc.fc_build_grid(pr.axes, pr.S)
     fc.fc_build_covariance(g, pr.F, pr.stat_mode, pr.stat_diag, forms=forms)
@@ -182,6 +195,51 @@ def test_scan_parity_bin_counts(fc, N):
         rep = parity.report(dev, ref, parity.TOL[form])
         assert rep["e_rel"] <= parity.TOL[form], (form, rep)
         assert rep["argmin_agree"] == 1.0, (form, rep)
+
+
+@pytest.mark.parametrize("entry", ["scan", "points"])
+def test_grid_chunks_and_their_ragged_tail(fc, entry):
+    """The scans split the grid into chunks (at most 2048 points; with so few
+    universes, many short ones to fill the GPU) and merge the chunks' minima
+    (packed-key atomics; FP64: partials merged in grid order): a grid of
+    2 x 2048 + 37 points with true points at chunk-boundary indices, every
+    universe against the oracle in every form, through fc_scan and
+    fc_scan_points; unfluctuated universes whose exact minimum is the last
+    grid point check the merge up to the ragged end."""
+    import types
+    N, G, K = 8, 2 * 2048 + 37, 300
+    rng = np.random.default_rng(4133)
+    S = rng.uniform(100, 300, size=(G, N))
+    A = rng.normal(size=(N, 2 * N))
+    W = A @ A.T
+    dw = np.sqrt(np.diag(W))
+    F = 0.5 * ((W / np.outer(dw, dw)) + (W / np.outer(dw, dw)).T) * 0.02
+    n_pts = 6
+    pts = np.array([0, 2047, 2048, 4095, 4096, G - 1], dtype=np.int64)
+    seg = np.linspace(0, K, n_pts + 1).astype(np.int64)
+    p = np.repeat(pts, np.diff(seg))
+    d = S[p] + rng.normal(0, 1, size=(K, N)) * np.sqrt(S[p])
+    d[seg[-2]:seg[-2] + 5] = S[G - 1]  # unfluctuated at the last grid point
+    ref = oracle.scan(S, F, d, p)
+    g = fc.fc_build_grid([np.arange(float(G))], S)
+    fc.fc_build_covariance(g, F, forms=ALL_FORMS)
+    pr = types.SimpleNamespace(S=S, F=F, stat_mode=0, stat_diag=None, G=G)
+    for form in FORM:
+        if entry == "scan":
+            dev = run_scan(fc, g, FORM[form], d, p)
+        else:
+            dev = run_points(fc, g, FORM[form], d, pts, seg)
+        parity.check_invariants(dev, G, all_finite=True)
+        tol = parity.split_bf16_tol(S, d, p) if form == "split_bf16" else parity.TOL[form]
+        rep = parity.report(dev, ref, tol)
+        rep.update(parity.argmin_validity(pr, dev, d, ref, tol))
+        assert rep["e_rel"] <= tol, (form, tol, rep)
+        assert rep["argmin_agree"] == 1.0, (form, rep)
+        assert rep["argmin_valid"] == 1.0, (form, tol, rep)
+        un = slice(seg[-2], seg[-2] + 5)
+        assert np.all(dev["argmin"][un] == G - 1), form
+        assert np.all(dev["dchi2"][un] == 0.0), form
+    g.destroy()
 
 
 @pytest.mark.parametrize("form", ["fp32", "fp64", "split_bf16", "split_fp16"])
