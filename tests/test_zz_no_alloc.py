@@ -68,6 +68,26 @@ def test_no_alloc_equals_fc_scan_on_two_calls(fc, setup, form, drop):
                 np.testing.assert_array_equal(got[k], ref[k], err_msg=f"{form} {drop} {k}")
 
 
+def test_no_alloc_fp64_fewer_chunks_same_result(fc):
+    """The FP64 form's chunk minima must fit the static array: on the 60^3
+    grid with 40 000 universes fc_scan takes 106 chunks of at most 2048 points
+    (68 MB of minima), the no-allocation entry only as many as fit 32 MiB; the
+    minima merge in grid order with the strict "<", so both give the same
+    results bit for bit."""
+    pr = fcgen.make_problem("c3", K=20000, true_subset=[0, 1])
+    g = fc.fc_build_grid(pr.axes, pr.S)
+    fc.fc_build_covariance(g, pr.F, forms=1)
+    d_t = torch.as_tensor(pr.d).cuda()
+    p_t = torch.as_tensor(pr.p_idx).cuda()
+    assert d_t.shape[0] * (pr.G // 2048) * 16 > fc.FC_NO_ALLOC_SCRATCH_BYTES
+    ref = run(fc, fc.fc_scan, g, 1, d_t, p_t)
+    got = run(fc, fc.fc_scan_no_alloc, g, 1, d_t, p_t)
+    for k in ref:
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+    assert np.all(np.isfinite(ref["dchi2"]))
+    g.destroy()
+
+
 def test_no_alloc_refuses_a_k_beyond_its_scratch(fc):
     """NULL chi2_min and chi2_p need 16 bytes per universe: 2^21 + 1 universes
     exceed the 32 MiB array, and the call fails before any device work."""
