@@ -440,6 +440,37 @@ def region_bench(pr, form_name: str, K0=256, K_max=4096, z=2.0):
 
 
 # ---------------------------------------------------------------------------
+# Universes drawn on the device (fc_generate_universes) in the workload's shape:
+# the same true points and universe counts, timed with events on the launch
+# stream; two launches with one seed must agree bit for bit.
+# ---------------------------------------------------------------------------
+def gen_bench(fc, grid, pr, pts_t, so_t, reps=3):
+    import torch
+    K, N = pr.K, pr.N
+    d = torch.empty((K, N), dtype=torch.float64, device="cuda")
+    d2 = torch.empty_like(d)
+    uf = torch.zeros(pts_t.numel(), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    fc.fc_generate_universes(grid, pts_t, so_t, 2020, d2, u_first=uf)  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(reps):
+        ev[0].record(stream)
+        fc.fc_generate_universes(grid, pts_t, so_t, 2020, d, u_first=uf)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    t = float(np.mean(ms)) * 1e-3
+    nbytes = K * N * 8
+    return {"universes": K, "bins": N, "ms": t * 1e3, "universes_per_s": K / t,
+            "bytes_written": nbytes, "GBps": nbytes / t / 1e9,
+            "bitwise_deterministic": bool(torch.equal(d, d2)),
+            "kernel": "k_gen_universes",
+            "work_per_universe": "N Poisson draws (PTRS) + N normals (Philox4x64-10) + "
+                                 "N(N+1)/2 FMAs of the systematic factor"}
+
+
+# ---------------------------------------------------------------------------
 # Grid sharding on one device: the grid cut into equal slices, each scanned by
 # its own call (one device's share of a grid-sharded job, at its real shape),
 # merged through one shared (key, chi2_p) state, checked bit for bit against
@@ -621,6 +652,8 @@ def main():
                     help="requests in the serving leg (0 to skip it; default 200)")
     ap.add_argument("--fixed", type=int, default=1,
                     help="1: the one-matrix scan leg on the c2 grid (0 to skip)")
+    ap.add_argument("--gen", type=int, default=1,
+                    help="1: time fc_generate_universes in the workload's shape (0 to skip)")
     ap.add_argument("--region", type=int, default=1,
                     help="1: the full-surface region leg on the c2 grid (0 to skip)")
     ap.add_argument("--shards", type=int, default=8,
@@ -789,6 +822,9 @@ def main():
         res["grid_shard"] = shard_bench(fc, grid, fc.FC_FORM_FP32, "fp32", "points", pr, d_t, p_t,
                                         pts_t, so_t, ref32, args.shards)
         del ref32
+    if args.gen:
+        log("[bench] universes drawn on the device")
+        res["universe_generation"] = gen_bench(fc, grid, pr, pts_t, so_t)
     grid.destroy()
     del d_t, p_t, outs
     torch.cuda.empty_cache()
